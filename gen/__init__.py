@@ -1,0 +1,241 @@
+"""Seeded synthetic workloads for Adaptive Hybrid Sort.
+
+Shared by the tests, the benchmark and the smoke check; holds none of the
+sorting method's arithmetic.  Raw draws come from ``libahs_gen.so``
+(counter-based SplitMix64, see ``ahs_gen.c``); this module composes them
+into the workloads used for parity and measurement:
+
+* ``pr1``: 1,000,000 u32 keys uniform on [0, 1023] (seed 0).
+* ``strategy_sweep``: u32 arrays, (a) uniform on [0, 4095], (b) 256 distinct
+  random 32-bit values drawn with Zipf(1.1) ranks, (c) uniform 32-bit keys,
+  the same sorted, reversed, and sorted with n/200 random transpositions.
+* ``wide_keys``: u64 uniform; u64 with 4,096 distinct values drawn with
+  Zipf(1.0); f32 and f64 Normal(0, sigma=1e3) with 0.1 % duplicates and a few
+  +-0.0 values.
+* ``segments``: many uneven u32 arrays with sizes log-uniform on [16, 2^20].
+* ``request_trace``: Poisson arrivals with log-uniform sizes and mixed types.
+
+The paper's own datasets (taxi timestamps, sensor readings, k-mers) are not
+available; these synthetic families stand in for its uniform, skewed and
+presorted inputs and its edge cases (Sec. III-B, Sec. IV-A).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libahs_gen.so")
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"generator library missing: {LIB_PATH}; run gen/build_gen.py")
+        L = C.CDLL(LIB_PATH)
+        u64, vp = C.c_uint64, C.c_void_p
+        L.gen_words.argtypes = [u64, u64, u64, vp]
+        L.gen_u32.argtypes = [u64, u64, u64, C.c_uint32, vp]
+        L.gen_u64.argtypes = [u64, u64, u64, u64, vp]
+        L.gen_index.argtypes = [u64, u64, u64, u64, vp]
+        L.gen_distinct.argtypes = [u64, u64, C.c_uint32, C.c_int, vp]
+        L.gen_distinct.restype = u64
+        L.gen_zipf_index.argtypes = [u64, u64, u64, C.c_double, C.c_uint32, vp]
+        L.gen_zipf_index.restype = C.c_int
+        L.gen_normal.argtypes = [u64, u64, u64, C.c_double, vp]
+        L.gen_exponential.argtypes = [u64, u64, u64, C.c_double, vp]
+        L.gen_unit.argtypes = [u64, u64, u64, vp]
+        L.gen_apply_swaps.argtypes = [vp, u64, C.c_uint32, u64, u64, u64]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+# ---------------------------------------------------------------- primitives
+def words(seed, stream, n):
+    out = np.empty(n, np.uint64)
+    lib().gen_words(seed, stream, n, _p(out))
+    return out
+
+
+def u32(seed, stream, n, mask=0xFFFFFFFF):
+    out = np.empty(n, np.uint32)
+    lib().gen_u32(seed, stream, n, mask, _p(out))
+    return out
+
+
+def u64(seed, stream, n, mask=0xFFFFFFFFFFFFFFFF):
+    out = np.empty(n, np.uint64)
+    lib().gen_u64(seed, stream, n, mask, _p(out))
+    return out
+
+
+def index(seed, stream, n, rng):
+    out = np.empty(n, np.uint64)
+    lib().gen_index(seed, stream, n, rng, _p(out))
+    return out
+
+
+def distinct(seed, stream, m, bits):
+    out = np.empty(m, np.uint64)
+    lib().gen_distinct(seed, stream, m, bits, _p(out))
+    return out if bits == 64 else out.astype(np.uint32)
+
+
+def zipf_index(seed, stream, n, s, m):
+    out = np.empty(n, np.uint32)
+    if lib().gen_zipf_index(seed, stream, n, s, m, _p(out)) != 0:
+        raise ValueError("zipf generator failed")
+    return out
+
+
+def normal(seed, stream, n, sigma):
+    out = np.empty(n, np.float64)
+    lib().gen_normal(seed, stream, n, sigma, _p(out))
+    return out
+
+
+def exponential(seed, stream, n, rate):
+    out = np.empty(n, np.float64)
+    lib().gen_exponential(seed, stream, n, rate, _p(out))
+    return out
+
+
+def unit(seed, stream, n):
+    out = np.empty(n, np.float64)
+    lib().gen_unit(seed, stream, n, _p(out))
+    return out
+
+
+def apply_swaps(arr, seed, stream, count):
+    assert arr.flags.c_contiguous
+    lib().gen_apply_swaps(_p(arr), arr.size, arr.itemsize, seed, stream, count)
+    return arr
+
+
+def zipf_keys(seed, n, m, s, bits):
+    """m distinct random values (stream 1), picked with Zipf(s, m) ranks (stream 2)."""
+    vals = distinct(seed, 1, m, bits)
+    return vals[zipf_index(seed, 2, n, s, m)]
+
+
+# ---------------------------------------------------------------- workloads
+def pr1(n=1_000_000, seed=0):
+    """u32 uniform on [0, 1023]."""
+    return u32(seed, 0, n, 1023)
+
+
+SWEEP_CASES = ("uniform4096", "zipf256", "uniform32", "sorted32", "reverse32", "swapped32")
+
+
+def strategy_sweep(case, n=1 << 28, seed=None):
+    """u32 keys of the strategy sweep; default seeds 1 (a), 2 (b), 3 (c)."""
+    if case == "uniform4096":
+        return u32(1 if seed is None else seed, 0, n, 4095)
+    if case == "zipf256":
+        return zipf_keys(2 if seed is None else seed, n, 256, 1.1, 32)
+    s = 3 if seed is None else seed
+    base = u32(s, 0, n)
+    if case == "uniform32":
+        return base
+    base.sort()
+    if case == "sorted32":
+        return base
+    if case == "reverse32":
+        return np.ascontiguousarray(base[::-1])
+    if case == "swapped32":
+        return apply_swaps(base, s, 5, n // 200)
+    raise ValueError(case)
+
+
+WIDE_CASES = ("u64uniform", "u64zipf4096", "f32normal", "f64normal")
+
+
+def _normal_recipe(seed, n, dtype):
+    x = normal(seed, 10, n, 1000.0).astype(dtype)
+    ndup = n // 1000
+    if ndup:
+        dst = index(seed, 11, ndup, n).astype(np.int64)
+        src = index(seed, 12, ndup, n).astype(np.int64)
+        x[dst] = x[src].copy()
+    nz = n // 20000
+    if nz:
+        x[index(seed, 13, nz, n).astype(np.int64)] = dtype(-0.0)
+        x[index(seed, 14, nz, n).astype(np.int64)] = dtype(0.0)
+    return x
+
+
+def wide_keys(case, n=1 << 27, seed=None):
+    """Wide and floating keys; default seeds 4..7.  Payload = original index."""
+    if case == "u64uniform":
+        return u64(4 if seed is None else seed, 0, n)
+    if case == "u64zipf4096":
+        return zipf_keys(5 if seed is None else seed, n, 4096, 1.0, 64)
+    if case == "f32normal":
+        return _normal_recipe(6 if seed is None else seed, n, np.float32)
+    if case == "f64normal":
+        return _normal_recipe(7 if seed is None else seed, n, np.float64)
+    raise ValueError(case)
+
+
+SEG_KINDS = ("u256", "u32", "zipf64", "sorted", "reverse")
+
+
+def segment_sizes(nseg, seed=8, lo_exp=4, span_exp=16, cap=1 << 20, lo=16):
+    u = unit(seed, 0, nseg)
+    s = np.floor(np.exp2(lo_exp + span_exp * u)).astype(np.int64)
+    return np.clip(s, lo, cap)
+
+
+def segments(nseg=65536, seed=8, sizes=None):
+    """Concatenated u32 segments and their u64 offsets[nseg + 1]; each segment's
+    distribution is drawn from SEG_KINDS (stream 1) and its keys from a
+    stream of its own."""
+    if sizes is None:
+        sizes = segment_sizes(nseg, seed)
+    kinds = (index(seed, 1, nseg, len(SEG_KINDS))).astype(np.int64)
+    offs = np.zeros(nseg + 1, np.uint64)
+    np.cumsum(sizes, out=offs[1:])
+    keys = np.empty(int(offs[-1]), np.uint32)
+    for i in range(nseg):
+        n = int(sizes[i])
+        st = 1000 + i
+        kind = SEG_KINDS[kinds[i]]
+        if kind == "u256":
+            v = u32(seed, st, n, 255)
+        elif kind == "u32":
+            v = u32(seed, st, n)
+        elif kind == "zipf64":
+            vals = distinct(seed * 7919 + i, 1, 64, 32)
+            v = vals[zipf_index(seed * 7919 + i, 2, n, 1.1, 64)]
+        elif kind == "sorted":
+            v = np.sort(u32(seed, st, n))
+        else:
+            v = np.sort(u32(seed, st, n))[::-1]
+        keys[int(offs[i]): int(offs[i + 1])] = v
+    return keys, offs, kinds
+
+
+def request_trace(duration_s=60.0, rate=2000.0, seed=9, lo_exp=10, span_exp=14, max_requests=None):
+    """Arrival times, sizes, dtype codes (0 u32, 1 u64, 2 f32), distribution
+    flags (0 uniform, 1 Zipf; f32 always Normal) and payload flags."""
+    cap = int(duration_s * rate * 2 + 100)
+    gaps = exponential(seed, 0, cap, rate)
+    t = np.cumsum(gaps)
+    keep = t < duration_s
+    t = t[keep]
+    m = t.size if max_requests is None else min(t.size, max_requests)
+    t = t[:m]
+    sizes = np.floor(np.exp2(lo_exp + span_exp * unit(seed, 1, m))).astype(np.int64)
+    dt = index(seed, 2, m, 3).astype(np.int64)
+    dist = index(seed, 3, m, 2).astype(np.int64)
+    pay = index(seed, 4, m, 2).astype(np.int64)
+    offs = index(seed, 5, m, 1 << 30).astype(np.int64)
+    return {"arrival_s": t, "size": sizes, "dtype": dt, "dist": dist, "payload": pay, "offset": offs}
