@@ -1,0 +1,196 @@
+/*
+ * ahs.h -- C ABI of the MI355X (gfx950) Adaptive Hybrid Sort library.
+ *
+ * Adaptive Hybrid Sort (arXiv 2506.20677) computes a state vector
+ * v = (n, k, H) over its input -- size, value range k = max - min + 1 and the
+ * Shannon entropy H = -sum p_i log2 p_i of the value distribution (Sec. III-A)
+ * -- and a decision engine (a finite-state machine, Sec. III-A and Fig. 2,
+ * optionally a learned predictor, Sec. III-H) dispatches to insertion sort
+ * (n <= 20), counting sort (small k), radix sort (k > 1e6 with low entropy)
+ * or quicksort (everything else).  The calls below follow that statement of
+ * the problem: ahs_features computes v, ahs_select runs the decision engine,
+ * ahs_sort runs the whole method (or one forced strategy) on device buffers.
+ *
+ * Conventions shared by every call:
+ *   - Every call returns an ahs_status.  On error no caller buffer has been
+ *     written, and ahs_last_error() holds a message.
+ *   - Device pointers ("d_") are HIP device memory owned by the caller.  The
+ *     library keeps no pointer after a call returns.  Host pointers ("h_")
+ *     are ordinary host memory.
+ *   - Keys are contiguous arrays of n elements of the given dtype.  Floating
+ *     keys are ordered by an order-preserving bit map (sign bit set: flip all
+ *     bits; clear: set the sign bit), so -0.0 sorts before +0.0, -inf first
+ *     and +inf last; NaN is rejected with AHS_E_NAN.  The paper accepts only
+ *     integers (Sec. III-K); floats are this library's extension.
+ *   - Payloads are optional uint32 arrays permuted with the keys.  Every
+ *     strategy is stable, so the payload result is unique.
+ *   - `stream` is a hipStream_t passed as void* (0 = the null stream).  Calls
+ *     that must decide on the host (AUTO, float NaN checks, radix pass
+ *     planning) synchronise that stream once or twice; the others only
+ *     enqueue work.
+ *   - `d_ws` is caller-provided device scratch of at least
+ *     ahs_workspace_bytes(...) bytes, 256-byte aligned.  The library never
+ *     allocates device memory inside a sort call.
+ *   - One context per host thread; contexts are not thread-safe.
+ *   - n must be below 2^32.
+ */
+#ifndef AHS_H
+#define AHS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { AHS_U32 = 0, AHS_U64 = 1, AHS_F32 = 2, AHS_F64 = 3 } ahs_dtype;
+
+/* AHS_INSERTION is only reported: it is the n <= n_small state of the FSM
+ * (Sec. III-A, Listing 1); it cannot be requested. */
+typedef enum {
+  AHS_AUTO = 0,
+  AHS_COUNTING = 1,
+  AHS_RADIX = 2,
+  AHS_QUICK = 3,
+  AHS_INSERTION = 4
+} ahs_strategy;
+
+typedef enum {
+  AHS_OK = 0,
+  AHS_E_INVALID_ARG = -1, /* bad pointer, size, dtype, strategy or overlap */
+  AHS_E_UNSUPPORTED = -2, /* n >= 2^32, or forced COUNTING with span >= k_count_cap */
+  AHS_E_NAN = -3,         /* a floating key is NaN */
+  AHS_E_WORKSPACE = -4,   /* ws_bytes below the required size */
+  AHS_E_OOM = -5,         /* host allocation failed (context creation only) */
+  AHS_E_DEVICE = -6,      /* a HIP runtime call failed */
+  AHS_E_NO_MODEL = -7,    /* use_model set but no model attached */
+  AHS_E_PARSE = -9        /* model file malformed */
+} ahs_status;
+
+/* The state vector v = (n, k, H) of Sec. III-A, plus what the GPU needs.
+ * min_key/max_key are in the mapped ordered-unsigned space, zero-extended to
+ * 64 bits.  k = span + 1 is not stored (it can be 2^64).  The entropy is
+ * taken over nbins = (span >> shift) + 1 <= 65,536 bins of
+ * (key - min) >> shift, shift the smallest such value; exact == 1 means one
+ * bin per value.  entropy_ratio = H / log2(nbins), 0 when nbins == 1. */
+typedef struct {
+  uint64_t n;
+  uint64_t min_key;
+  uint64_t max_key;
+  uint64_t span;
+  uint64_t nan_count;
+  uint32_t shift;
+  uint32_t nbins;
+  uint32_t exact;
+  uint32_t reserved;
+  double entropy_bits;
+  double entropy_ratio;
+} ahs_feature_vector;
+
+/* Decision thresholds (Sec. III-A; Table II; Sec. III-H).
+ *   INSERTION  if n <= n_small
+ *   COUNTING   else if k <= k_count            (span <= k_count - 1)
+ *   RADIX      else if k > k_radix and H < h_ratio * log2(nbins)
+ *   QUICK      otherwise
+ * With use_model and n >= ml_min_n the attached model decides instead,
+ * except that a COUNTING prediction with span >= k_count_cap falls back to
+ * the FSM.  Forced COUNTING is refused when span >= k_count_cap. */
+typedef struct {
+  uint32_t n_small;
+  uint32_t use_model;
+  uint64_t k_count;
+  uint64_t k_radix;
+  double h_ratio;
+  uint64_t ml_min_n;
+  uint64_t k_count_cap;
+} ahs_config;
+
+enum {
+  AHS_PRESET_GPU = 0,         /* k_count 4096 (default) */
+  AHS_PRESET_PAPER_TEXT = 1,  /* k_count 1000 (Sec. III-A) */
+  AHS_PRESET_PAPER_TABLE2 = 2 /* k_count 1024 (Table II) */
+};
+
+typedef struct ahs_context ahs_context;
+typedef struct ahs_model ahs_model;
+
+/* Fills *cfg with a preset: n_small 20, k_radix 1e6, h_ratio 0.7,
+ * ml_min_n 1000, k_count_cap 65,536, use_model 0, and the preset's k_count. */
+ahs_status ahs_config_init(ahs_config* cfg, int preset);
+
+/* Creates host-side state bound to HIP device `device`: device properties,
+ * a small pinned staging buffer, per-kernel timing, the optional model.  No
+ * device memory is allocated. */
+ahs_status ahs_context_create(int device, ahs_context** out);
+void ahs_context_destroy(ahs_context* ctx);
+
+/* Attaches (borrows) a model used when cfg->use_model is set; NULL detaches. */
+ahs_status ahs_context_set_model(ahs_context* ctx, const ahs_model* model);
+
+/* Number of compute units of the context's device. */
+uint32_t ahs_device_cu_count(const ahs_context* ctx);
+
+/* Bytes of scratch that ahs_features (strategy ignored) or ahs_sort with
+ * `strategy` needs for n keys of `dtype`; AUTO returns the maximum over the
+ * strategies.  Depends only on the arguments, not on the data. */
+size_t ahs_workspace_bytes(uint64_t n, ahs_dtype dtype, int with_payload, ahs_strategy strategy);
+
+/* Features (Sec. III-A): n, min, max, span, shift, nbins, the binned
+ * entropy and its ratio, and the NaN count.  If d_hist is non-null it
+ * receives the nbins counts (capacity: 65,536 uint32).  Blocks until *h_out
+ * is valid.  NaN keys: returns AHS_E_NAN with n and nan_count set. */
+ahs_status ahs_features(ahs_context* ctx, const void* d_keys, uint64_t n, ahs_dtype dtype,
+                        uint32_t* d_hist, void* d_ws, size_t ws_bytes, void* stream,
+                        ahs_feature_vector* h_out);
+
+/* Decision engine (Sec. III-A FSM; Sec. III-H predictor).  Pure host
+ * function; `model` may be NULL unless cfg->use_model is set and
+ * f->n >= cfg->ml_min_n (then AHS_E_NO_MODEL). */
+ahs_status ahs_select(const ahs_feature_vector* f, const ahs_config* cfg, const ahs_model* model,
+                      ahs_strategy* out);
+
+/* The whole method (Sec. III, Fig. 1): features, decision, then the chosen
+ * sort -- or the requested strategy when it is not AHS_AUTO.  Sorts n keys
+ * ascending and stably into d_keys_out; d_vals_in/d_vals_out are both NULL
+ * or both non-NULL and are permuted alike.  In-place (in == out) is allowed;
+ * partial overlap is AHS_E_INVALID_ARG.  cfg NULL means AHS_PRESET_GPU.
+ * h_chosen (nullable) receives the strategy that ran (AHS_INSERTION for
+ * n <= n_small under AUTO).  h_feats (nullable) receives the full feature
+ * vector; asking for it makes the call compute the entropy even when the
+ * decision does not need it.  n == 0 returns AHS_OK without launching. */
+ahs_status ahs_sort(ahs_context* ctx, const void* d_keys_in, void* d_keys_out,
+                    const uint32_t* d_vals_in, uint32_t* d_vals_out, uint64_t n, ahs_dtype dtype,
+                    ahs_strategy requested, const ahs_config* cfg, void* d_ws, size_t ws_bytes,
+                    void* stream, ahs_strategy* h_chosen, ahs_feature_vector* h_feats);
+
+/* Learned predictor (Sec. III-H, Listing 5): gradient-boosted trees over
+ * (n, k, H) in the project's text format
+ *   ahs-gbt 1 / num_class 3 / base_score s0 s1 s2 / num_trees T /
+ *   T x { tree <class> <nodes>; nodes x { <id> split <f> <thr> <l> <r> |
+ *                                          <id> leaf <value> } }
+ * (features 0 = n, 1 = k, 2 = H; left when x < thr; classes 0 COUNTING,
+ * 1 RADIX, 2 QUICK; largest summed score wins, ties to the lower class). */
+ahs_status ahs_model_load(const char* path, ahs_model** out);
+void ahs_model_free(ahs_model* m);
+ahs_status ahs_model_predict(const ahs_model* m, const ahs_feature_vector* f, ahs_strategy* out);
+
+/* Per-kernel timing with HIP events on the launch stream.  When enabled,
+ * every kernel launch of the context is bracketed by two events; totals are
+ * collected (with a stream synchronisation) by ahs_profile_query.  `kernel`
+ * is a family name such as "onesweep_pass", "minmax", "feature_hist". */
+ahs_status ahs_profile_enable(ahs_context* ctx, int on);
+ahs_status ahs_profile_reset(ahs_context* ctx);
+ahs_status ahs_profile_query(ahs_context* ctx, const char* kernel, uint64_t* launches,
+                             double* total_ms);
+/* Writes "name launches total_ms\n" lines for every kernel seen; returns the
+ * number of bytes needed (including the terminating zero). */
+size_t ahs_profile_dump(ahs_context* ctx, char* buf, size_t len);
+
+const char* ahs_status_str(ahs_status s);
+const char* ahs_last_error(const ahs_context* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,314 @@
+"""MI355X-native Adaptive Hybrid Sort (arXiv 2506.20677): Python binding.
+
+A thin ctypes layer over ``libahs.so`` (the C ABI of ``include/ahs.h``).
+It only marshals arguments: torch tensors supply device memory and HIP
+streams; every step of the method runs in the library's gfx950 kernels.  If
+the library is missing the import of any call fails loudly; there is no
+fallback path.
+
+Calls (same names as the C ABI):
+    ahs_config_init, ahs_context_create, ahs_workspace_bytes,
+    ahs_features, ahs_select, ahs_sort, ahs_model_load, ahs_model_predict,
+    ahs_profile_enable / ahs_profile_reset / ahs_profile_query / ahs_profile_dump
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libahs.so")
+
+U32, U64, F32, F64 = 0, 1, 2, 3
+AUTO, COUNTING, RADIX, QUICK, INSERTION = 0, 1, 2, 3, 4
+STRATEGY_NAMES = {AUTO: "auto", COUNTING: "counting", RADIX: "radix", QUICK: "quick", INSERTION: "insertion"}
+STRATEGY_CODES = {v: k for k, v in STRATEGY_NAMES.items()}
+OK, E_INVALID_ARG, E_UNSUPPORTED, E_NAN, E_WORKSPACE, E_OOM, E_DEVICE, E_NO_MODEL, E_PARSE = (
+    0, -1, -2, -3, -4, -5, -6, -7, -9)
+PRESET_GPU, PRESET_PAPER_TEXT, PRESET_PAPER_TABLE2 = 0, 1, 2
+
+_TORCH_DTYPES = {torch.uint32: U32, torch.int32: U32, torch.uint64: U64, torch.int64: U64,
+                 torch.float32: F32, torch.float64: F64}
+_KEY_BYTES = {U32: 4, U64: 8, F32: 4, F64: 8}
+
+
+class AhsError(RuntimeError):
+    def __init__(self, status, message, features=None):
+        super().__init__(f"ahs status {status}: {message}")
+        self.status = status
+        self.features = features
+
+
+class FeatureVector(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("min_key", C.c_uint64), ("max_key", C.c_uint64),
+                ("span", C.c_uint64), ("nan_count", C.c_uint64),
+                ("shift", C.c_uint32), ("nbins", C.c_uint32), ("exact", C.c_uint32),
+                ("reserved", C.c_uint32), ("entropy_bits", C.c_double), ("entropy_ratio", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class Config(C.Structure):
+    _fields_ = [("n_small", C.c_uint32), ("use_model", C.c_uint32), ("k_count", C.c_uint64),
+                ("k_radix", C.c_uint64), ("h_ratio", C.c_double), ("ml_min_n", C.c_uint64),
+                ("k_count_cap", C.c_uint64)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib():
+    """Loads libahs.so once; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(hipcc for gfx950); there is no fallback implementation")
+        L = C.CDLL(LIB_PATH)
+        vp, u64, u32, i32, sz = C.c_void_p, C.c_uint64, C.c_uint32, C.c_int, C.c_size_t
+        sig = {
+            "ahs_config_init": (i32, [C.POINTER(Config), i32]),
+            "ahs_context_create": (i32, [i32, C.POINTER(vp)]),
+            "ahs_context_destroy": (None, [vp]),
+            "ahs_context_set_model": (i32, [vp, vp]),
+            "ahs_device_cu_count": (u32, [vp]),
+            "ahs_workspace_bytes": (sz, [u64, i32, i32, i32]),
+            "ahs_features": (i32, [vp, vp, u64, i32, vp, vp, sz, vp, C.POINTER(FeatureVector)]),
+            "ahs_select": (i32, [C.POINTER(FeatureVector), C.POINTER(Config), vp, C.POINTER(C.c_int)]),
+            "ahs_sort": (i32, [vp, vp, vp, vp, vp, u64, i32, i32, C.POINTER(Config), vp, sz, vp,
+                               C.POINTER(C.c_int), C.POINTER(FeatureVector)]),
+            "ahs_model_load": (i32, [C.c_char_p, C.POINTER(vp)]),
+            "ahs_model_free": (None, [vp]),
+            "ahs_model_predict": (i32, [vp, C.POINTER(FeatureVector), C.POINTER(C.c_int)]),
+            "ahs_profile_enable": (i32, [vp, i32]),
+            "ahs_profile_reset": (i32, [vp]),
+            "ahs_profile_query": (i32, [vp, C.c_char_p, C.POINTER(C.c_uint64), C.POINTER(C.c_double)]),
+            "ahs_profile_dump": (sz, [vp, C.c_char_p, sz]),
+            "ahs_status_str": (C.c_char_p, [i32]),
+            "ahs_last_error": (C.c_char_p, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+        return _lib
+
+
+def _raise(status, ctx=None, features=None):
+    msg = lib().ahs_last_error(ctx.handle).decode() if ctx is not None else lib().ahs_status_str(status).decode()
+    raise AhsError(status, msg, features)
+
+
+def ahs_config_init(preset: int = PRESET_GPU, **overrides) -> Config:
+    cfg = Config()
+    st = lib().ahs_config_init(C.byref(cfg), preset)
+    if st != OK:
+        _raise(st)
+    for k, v in overrides.items():
+        setattr(cfg, k, v)
+    return cfg
+
+
+class Model:
+    """Tree-ensemble strategy predictor (Sec. III-H) loaded by the library."""
+
+    def __init__(self, path: str):
+        h = C.c_void_p()
+        st = lib().ahs_model_load(os.fsencode(path), C.byref(h))
+        if st != OK:
+            raise AhsError(st, f"cannot load model {path}")
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.ahs_model_free(self.handle)
+            self.handle = None
+
+
+def ahs_model_load(path: str) -> Model:
+    return Model(path)
+
+
+def ahs_model_predict(model: Model, f: FeatureVector) -> int:
+    out = C.c_int()
+    st = lib().ahs_model_predict(model.handle, C.byref(f), C.byref(out))
+    if st != OK:
+        _raise(st)
+    return out.value
+
+
+class Context:
+    """Host-side library state bound to one HIP device, plus a cached
+    device workspace allocated through torch."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        st = lib().ahs_context_create(device, C.byref(h))
+        if st != OK:
+            raise AhsError(st, f"cannot create a context on device {device}")
+        self.handle = h
+        self.device = device
+        self._ws = None
+        self._model = None
+
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+    def set_model(self, model: Model | None):
+        self._model = model
+        st = lib().ahs_context_set_model(self.handle, model.handle if model else None)
+        if st != OK:
+            _raise(st, self)
+
+    @property
+    def cu_count(self) -> int:
+        return lib().ahs_device_cu_count(self.handle)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.ahs_context_destroy(self.handle)
+            self.handle = None
+
+
+def ahs_context_create(device: int = 0) -> Context:
+    return Context(device)
+
+
+_default_ctx = {}
+
+
+def default_context(device: int | None = None) -> Context:
+    d = torch.cuda.current_device() if device is None else device
+    if d not in _default_ctx:
+        _default_ctx[d] = Context(d)
+    return _default_ctx[d]
+
+
+def dtype_code(t: torch.Tensor, dtype: int | None = None) -> int:
+    if dtype is not None:
+        return dtype
+    try:
+        return _TORCH_DTYPES[t.dtype]
+    except KeyError:
+        raise TypeError(f"unsupported key dtype {t.dtype}") from None
+
+
+def ahs_workspace_bytes(n: int, dtype: int, with_payload: bool, strategy: int = AUTO) -> int:
+    return lib().ahs_workspace_bytes(n, dtype, 1 if with_payload else 0, strategy)
+
+
+def _stream_handle(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _check_keys(keys: torch.Tensor, code: int):
+    if not keys.is_cuda or not keys.is_contiguous():
+        raise ValueError("keys must be a contiguous device tensor")
+    if keys.element_size() != _KEY_BYTES[code]:
+        raise ValueError("key tensor element size does not match the dtype")
+
+
+def ahs_features(keys: torch.Tensor, hist: torch.Tensor | None = None, dtype: int | None = None,
+                 ctx: Context | None = None, stream=None) -> FeatureVector:
+    """Feature vector of a device key array (Sec. III-A).  ``hist`` (optional,
+    >= 65,536 uint32/int32 elements) receives the nbins counts."""
+    code = dtype_code(keys, dtype)
+    _check_keys(keys, code)
+    ctx = ctx or default_context(keys.device.index)
+    n = keys.numel()
+    if hist is not None and (not hist.is_cuda or hist.numel() < 65536 or hist.element_size() != 4):
+        raise ValueError("hist must be a device tensor of at least 65,536 32-bit elements")
+    wsb = ahs_workspace_bytes(n, code, False, AUTO)
+    ws = ctx.workspace(wsb)
+    f = FeatureVector()
+    st = lib().ahs_features(ctx.handle, C.c_void_p(keys.data_ptr()), n, code,
+                            C.c_void_p(hist.data_ptr()) if hist is not None else None,
+                            C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream), C.byref(f))
+    if st != OK:
+        _raise(st, ctx, f)
+    return f
+
+
+def ahs_select(f: FeatureVector, cfg: Config | None = None, model: Model | None = None) -> int:
+    cfg = cfg or ahs_config_init()
+    out = C.c_int()
+    st = lib().ahs_select(C.byref(f), C.byref(cfg), model.handle if model else None, C.byref(out))
+    if st != OK:
+        _raise(st)
+    return out.value
+
+
+def ahs_sort(keys: torch.Tensor, values: torch.Tensor | None = None, strategy: int | str = AUTO,
+             cfg: Config | None = None, out: torch.Tensor | None = None,
+             out_values: torch.Tensor | None = None, dtype: int | None = None,
+             ctx: Context | None = None, stream=None, want_features: bool = False):
+    """Sorts device keys (and an optional uint32 payload) ascending and stably.
+
+    Returns (keys_out, values_out or None, chosen strategy, FeatureVector or
+    None).  ``out``/``out_values`` may alias the inputs (in place)."""
+    if isinstance(strategy, str):
+        strategy = STRATEGY_CODES[strategy]
+    code = dtype_code(keys, dtype)
+    _check_keys(keys, code)
+    ctx = ctx or default_context(keys.device.index)
+    n = keys.numel()
+    if out is None:
+        out = torch.empty_like(keys)
+    if values is not None:
+        if values.numel() != n or values.element_size() != 4 or not values.is_cuda or not values.is_contiguous():
+            raise ValueError("values must be a contiguous device tensor of n 32-bit elements")
+        if out_values is None:
+            out_values = torch.empty_like(values)
+    elif out_values is not None:
+        raise ValueError("out_values given without values")
+    wsb = ahs_workspace_bytes(n, code, values is not None, strategy)
+    ws = ctx.workspace(wsb)
+    chosen = C.c_int()
+    f = FeatureVector()
+    vp = (lambda t: C.c_void_p(t.data_ptr()) if t is not None else None)
+    st = lib().ahs_sort(ctx.handle, vp(keys), vp(out), vp(values), vp(out_values), n, code, strategy,
+                        C.byref(cfg) if cfg is not None else None, C.c_void_p(ws.data_ptr()), ws.numel(),
+                        _stream_handle(stream), C.byref(chosen), C.byref(f) if want_features else None)
+    if st != OK:
+        _raise(st, ctx, f if want_features else None)
+    return out, out_values, chosen.value, (f if want_features else None)
+
+
+def ahs_profile_enable(ctx: Context, on: bool = True):
+    lib().ahs_profile_enable(ctx.handle, 1 if on else 0)
+
+
+def ahs_profile_reset(ctx: Context):
+    lib().ahs_profile_reset(ctx.handle)
+
+
+def ahs_profile_query(ctx: Context, kernel: str):
+    n = C.c_uint64()
+    ms = C.c_double()
+    lib().ahs_profile_query(ctx.handle, kernel.encode(), C.byref(n), C.byref(ms))
+    return n.value, ms.value
+
+
+def ahs_profile_dump(ctx: Context) -> dict:
+    need = lib().ahs_profile_dump(ctx.handle, None, 0)
+    buf = C.create_string_buffer(need)
+    lib().ahs_profile_dump(ctx.handle, buf, need)
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, cnt, ms = line.split()
+        out[name] = (int(cnt), float(ms))
+    return out

@@ -1,0 +1,384 @@
+// Feature extraction on gfx950 (Sec. III-A): min/max over mapped keys with
+// a NaN count, the binned key histogram and its Shannon entropy in FP64.
+//
+// Bins: (key - min) >> shift with the smallest shift giving at most 65,536
+// bins.  Up to 8,192 bins (span < 8,192, always exact) the histogram lives
+// in LDS as u32 counters; above that as 65,536 packed u16 counters (128 KiB)
+// whose 16-bit overflows are detected from the atomic's return value and
+// carried exactly into a global correction array.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace ahs {
+
+// Streams the keys of [0, n) assigned to this thread with 16-byte loads
+// (4 u32 or 2 u64 per load, UNROLL loads in flight), handling an unaligned
+// head and the tail with scalar loads.  f(key) is called on raw bit patterns.
+template <typename K, int UNROLL, typename F>
+__device__ __forceinline__ void for_each_key(const K* __restrict__ keys, uint64_t n, uint64_t tid,
+                                             uint64_t nthreads, F&& f) {
+  constexpr int V = 16 / sizeof(K);
+  const uintptr_t addr = reinterpret_cast<uintptr_t>(keys);
+  uint64_t head = ((16u - (addr & 15u)) & 15u) / sizeof(K);
+  if (head > n) head = n;
+  for (uint64_t i = tid; i < head; i += nthreads) f(keys[i]);
+  const uint64_t nvec = (n - head) / V;
+  const u32x4* __restrict__ vp = reinterpret_cast<const u32x4*>(keys + head);
+  uint64_t j = tid;
+  for (; j + (UNROLL - 1) * nthreads < nvec; j += UNROLL * nthreads) {
+    u32x4 v[UNROLL];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) v[u] = vp[j + u * nthreads];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      if constexpr (sizeof(K) == 4) {
+        f(v[u].x); f(v[u].y); f(v[u].z); f(v[u].w);
+      } else {
+        f((uint64_t)v[u].x | ((uint64_t)v[u].y << 32));
+        f((uint64_t)v[u].z | ((uint64_t)v[u].w << 32));
+      }
+    }
+  }
+  for (; j < nvec; j += nthreads) {
+    u32x4 v = vp[j];
+    if constexpr (sizeof(K) == 4) {
+      f(v.x); f(v.y); f(v.z); f(v.w);
+    } else {
+      f((uint64_t)v.x | ((uint64_t)v.y << 32));
+      f((uint64_t)v.z | ((uint64_t)v.w << 32));
+    }
+  }
+  for (uint64_t i = head + nvec * V + tid; i < n; i += nthreads) f(keys[i]);
+}
+
+// ------------------------------------------------------------------ min/max
+template <int KK>
+__global__ __launch_bounds__(MINMAX_THREADS) void k_minmax(const typename KeyTraits<KK>::K* __restrict__ keys,
+                                                           uint64_t n, MinMaxPartial* __restrict__ part) {
+  using K = typename KeyTraits<KK>::K;
+  K mn = ~K(0), mx = K(0);
+  uint32_t nan = 0;
+  const uint64_t tid = (uint64_t)blockIdx.x * MINMAX_THREADS + threadIdx.x;
+  for_each_key<K, 4>(keys, n, tid, (uint64_t)gridDim.x * MINMAX_THREADS, [&](K b) {
+    if constexpr (KeyTraits<KK>::FLT) {
+      if (fnan(b)) { ++nan; return; }
+    }
+    const K m = map_key<KK>(b);
+    mn = m < mn ? m : mn;
+    mx = m > mx ? m : mx;
+  });
+  mn = wave_min(mn);
+  mx = wave_max(mx);
+  nan = wave_sum(nan);
+  __shared__ K smn[MINMAX_THREADS / WAVE], smx[MINMAX_THREADS / WAVE];
+  __shared__ uint32_t snan[MINMAX_THREADS / WAVE];
+  const int w = threadIdx.x / WAVE;
+  if (lane_id() == 0) { smn[w] = mn; smx[w] = mx; snan[w] = nan; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < MINMAX_THREADS / WAVE; ++i) {
+      mn = smn[i] < mn ? smn[i] : mn;
+      mx = smx[i] > mx ? smx[i] : mx;
+      nan += snan[i];
+    }
+    part[blockIdx.x].mn = mn;
+    part[blockIdx.x].mx = mx;
+    part[blockIdx.x].nan = nan;
+  }
+}
+
+// One workgroup folds the partials and derives span, shift and nbins.
+__global__ __launch_bounds__(256) void k_minmax_final(const MinMaxPartial* __restrict__ part, int nparts,
+                                                      uint64_t n, DevFeatures* __restrict__ df) {
+  uint64_t mn = ~0ull, mx = 0, nan = 0;
+  for (int i = threadIdx.x; i < nparts; i += 256) {
+    mn = part[i].mn < mn ? part[i].mn : mn;
+    mx = part[i].mx > mx ? part[i].mx : mx;
+    nan += part[i].nan;
+  }
+  mn = wave_min(mn);
+  mx = wave_max(mx);
+  nan = wave_sum(nan);
+  __shared__ uint64_t s[3][4];
+  const int w = threadIdx.x / WAVE;
+  if (lane_id() == 0) { s[0][w] = mn; s[1][w] = mx; s[2][w] = nan; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < 4; ++i) {
+      mn = s[0][i] < mn ? s[0][i] : mn;
+      mx = s[1][i] > mx ? s[1][i] : mx;
+      nan += s[2][i];
+    }
+    DevFeatures f = {};
+    f.n = n;
+    f.nan_count = nan;
+    if (nan == n) { mn = 0; mx = 0; }
+    f.min_key = mn;
+    f.max_key = mx;
+    f.span = mx - mn;
+    const int bl = bitlen64(f.span);
+    f.shift = bl > 16 ? (uint32_t)(bl - 16) : 0u;
+    f.nbins = (uint32_t)(f.span >> f.shift) + 1u;
+    f.exact = f.shift == 0 ? 1u : 0u;
+    *df = f;
+  }
+}
+
+hipError_t launch_minmax(int kk, const void* keys, uint64_t n, MinMaxPartial* partials, int nblocks,
+                         DevFeatures* df, hipStream_t s) {
+  switch (kk) {
+    case KK_U32: k_minmax<KK_U32><<<nblocks, MINMAX_THREADS, 0, s>>>((const uint32_t*)keys, n, partials); break;
+    case KK_U64: k_minmax<KK_U64><<<nblocks, MINMAX_THREADS, 0, s>>>((const uint64_t*)keys, n, partials); break;
+    case KK_F32: k_minmax<KK_F32><<<nblocks, MINMAX_THREADS, 0, s>>>((const uint32_t*)keys, n, partials); break;
+    case KK_F64: k_minmax<KK_F64><<<nblocks, MINMAX_THREADS, 0, s>>>((const uint64_t*)keys, n, partials); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_minmax_final<<<1, 256, 0, s>>>(partials, nblocks, n, df);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ histograms
+// Exact small histogram: nbins <= 8,192 u32 counters in LDS; each block
+// writes its counts to partials[block][nbins].
+template <int KK>
+__global__ __launch_bounds__(HIST_SMALL_THREADS) void k_hist_small(const typename KeyTraits<KK>::K* __restrict__ keys,
+                                                                   uint64_t n, typename KeyTraits<KK>::K kmin,
+                                                                   uint32_t shift, uint32_t nbins,
+                                                                   uint32_t* __restrict__ partials) {
+  using K = typename KeyTraits<KK>::K;
+  __shared__ uint32_t h[HIST_SMALL_MAX_BINS];
+  for (uint32_t b = threadIdx.x; b < nbins; b += HIST_SMALL_THREADS) h[b] = 0;
+  __syncthreads();
+  const uint64_t tid = (uint64_t)blockIdx.x * HIST_SMALL_THREADS + threadIdx.x;
+  for_each_key<K, 4>(keys, n, tid, (uint64_t)gridDim.x * HIST_SMALL_THREADS, [&](K b) {
+    const K off = map_key<KK>(b) - kmin;
+    atomicAdd(&h[(uint32_t)(off >> shift)], 1u);
+  });
+  __syncthreads();
+  uint32_t* out = partials + (size_t)blockIdx.x * nbins;
+  for (uint32_t b = threadIdx.x; b < nbins; b += HIST_SMALL_THREADS) out[b] = h[b];
+}
+
+hipError_t launch_hist_small(int kk, const void* keys, uint64_t n, uint64_t kmin, uint32_t shift,
+                             uint32_t nbins, uint32_t* partials, int nblocks, hipStream_t s) {
+  if (nbins > (uint32_t)HIST_SMALL_MAX_BINS) return hipErrorInvalidValue;
+  switch (kk) {
+    case KK_U32: k_hist_small<KK_U32><<<nblocks, HIST_SMALL_THREADS, 0, s>>>((const uint32_t*)keys, n, (uint32_t)kmin, shift, nbins, partials); break;
+    case KK_U64: k_hist_small<KK_U64><<<nblocks, HIST_SMALL_THREADS, 0, s>>>((const uint64_t*)keys, n, kmin, shift, nbins, partials); break;
+    case KK_F32: k_hist_small<KK_F32><<<nblocks, HIST_SMALL_THREADS, 0, s>>>((const uint32_t*)keys, n, (uint32_t)kmin, shift, nbins, partials); break;
+    case KK_F64: k_hist_small<KK_F64><<<nblocks, HIST_SMALL_THREADS, 0, s>>>((const uint64_t*)keys, n, kmin, shift, nbins, partials); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Large histogram: 65,536 bins as packed u16 pairs in 128 KiB of LDS.  Word
+// w holds bin 2w in its low half and bin 2w+1 in its high half.  All counter
+// arithmetic is additive modulo 2^32, so overflows are repaired exactly:
+//   low half wraps (old low == 0xFFFF): bin 2w gets +65,536 and the carry
+//     that leaked into the high half is taken back (bin 2w+1 gets -1); if the
+//     whole word wrapped (old == 0xFFFFFFFF) that carry also left the word,
+//     so bin 2w+1 gets +65,536 as well;
+//   high half wraps (old high == 0xFFFF): bin 2w+1 gets +65,536.
+// The final count of bin b is sum over blocks of its half plus corr[b],
+// modulo 2^32, which is exact because every true count is below 2^32.
+// Optionally also counts ndig 8-bit digits of (key - min) per key: the
+// upfront digit histogram of the LSD radix sort, fused into the same read.
+template <int KK, bool DIG>
+__global__ __launch_bounds__(HIST_LARGE_THREADS) void k_hist_large(const typename KeyTraits<KK>::K* __restrict__ keys,
+                                                                   uint64_t n, typename KeyTraits<KK>::K kmin,
+                                                                   uint32_t shift, uint32_t* __restrict__ partials,
+                                                                   uint32_t* __restrict__ corr, int ndig,
+                                                                   uint32_t* __restrict__ digit_partials) {
+  using K = typename KeyTraits<KK>::K;
+  __shared__ uint32_t h[HIST_LARGE_WORDS];
+  __shared__ uint32_t dh[DIG ? 8 * 256 : 1];
+  for (int i = threadIdx.x; i < HIST_LARGE_WORDS; i += HIST_LARGE_THREADS) h[i] = 0;
+  if constexpr (DIG)
+    for (int i = threadIdx.x; i < 8 * 256; i += HIST_LARGE_THREADS) dh[i] = 0;
+  __syncthreads();
+  const uint64_t tid = (uint64_t)blockIdx.x * HIST_LARGE_THREADS + threadIdx.x;
+  for_each_key<K, 2>(keys, n, tid, (uint64_t)gridDim.x * HIST_LARGE_THREADS, [&](K b) {
+    const K off = map_key<KK>(b) - kmin;
+    const uint32_t bin = (uint32_t)(off >> shift);
+    const uint32_t hi = bin & 1u;
+    const uint32_t old = atomicAdd(&h[bin >> 1], hi ? 0x10000u : 1u);
+    if (hi) {
+      if ((old >> 16) == 0xFFFFu) add_agent(&corr[bin], 65536u);
+    } else if ((old & 0xFFFFu) == 0xFFFFu) {
+      add_agent(&corr[bin], 65536u);
+      add_agent(&corr[bin + 1], old == 0xFFFFFFFFu ? 65535u : 0xFFFFFFFFu);
+    }
+    if constexpr (DIG) {
+      for (int p = 0; p < ndig; ++p) atomicAdd(&dh[p * 256 + (uint32_t)((off >> (8 * p)) & 255u)], 1u);
+    }
+  });
+  __syncthreads();
+  uint32_t* out = partials + (size_t)blockIdx.x * HIST_LARGE_WORDS;
+  for (int i = threadIdx.x; i < HIST_LARGE_WORDS; i += HIST_LARGE_THREADS) out[i] = h[i];
+  if constexpr (DIG) {
+    uint32_t* dout = digit_partials + (size_t)blockIdx.x * ndig * 256;
+    for (int i = threadIdx.x; i < ndig * 256; i += HIST_LARGE_THREADS) dout[i] = dh[i];
+  }
+}
+
+template <int KK>
+static hipError_t hist_large_kk(const void* keys, uint64_t n, uint64_t kmin, uint32_t shift, uint32_t* partials,
+                                uint32_t* corr, int nblocks, int ndig, uint32_t* dparts, hipStream_t s) {
+  using K = typename KeyTraits<KK>::K;
+  if (ndig > 0)
+    k_hist_large<KK, true><<<nblocks, HIST_LARGE_THREADS, 0, s>>>((const K*)keys, n, (K)kmin, shift, partials, corr, ndig, dparts);
+  else
+    k_hist_large<KK, false><<<nblocks, HIST_LARGE_THREADS, 0, s>>>((const K*)keys, n, (K)kmin, shift, partials, corr, 0, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_hist_large(int kk, const void* keys, uint64_t n, uint64_t kmin, uint32_t shift,
+                             uint32_t* partials, uint32_t* corr, int nblocks, int ndig,
+                             uint32_t* digit_partials, hipStream_t s) {
+  if (ndig < 0 || ndig > 8) return hipErrorInvalidValue;
+  switch (kk) {
+    case KK_U32: return hist_large_kk<KK_U32>(keys, n, kmin, shift, partials, corr, nblocks, ndig, digit_partials, s);
+    case KK_U64: return hist_large_kk<KK_U64>(keys, n, kmin, shift, partials, corr, nblocks, ndig, digit_partials, s);
+    case KK_F32: return hist_large_kk<KK_F32>(keys, n, kmin, shift, partials, corr, nblocks, ndig, digit_partials, s);
+    case KK_F64: return hist_large_kk<KK_F64>(keys, n, kmin, shift, partials, corr, nblocks, ndig, digit_partials, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Folds the per-block histograms into the final counts, writes them (when
+// hist_out is non-null) and sums the entropy terms -(c/n) log2(c/n) of the
+// block's bins in FP64 into hpart[block].  Large histograms: one thread per
+// packed word (two bins); small: one thread per bin.
+constexpr int HRED_THREADS = 256;
+
+__global__ __launch_bounds__(HRED_THREADS) void k_hist_reduce(const uint32_t* __restrict__ partials, int ngroups,
+                                                              uint32_t nbins, int large,
+                                                              const uint32_t* __restrict__ corr,
+                                                              uint32_t* __restrict__ hist_out, uint64_t n,
+                                                              double* __restrict__ hpart) {
+  const double inv_n = 1.0 / (double)n;
+  double term = 0.0;
+  const uint32_t t = blockIdx.x * HRED_THREADS + threadIdx.x;
+  if (large) {
+    const uint32_t nwords = (nbins + 1u) / 2u;
+    if (t < nwords) {
+      uint32_t c0 = corr[2 * t], c1 = corr[2 * t + 1];
+      for (int g = 0; g < ngroups; ++g) {
+        const uint32_t w = partials[(size_t)g * HIST_LARGE_WORDS + t];
+        c0 += w & 0xFFFFu;
+        c1 += w >> 16;
+      }
+      if (hist_out) {
+        hist_out[2 * t] = c0;
+        if (2 * t + 1 < nbins) hist_out[2 * t + 1] = c1;
+      }
+      if (c0) { const double p = (double)c0 * inv_n; term -= p * log2(p); }
+      if (2 * t + 1 < nbins && c1) { const double p = (double)c1 * inv_n; term -= p * log2(p); }
+    }
+  } else if (t < nbins) {
+    uint32_t c = 0;
+    for (int g = 0; g < ngroups; ++g) c += partials[(size_t)g * nbins + t];
+    if (hist_out) hist_out[t] = c;
+    if (c) { const double p = (double)c * inv_n; term -= p * log2(p); }
+  }
+  term = wave_sum(term);
+  __shared__ double s[HRED_THREADS / WAVE];
+  if (lane_id() == 0) s[threadIdx.x / WAVE] = term;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double acc = 0.0;
+    for (int i = 0; i < HRED_THREADS / WAVE; ++i) acc += s[i];
+    hpart[blockIdx.x] = acc;
+  }
+}
+
+hipError_t launch_hist_reduce(const uint32_t* partials, int ngroups, uint32_t nbins, int large,
+                              const uint32_t* corr, uint32_t* hist_out, uint64_t n, double* hpart,
+                              int* nparts_out, hipStream_t s) {
+  const uint32_t items = large ? (nbins + 1u) / 2u : nbins;
+  const int nb = (int)((items + HRED_THREADS - 1) / HRED_THREADS);
+  *nparts_out = nb;
+  k_hist_reduce<<<nb, HRED_THREADS, 0, s>>>(partials, ngroups, nbins, large, corr, hist_out, n, hpart);
+  return hipGetLastError();
+}
+
+// Sums the per-block entropy partials in a fixed order and sets the ratio.
+__global__ __launch_bounds__(256) void k_entropy_final(const double* __restrict__ hpart, int nparts,
+                                                       DevFeatures* __restrict__ df) {
+  __shared__ double s[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += 256) acc += hpart[i];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double H = 0.0;
+    for (int i = 0; i < 256; ++i) H += s[i];
+    if (H < 0.0) H = 0.0;
+    df->entropy_bits = H;
+    df->entropy_ratio = df->nbins > 1 ? H / log2((double)df->nbins) : 0.0;
+  }
+}
+
+hipError_t launch_entropy_final(const double* hpart, int nparts, DevFeatures* df, hipStream_t s) {
+  k_entropy_final<<<1, 256, 0, s>>>(hpart, nparts, df);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ upfront digit counts
+// Counts the ndig 8-bit digits of (key - min) of every key in one read: the
+// per-pass digit histograms of the LSD radix sort.
+template <int KK>
+__global__ __launch_bounds__(DIGIT_HIST_THREADS) void k_digit_hist(const typename KeyTraits<KK>::K* __restrict__ keys,
+                                                                   uint64_t n, typename KeyTraits<KK>::K kmin, int ndig,
+                                                                   uint32_t* __restrict__ digit_partials) {
+  using K = typename KeyTraits<KK>::K;
+  __shared__ uint32_t dh[8 * 256];
+  for (int i = threadIdx.x; i < 8 * 256; i += DIGIT_HIST_THREADS) dh[i] = 0;
+  __syncthreads();
+  const uint64_t tid = (uint64_t)blockIdx.x * DIGIT_HIST_THREADS + threadIdx.x;
+  for_each_key<K, 4>(keys, n, tid, (uint64_t)gridDim.x * DIGIT_HIST_THREADS, [&](K b) {
+    const K off = map_key<KK>(b) - kmin;
+    for (int p = 0; p < ndig; ++p) atomicAdd(&dh[p * 256 + (uint32_t)((off >> (8 * p)) & 255u)], 1u);
+  });
+  __syncthreads();
+  uint32_t* out = digit_partials + (size_t)blockIdx.x * ndig * 256;
+  for (int i = threadIdx.x; i < ndig * 256; i += DIGIT_HIST_THREADS) out[i] = dh[i];
+}
+
+hipError_t launch_digit_hist(int kk, const void* keys, uint64_t n, uint64_t kmin, int ndig,
+                             uint32_t* digit_partials, int nblocks, hipStream_t s) {
+  if (ndig < 1 || ndig > 8) return hipErrorInvalidValue;
+  switch (kk) {
+    case KK_U32: k_digit_hist<KK_U32><<<nblocks, DIGIT_HIST_THREADS, 0, s>>>((const uint32_t*)keys, n, (uint32_t)kmin, ndig, digit_partials); break;
+    case KK_U64: k_digit_hist<KK_U64><<<nblocks, DIGIT_HIST_THREADS, 0, s>>>((const uint64_t*)keys, n, kmin, ndig, digit_partials); break;
+    case KK_F32: k_digit_hist<KK_F32><<<nblocks, DIGIT_HIST_THREADS, 0, s>>>((const uint32_t*)keys, n, (uint32_t)kmin, ndig, digit_partials); break;
+    case KK_F64: k_digit_hist<KK_F64><<<nblocks, DIGIT_HIST_THREADS, 0, s>>>((const uint64_t*)keys, n, kmin, ndig, digit_partials); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// One thread per (pass, digit): sums the block partials; then each pass's
+// 256 counts are exclusively scanned by one wave group.
+__global__ __launch_bounds__(256) void k_digit_reduce(const uint32_t* __restrict__ parts, int nblocks, int ndig,
+                                                      uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets) {
+  const int p = blockIdx.x, d = threadIdx.x;
+  uint32_t c = 0;
+  for (int b = 0; b < nblocks; ++b) c += parts[((size_t)b * ndig + p) * 256 + d];
+  __shared__ uint32_t sm[8];
+  uint32_t total;
+  const uint32_t ex = block_excl_scan<256>(c, sm, total);
+  counts[p * 256 + d] = c;
+  offsets[p * 256 + d] = ex;
+}
+
+hipError_t launch_digit_reduce(const uint32_t* digit_partials, int nblocks, int ndig, uint32_t* counts,
+                               uint32_t* offsets, hipStream_t s) {
+  k_digit_reduce<<<ndig, 256, 0, s>>>(digit_partials, nblocks, ndig, counts, offsets);
+  return hipGetLastError();
+}
+
+}  // namespace ahs

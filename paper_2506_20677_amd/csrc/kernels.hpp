@@ -1,0 +1,107 @@
+// Host-side launchers of the gfx950 kernels and the small structures they
+// share with the host dispatcher.  Every launcher enqueues on `s` and
+// returns the hipError_t of the launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ahs {
+
+// Key kinds: the dtype enum of the ABI, as template parameters.
+enum KeyKind : int { KK_U32 = 0, KK_U64 = 1, KK_F32 = 2, KK_F64 = 3 };
+
+// Bit length of a 64-bit value (0 for 0).
+__host__ __device__ __forceinline__ int bitlen64(uint64_t x) { return x ? 64 - __builtin_clzll(x) : 0; }
+
+// Device copy of the feature vector; same layout as ahs_feature_vector.
+struct DevFeatures {
+  uint64_t n, min_key, max_key, span, nan_count;
+  uint32_t shift, nbins, exact, reserved;
+  double entropy_bits, entropy_ratio;
+};
+
+struct MinMaxPartial {
+  uint64_t mn, mx, nan;
+  uint64_t pad;
+};
+
+// Launch-geometry constants used by both the host planner and the kernels.
+constexpr int HIST_SMALL_MAX_BINS = 8192;      // u32 LDS bins
+constexpr int HIST_LARGE_WORDS = 32768;        // 65,536 packed u16 bins
+constexpr int MINMAX_THREADS = 256;
+constexpr int HIST_SMALL_THREADS = 256;
+constexpr int HIST_LARGE_THREADS = 1024;
+constexpr int DIGIT_HIST_THREADS = 256;
+constexpr int EXPAND_THREADS = 256;
+constexpr int EXPAND_TILE = EXPAND_THREADS * 4 * 8;   // positions per block
+
+// Onesweep tile shapes: 512 threads (8 waves); 16 keys per thread for 32-bit
+// keys, 8 for 64-bit keys.
+constexpr int OS_THREADS = 512;
+constexpr int OS_WAVES = OS_THREADS / 64;
+inline int os_items(int key_bytes) { return key_bytes == 4 ? 16 : 8; }
+inline int os_tile(int key_bytes) { return OS_THREADS * os_items(key_bytes); }
+
+// Look-back status word: bits 63..62 flag (1 aggregate, 2 inclusive),
+// bits 61..56 epoch (pass number within one call, 1..63), 55..0 value.
+constexpr uint64_t ST_AGG = 1ull << 62;
+constexpr uint64_t ST_INC = 2ull << 62;
+constexpr uint64_t ST_FLAG_MASK = 3ull << 62;
+constexpr int ST_EPOCH_SHIFT = 56;
+constexpr uint64_t ST_VALUE_MASK = (1ull << 56) - 1;
+
+// ---------------------------------------------------------------- features
+hipError_t launch_minmax(int kk, const void* keys, uint64_t n, MinMaxPartial* partials, int nblocks,
+                         DevFeatures* df, hipStream_t s);
+hipError_t launch_hist_small(int kk, const void* keys, uint64_t n, uint64_t kmin, uint32_t shift,
+                             uint32_t nbins, uint32_t* partials, int nblocks, hipStream_t s);
+hipError_t launch_hist_large(int kk, const void* keys, uint64_t n, uint64_t kmin, uint32_t shift,
+                             uint32_t* partials, uint32_t* corr, int nblocks, int ndig,
+                             uint32_t* digit_partials, hipStream_t s);
+hipError_t launch_hist_reduce(const uint32_t* partials, int ngroups, uint32_t nbins, int large,
+                              const uint32_t* corr, uint32_t* hist_out, uint64_t n, double* hpart,
+                              int* nparts_out, hipStream_t s);
+hipError_t launch_entropy_final(const double* hpart, int nparts, DevFeatures* df, hipStream_t s);
+
+// ---------------------------------------------------------------- counting
+hipError_t launch_scan_bins(const uint32_t* hist, uint32_t nbins, uint32_t* offsets, hipStream_t s);
+hipError_t launch_expand(int kk, const uint32_t* offsets, uint32_t nbins, uint64_t kmin, void* out,
+                         uint64_t n, hipStream_t s);
+
+// ---------------------------------------------------------------- radix
+hipError_t launch_digit_hist(int kk, const void* keys, uint64_t n, uint64_t kmin, int ndig,
+                             uint32_t* digit_partials, int nblocks, hipStream_t s);
+// Sums per-block digit counts into counts[ndig][256] and their exclusive
+// scans into offsets[ndig][256].
+hipError_t launch_digit_reduce(const uint32_t* digit_partials, int nblocks, int ndig,
+                               uint32_t* counts, uint32_t* offsets, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t* p, uint64_t count, uint64_t value, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t s);
+
+struct OnesweepArgs {
+  const void* src;
+  void* dst;
+  const uint32_t* vsrc;
+  uint32_t* vdst;
+  uint64_t n;
+  uint64_t kmin;
+  uint32_t digit_shift;   // digit = ((key - kmin) >> digit_shift) & 255
+  uint32_t map_in;        // keys in src are raw (apply the float map)
+  uint32_t unmap_out;     // write raw keys to dst (apply the inverse map)
+  uint32_t epoch;         // 1..63
+  const uint32_t* digit_offsets;  // [256] global exclusive offsets of this pass
+  uint64_t* status;       // [tiles][256]
+  uint32_t* tile_counter; // zero before the launch
+};
+hipError_t launch_onesweep(int kk, int with_vals, const OnesweepArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------- small
+hipError_t launch_small_sort(int kk, const void* src, void* dst, const uint32_t* vsrc, uint32_t* vdst,
+                             uint32_t n, hipStream_t s);
+constexpr int SMALL_SORT_MAX = 1024;
+
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+
+}  // namespace ahs

@@ -1,0 +1,500 @@
+// General path on gfx950: a stable GPU sample sort, the multi-pivot form of
+// the paper's quicksort (Sec. III-G.1, Listing 4).  Where quicksort splits a
+// range around one median-of-three pivot into <, == and >, each level here
+// splits every active segment around 255 pivots (splitters) drawn from a
+// sample, into 255 open intervals and 255 "equal to splitter" buckets, with
+// a stable scatter; equal-key buckets are final, buckets of at most
+// SS_CAP keys are finished by an in-LDS stable block sort, larger ones form
+// the next level's segments.
+//
+// Bucket id of key x against sorted splitters s_0 <= ... <= s_254:
+//   r = #{i : s_i < x};  id = 2r + (r < 255 && x == s_r)
+// so ids ascend with the key and duplicate splitters only leave buckets
+// empty.
+#include "onesweep.hpp"
+#include "samplesort.hpp"
+
+namespace ahs {
+
+template <typename K>
+__device__ __forceinline__ uint32_t ss_classify(K x, const K* __restrict__ spl) {
+  uint32_t r = 0;
+#pragma unroll
+  for (uint32_t step = 128; step >= 1; step >>= 1)
+    if (spl[r + step - 1] < x) r += step;
+  const uint32_t eq = (r < (uint32_t)SS_P && spl[r] == x) ? 1u : 0u;
+  return 2u * r + eq;
+}
+
+__device__ __forceinline__ uint64_t ss_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Segment holding tile `tile` (segments' first_tile ascend).
+__device__ __forceinline__ uint32_t ss_seg_of_tile(const SsSeg* __restrict__ segs, uint32_t nsegs, uint32_t tile) {
+  uint32_t lo = 0, hi = nsegs;  // largest s with first_tile <= tile
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (segs[mid].first_tile <= tile) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------------ init
+// Level 0: one segment (or, for n <= SS_CAP, one block-sort item) covering
+// the whole input.
+__global__ void k_ss_init(SsSeg* segs, SsItem* items, uint64_t n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    segs[0].start = 0;
+    segs[0].size = (uint32_t)n;
+    segs[0].first_tile = 0;
+    items[0].start = 0;
+    items[0].size = (uint32_t)n;
+    items[0].flags = SS_BUF_IN << 8;
+  }
+}
+
+// ------------------------------------------------------------------ sample + splitters
+// One block per segment: SS_SAMPLES keys at pseudo-random positions, sorted
+// in LDS by a bitonic network; splitter i is sample (i + 1) * 32.
+template <int KK>
+__global__ __launch_bounds__(SS_THREADS) void k_ss_sample(const typename KeyTraits<KK>::K* __restrict__ src,
+                                                          int map_in, const SsSeg* __restrict__ segs,
+                                                          typename KeyTraits<KK>::K* __restrict__ spl,
+                                                          uint64_t seed) {
+  using K = typename KeyTraits<KK>::K;
+  __shared__ K s[SS_SAMPLES];
+  const SsSeg sg = segs[blockIdx.x];
+  const int t = threadIdx.x;
+  const uint64_t base = ss_mix(seed ^ (sg.start * 0x9E3779B97F4A7C15ull));
+  for (int j = t; j < SS_SAMPLES; j += SS_THREADS) {
+    const uint64_t h = ss_mix(base + (uint64_t)(j + 1) * 0x9E3779B97F4A7C15ull);
+    const uint64_t pos = sg.start + (((h >> 32) * (uint64_t)sg.size) >> 32);
+    K x = src[pos];
+    if constexpr (KeyTraits<KK>::FLT) x = map_in ? fmap(x) : x;
+    s[j] = x;
+  }
+  __syncthreads();
+  for (int k = 2; k <= SS_SAMPLES; k <<= 1) {
+    for (int jj = k >> 1; jj > 0; jj >>= 1) {
+      for (int i = t; i < SS_SAMPLES; i += SS_THREADS) {
+        const int ixj = i ^ jj;
+        if (ixj > i) {
+          const K a = s[i], b = s[ixj];
+          const bool up = (i & k) == 0;
+          if ((a > b) == up) { s[i] = b; s[ixj] = a; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = t; i < SS_P; i += SS_THREADS) spl[(size_t)blockIdx.x * 256 + i] = s[(i + 1) * (SS_SAMPLES / 256)];
+}
+
+// ------------------------------------------------------------------ counting
+// Each block walks a contiguous range of tiles, classifying keys and
+// counting bucket ids in LDS; counts are flushed to the segment's global
+// counters whenever the segment changes.
+template <int KK>
+__global__ __launch_bounds__(SS_THREADS) void k_ss_count(const typename KeyTraits<KK>::K* __restrict__ src, int map_in,
+                                                         const SsSeg* __restrict__ segs, uint32_t nsegs,
+                                                         uint32_t ntiles, uint32_t tile_keys,
+                                                         const typename KeyTraits<KK>::K* __restrict__ spl,
+                                                         uint32_t* __restrict__ counts) {
+  using K = typename KeyTraits<KK>::K;
+  __shared__ K s_spl[256];
+  __shared__ uint32_t s_cnt[SS_NB];
+  const int t = threadIdx.x;
+  const uint32_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+  const uint32_t t0 = blockIdx.x * per;
+  const uint32_t t1 = t0 + per < ntiles ? t0 + per : ntiles;
+  int64_t cur = -1;
+  for (uint32_t tile = t0; tile < t1; ++tile) {
+    const uint32_t sidx = ss_seg_of_tile(segs, nsegs, tile);
+    if ((int64_t)sidx != cur) {
+      if (cur >= 0) {
+        for (int b = t; b < SS_NB; b += SS_THREADS)
+          if (s_cnt[b]) add_agent(&counts[(size_t)cur * SS_NB + b], s_cnt[b]);
+      }
+      __syncthreads();
+      for (int b = t; b < SS_NB; b += SS_THREADS) s_cnt[b] = 0;
+      for (int i = t; i < SS_P; i += SS_THREADS) s_spl[i] = spl[(size_t)sidx * 256 + i];
+      cur = sidx;
+      __syncthreads();
+    }
+    const SsSeg sg = segs[sidx];
+    const uint64_t off = (uint64_t)(tile - sg.first_tile) * tile_keys;
+    const uint64_t rem = (uint64_t)sg.size - off;
+    const uint32_t cnt = rem < tile_keys ? (uint32_t)rem : tile_keys;
+    const K* p = src + sg.start + off;
+    for (uint32_t i = t; i < cnt; i += SS_THREADS) {
+      K x = p[i];
+      if constexpr (KeyTraits<KK>::FLT) x = map_in ? fmap(x) : x;
+      atomicAdd(&s_cnt[ss_classify<K>(x, s_spl)], 1u);
+    }
+  }
+  __syncthreads();
+  if (cur >= 0)
+    for (int b = t; b < SS_NB; b += SS_THREADS)
+      if (s_cnt[b]) add_agent(&counts[(size_t)cur * SS_NB + b], s_cnt[b]);
+}
+
+// ------------------------------------------------------------------ plan
+// One block per segment: bucket start positions (exclusive scan of the
+// counts from the segment start) and the fate of every bucket: equal-key
+// buckets are final (copied out unless already in place), buckets of at
+// most SS_CAP keys become block-sort items, larger ones next-level segments.
+__global__ __launch_bounds__(SS_NB) void k_ss_plan(const SsSeg* __restrict__ segs, const uint32_t* __restrict__ counts,
+                                                   uint32_t* __restrict__ offs, uint32_t dst_buf, int copy_in_place,
+                                                   SsSeg* __restrict__ next, SsItem* __restrict__ items,
+                                                   SsCounters* __restrict__ ctr, uint32_t item_cap,
+                                                   uint32_t seg_cap) {
+  __shared__ uint32_t sm[SS_NB / WAVE + 1];
+  const SsSeg sg = segs[blockIdx.x];
+  const int b = threadIdx.x;
+  const uint32_t c = counts[(size_t)blockIdx.x * SS_NB + b];
+  uint32_t total;
+  const uint32_t ex = block_excl_scan<SS_NB>(c, sm, total);
+  const uint64_t pos = sg.start + ex;
+  offs[(size_t)blockIdx.x * SS_NB + b] = (uint32_t)pos;
+  if (c == 0) return;
+  if (b & 1) {
+    if (dst_buf == SS_BUF_OUT && !copy_in_place) return;
+    const uint32_t nchunks = (c + SS_CAP - 1) / SS_CAP;
+    const uint32_t at = atomicAdd(&ctr->nitems, nchunks);
+    for (uint32_t q = 0; q < nchunks; ++q) {
+      if (at + q >= item_cap) { atomicOr(&ctr->overflow, 1u); break; }
+      SsItem it;
+      it.start = pos + (uint64_t)q * SS_CAP;
+      it.size = (c - q * SS_CAP) < SS_CAP ? (c - q * SS_CAP) : SS_CAP;
+      it.flags = SS_ITEM_COPY | (dst_buf << 8);
+      items[at + q] = it;
+    }
+  } else if (c <= SS_CAP) {
+    const uint32_t at = atomicAdd(&ctr->nitems, 1u);
+    if (at >= item_cap) { atomicOr(&ctr->overflow, 1u); return; }
+    SsItem it;
+    it.start = pos;
+    it.size = c;
+    it.flags = dst_buf << 8;
+    items[at] = it;
+  } else {
+    const uint32_t at = atomicAdd(&ctr->nsegs_next, 1u);
+    if (at >= seg_cap) { atomicOr(&ctr->overflow, 2u); return; }
+    SsSeg ns;
+    ns.start = pos;
+    ns.size = c;
+    ns.first_tile = 0;
+    next[at] = ns;
+  }
+}
+
+// One block: first_tile of every next-level segment (exclusive scan of its
+// tile count) and the level's total tile count.
+constexpr int SS_TILES_THREADS = 1024;
+__global__ __launch_bounds__(SS_TILES_THREADS) void k_ss_tiles(SsSeg* __restrict__ segs, SsCounters* __restrict__ ctr,
+                                                               uint32_t tile_keys, uint32_t seg_cap) {
+  __shared__ uint32_t sm[SS_TILES_THREADS / WAVE + 1];
+  uint32_t nsegs = ctr->nsegs_next;
+  if (nsegs > seg_cap) nsegs = seg_cap;
+  const uint32_t per = (nsegs + SS_TILES_THREADS - 1) / SS_TILES_THREADS;
+  const uint32_t s0 = threadIdx.x * per;
+  uint32_t local = 0;
+  for (uint32_t i = 0; i < per; ++i)
+    if (s0 + i < nsegs) local += (segs[s0 + i].size + tile_keys - 1) / tile_keys;
+  uint32_t total;
+  uint32_t run = block_excl_scan<SS_TILES_THREADS>(local, sm, total);
+  for (uint32_t i = 0; i < per; ++i) {
+    if (s0 + i < nsegs) {
+      segs[s0 + i].first_tile = run;
+      run += (segs[s0 + i].size + tile_keys - 1) / tile_keys;
+    }
+  }
+  if (threadIdx.x == 0) ctr->ntiles_next = total;
+}
+
+// ------------------------------------------------------------------ scatter
+// Segmented single-pass stable scatter by bucket id (512 ids): the onesweep
+// tile machinery with the splitter classifier as the digit, a look-back
+// chain per segment and per-segment bucket offsets.
+template <int KK, bool PAY, int IPT>
+__global__ __launch_bounds__(SS_THREADS) void k_ss_scatter(SsScatterArgs a) {
+  using K = typename KeyTraits<KK>::K;
+  constexpr int TILE = SS_THREADS * IPT;
+  constexpr int NW = SS_THREADS / WAVE;
+  __shared__ uint64_t s_mask[NW][SS_NB];
+  __shared__ uint32_t s_whist[NW][SS_NB];
+  __shared__ uint32_t s_tstart[SS_NB];
+  __shared__ uint32_t s_dbase[SS_NB];
+  __shared__ K s_spl[256];
+  __shared__ K s_keys[TILE];
+  __shared__ uint32_t s_vals[PAY ? TILE : 1];
+  __shared__ uint16_t s_dig[TILE];
+  __shared__ uint32_t s_scan[NW + 1];
+  __shared__ uint32_t s_tile;
+
+  const int t = threadIdx.x, w = t / WAVE, lane = lane_id();
+  for (int i = t; i < NW * SS_NB; i += SS_THREADS) {
+    (&s_mask[0][0])[i] = 0ull;
+    (&s_whist[0][0])[i] = 0u;
+  }
+  if (t == 0) s_tile = add_agent(a.tile_counter, 1u);
+  __syncthreads();
+  const uint32_t tile = s_tile;
+  const uint32_t sidx = ss_seg_of_tile(a.segs, a.nsegs, tile);
+  const SsSeg sg = a.segs[sidx];
+  for (int i = t; i < SS_P; i += SS_THREADS) s_spl[i] = ((const K*)a.spl)[(size_t)sidx * 256 + i];
+  const uint64_t off = (uint64_t)(tile - sg.first_tile) * TILE;
+  const uint64_t rem = (uint64_t)sg.size - off;
+  const uint32_t valid = rem < (uint64_t)TILE ? (uint32_t)rem : (uint32_t)TILE;
+  const K* __restrict__ src = (const K*)a.src + sg.start + off;
+  __syncthreads();
+
+  K k[IPT];
+  uint32_t v[IPT];
+  uint32_t d[IPT];
+  const uint32_t wbase = (uint32_t)w * WAVE * IPT;
+#pragma unroll
+  for (int i = 0; i < IPT; ++i) {
+    const uint32_t idx = wbase + (uint32_t)i * WAVE + lane;
+    if (idx < valid) {
+      K x = src[idx];
+      if constexpr (KeyTraits<KK>::FLT) x = a.map_in ? fmap(x) : x;
+      k[i] = x;
+      if constexpr (PAY) v[i] = a.vsrc[sg.start + off + idx];
+      d[i] = ss_classify<K>(x, s_spl);
+    } else {
+      k[i] = ~K(0);
+      if constexpr (PAY) v[i] = 0;
+      d[i] = SS_NB - 1;
+    }
+  }
+
+  uint32_t r[IPT];
+  rank_wave_items<IPT>(d, r, s_mask[w], s_whist[w]);
+  __syncthreads();
+
+  uint32_t cnt = wave_prefix_per_digit<NW, SS_NB>(s_whist);
+  if (t == SS_NB - 1) cnt -= (uint32_t)TILE - valid;  // padding: last id, sorted last
+  uint32_t total;
+  const uint32_t tstart = block_excl_scan<SS_THREADS>(cnt, s_scan, total);
+  s_tstart[t] = tstart;
+  const uint64_t excl = lookback<SS_NB>(a.status, tile, sg.first_tile, (uint32_t)t, cnt, a.epoch);
+  s_dbase[t] = a.offs[(size_t)sidx * SS_NB + t] + (uint32_t)excl;
+  __syncthreads();
+
+#pragma unroll
+  for (int i = 0; i < IPT; ++i) {
+    const uint32_t lp = s_tstart[d[i]] + s_whist[w][d[i]] + r[i];
+    if (lp < (uint32_t)TILE) {
+      s_keys[lp] = k[i];
+      if constexpr (PAY) s_vals[lp] = v[i];
+      s_dig[lp] = (uint16_t)d[i];
+    }
+  }
+  __syncthreads();
+
+  K* __restrict__ dst = (K*)a.dst;
+  const uint64_t lim = sg.start + sg.size;
+  for (uint32_t j = t; j < valid; j += SS_THREADS) {
+    const uint32_t dj = s_dig[j];
+    const uint64_t o = (uint64_t)s_dbase[dj] + (j - s_tstart[dj]);
+    if (o < sg.start || o >= lim) continue;  // unreachable with consistent counts
+    dst[o] = s_keys[j];
+    if constexpr (PAY) a.vdst[o] = s_vals[j];
+  }
+}
+
+// ------------------------------------------------------------------ block sort
+// One block per item.  COPY items move (and unmap) keys.  SORT items (at
+// most SS_CAP keys) are loaded into LDS and sorted stably by LSD passes over
+// 8-bit digits of (key - min) using the same wave ranking, then written out.
+template <int KK, bool PAY>
+__global__ __launch_bounds__(SS_THREADS) void k_ss_block(SsBlockArgs a) {
+  using K = typename KeyTraits<KK>::K;
+  constexpr int IPT = SS_CAP / SS_THREADS;
+  constexpr int NW = SS_THREADS / WAVE;
+  __shared__ uint64_t s_mask[NW][256];
+  __shared__ uint32_t s_whist[NW][256];
+  __shared__ uint32_t s_tstart[256];
+  __shared__ K s_keys[SS_CAP];
+  __shared__ uint32_t s_vals[PAY ? SS_CAP : 1];
+  __shared__ uint32_t s_scan[NW + 1];
+  __shared__ K s_red[2][NW];
+
+  const SsItem it = a.items[blockIdx.x];
+  const uint32_t buf = (it.flags >> 8) & 0xFFu;
+  const K* __restrict__ src = (const K*)(buf == SS_BUF_IN ? a.kin : (buf == SS_BUF_OUT ? a.kout : a.ktmp));
+  const uint32_t* __restrict__ vsrc = buf == SS_BUF_IN ? a.vin : (buf == SS_BUF_OUT ? a.vout : a.vtmp);
+  const bool raw = buf == SS_BUF_IN;
+  K* __restrict__ dst = (K*)a.kout;
+  const int t = threadIdx.x, w = t / WAVE, lane = lane_id();
+  const uint64_t base = it.start;
+  const uint32_t size = it.size;
+
+  if (it.flags & SS_ITEM_COPY) {
+    for (uint32_t j = t; j < size; j += SS_THREADS) {
+      K x = src[base + j];
+      if constexpr (KeyTraits<KK>::FLT) x = raw ? x : funmap(x);
+      dst[base + j] = x;
+      if constexpr (PAY) a.vout[base + j] = vsrc[base + j];
+    }
+    return;
+  }
+
+  K mn = ~K(0), mx = K(0);
+  for (uint32_t j = t; j < size; j += SS_THREADS) {
+    K x = src[base + j];
+    if constexpr (KeyTraits<KK>::FLT) x = raw ? fmap(x) : x;
+    s_keys[j] = x;
+    if constexpr (PAY) s_vals[j] = vsrc[base + j];
+    mn = x < mn ? x : mn;
+    mx = x > mx ? x : mx;
+  }
+  mn = wave_min(mn);
+  mx = wave_max(mx);
+  if (lane == 0) { s_red[0][w] = mn; s_red[1][w] = mx; }
+  for (int i = t; i < NW * 256; i += SS_THREADS) {
+    (&s_mask[0][0])[i] = 0ull;
+  }
+  __syncthreads();
+  mn = s_red[0][0];
+  mx = s_red[1][0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) {
+    mn = s_red[0][i] < mn ? s_red[0][i] : mn;
+    mx = s_red[1][i] > mx ? s_red[1][i] : mx;
+  }
+  const int npass = (bitlen64((uint64_t)(mx - mn)) + 7) / 8;
+
+  for (int p = 0; p < npass; ++p) {
+    K k[IPT];
+    uint32_t v[IPT];
+    uint32_t d[IPT];
+    const uint32_t wbase = (uint32_t)w * WAVE * IPT;
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+      const uint32_t idx = wbase + (uint32_t)i * WAVE + lane;
+      if (idx < size) {
+        k[i] = s_keys[idx];
+        if constexpr (PAY) v[i] = s_vals[idx];
+        d[i] = (uint32_t)(((k[i] - mn) >> (8 * p)) & 255u);
+      } else {
+        k[i] = ~K(0);
+        if constexpr (PAY) v[i] = 0;
+        d[i] = 255u;
+      }
+    }
+    for (int i = t; i < NW * 256; i += SS_THREADS) (&s_whist[0][0])[i] = 0u;
+    __syncthreads();
+    uint32_t r[IPT];
+    rank_wave_items<IPT>(d, r, s_mask[w], s_whist[w]);
+    __syncthreads();
+    const uint32_t cnt = wave_prefix_per_digit<NW>(s_whist);
+    uint32_t total;
+    const uint32_t tstart = block_excl_scan<SS_THREADS>(t < 256 ? cnt : 0u, s_scan, total);
+    if (t < 256) s_tstart[t] = tstart;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+      const uint32_t lp = s_tstart[d[i]] + s_whist[w][d[i]] + r[i];
+      if (lp < (uint32_t)SS_CAP) {
+        s_keys[lp] = k[i];
+        if constexpr (PAY) s_vals[lp] = v[i];
+      }
+    }
+    __syncthreads();
+  }
+
+  for (uint32_t j = t; j < size; j += SS_THREADS) {
+    K x = s_keys[j];
+    if constexpr (KeyTraits<KK>::FLT) x = funmap(x);
+    dst[base + j] = x;
+    if constexpr (PAY) a.vout[base + j] = s_vals[j];
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+hipError_t launch_ss_init(SsSeg* segs, SsItem* items, uint64_t n, hipStream_t s) {
+  k_ss_init<<<1, 64, 0, s>>>(segs, items, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_ss_sample(int kk, const void* src, int map_in, const SsSeg* segs, uint32_t nsegs, void* spl,
+                            uint64_t seed, hipStream_t s) {
+  switch (kk) {
+    case KK_U32: k_ss_sample<KK_U32><<<nsegs, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, (uint32_t*)spl, seed); break;
+    case KK_U64: k_ss_sample<KK_U64><<<nsegs, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, (uint64_t*)spl, seed); break;
+    case KK_F32: k_ss_sample<KK_F32><<<nsegs, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, (uint32_t*)spl, seed); break;
+    case KK_F64: k_ss_sample<KK_F64><<<nsegs, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, (uint64_t*)spl, seed); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ss_count(int kk, const void* src, int map_in, const SsSeg* segs, uint32_t nsegs, uint32_t ntiles,
+                           const void* spl, uint32_t* counts, int nblocks, hipStream_t s) {
+  const uint32_t tk = (uint32_t)ss_tile(kk == KK_U32 || kk == KK_F32 ? 4 : 8);
+  switch (kk) {
+    case KK_U32: k_ss_count<KK_U32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, nsegs, ntiles, tk, (const uint32_t*)spl, counts); break;
+    case KK_U64: k_ss_count<KK_U64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, nsegs, ntiles, tk, (const uint64_t*)spl, counts); break;
+    case KK_F32: k_ss_count<KK_F32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, nsegs, ntiles, tk, (const uint32_t*)spl, counts); break;
+    case KK_F64: k_ss_count<KK_F64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, nsegs, ntiles, tk, (const uint64_t*)spl, counts); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ss_plan(const SsSeg* segs, uint32_t nsegs, const uint32_t* counts, uint32_t* offs, uint32_t dst_buf,
+                          int copy_in_place, SsSeg* next, SsItem* items, SsCounters* ctr, uint32_t item_cap,
+                          uint32_t seg_cap, hipStream_t s) {
+  k_ss_plan<<<nsegs, SS_NB, 0, s>>>(segs, counts, offs, dst_buf, copy_in_place, next, items, ctr, item_cap, seg_cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_ss_tiles(SsSeg* segs, SsCounters* ctr, uint32_t tile_keys, uint32_t seg_cap, hipStream_t s) {
+  k_ss_tiles<<<1, SS_TILES_THREADS, 0, s>>>(segs, ctr, tile_keys, seg_cap);
+  return hipGetLastError();
+}
+
+template <int KK, bool PAY>
+static hipError_t scatter_kk(const SsScatterArgs& a, uint32_t ntiles, hipStream_t s) {
+  constexpr int IPT = sizeof(typename KeyTraits<KK>::K) == 4 ? 16 : 8;
+  k_ss_scatter<KK, PAY, IPT><<<ntiles, SS_THREADS, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_ss_scatter(int kk, int with_vals, const SsScatterArgs& a, uint32_t ntiles, hipStream_t s) {
+  if (ntiles == 0) return hipSuccess;
+  switch (kk * 2 + (with_vals ? 1 : 0)) {
+    case KK_U32 * 2: return scatter_kk<KK_U32, false>(a, ntiles, s);
+    case KK_U32 * 2 + 1: return scatter_kk<KK_U32, true>(a, ntiles, s);
+    case KK_U64 * 2: return scatter_kk<KK_U64, false>(a, ntiles, s);
+    case KK_U64 * 2 + 1: return scatter_kk<KK_U64, true>(a, ntiles, s);
+    case KK_F32 * 2: return scatter_kk<KK_F32, false>(a, ntiles, s);
+    case KK_F32 * 2 + 1: return scatter_kk<KK_F32, true>(a, ntiles, s);
+    case KK_F64 * 2: return scatter_kk<KK_F64, false>(a, ntiles, s);
+    case KK_F64 * 2 + 1: return scatter_kk<KK_F64, true>(a, ntiles, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_ss_block(int kk, int with_vals, const SsBlockArgs& a, uint32_t nitems, hipStream_t s) {
+  if (nitems == 0) return hipSuccess;
+  switch (kk * 2 + (with_vals ? 1 : 0)) {
+    case KK_U32 * 2: k_ss_block<KK_U32, false><<<nitems, SS_THREADS, 0, s>>>(a); break;
+    case KK_U32 * 2 + 1: k_ss_block<KK_U32, true><<<nitems, SS_THREADS, 0, s>>>(a); break;
+    case KK_U64 * 2: k_ss_block<KK_U64, false><<<nitems, SS_THREADS, 0, s>>>(a); break;
+    case KK_U64 * 2 + 1: k_ss_block<KK_U64, true><<<nitems, SS_THREADS, 0, s>>>(a); break;
+    case KK_F32 * 2: k_ss_block<KK_F32, false><<<nitems, SS_THREADS, 0, s>>>(a); break;
+    case KK_F32 * 2 + 1: k_ss_block<KK_F32, true><<<nitems, SS_THREADS, 0, s>>>(a); break;
+    case KK_F64 * 2: k_ss_block<KK_F64, false><<<nitems, SS_THREADS, 0, s>>>(a); break;
+    case KK_F64 * 2 + 1: k_ss_block<KK_F64, true><<<nitems, SS_THREADS, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ahs

@@ -1,0 +1,74 @@
+// Sample-sort shapes, device tables and launchers shared by the kernels
+// (samplesort.hip) and the host level loop (samplesort_host.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+
+namespace ahs {
+
+constexpr int SS_P = 255;             // splitters per segment
+constexpr int SS_NB = 512;            // bucket-id space (2 * SS_P + 1 used)
+constexpr int SS_SAMPLES = 8192;      // sample keys per segment
+constexpr int SS_CAP = 8192;          // largest bucket finished in LDS
+constexpr int SS_THREADS = 512;
+constexpr int SS_MAX_LEVELS = 48;
+inline int ss_tile(int key_bytes) { return SS_THREADS * (key_bytes == 4 ? 16 : 8); }
+
+constexpr uint32_t SS_BUF_IN = 0, SS_BUF_OUT = 1, SS_BUF_TMP = 2;
+constexpr uint32_t SS_ITEM_COPY = 1;
+
+struct SsSeg {        // a range of the current buffer still to be split
+  uint64_t start;
+  uint32_t size;
+  uint32_t first_tile;
+};
+struct SsItem {       // a finished bucket: sort in LDS, or copy
+  uint64_t start;
+  uint32_t size;
+  uint32_t flags;     // bit 0: copy only; bits 8..15: source buffer id
+};
+struct SsCounters {   // per level, written by the device, read by the host
+  uint32_t nsegs_next, nitems, ntiles_next, overflow;
+};
+
+struct SsScatterArgs {
+  const void* src;
+  void* dst;
+  const uint32_t* vsrc;
+  uint32_t* vdst;
+  uint32_t map_in;
+  uint32_t nsegs;
+  const SsSeg* segs;
+  const void* spl;
+  const uint32_t* offs;
+  uint64_t* status;
+  uint32_t* tile_counter;
+  uint32_t epoch;
+};
+
+struct SsBlockArgs {
+  const SsItem* items;
+  const void* kin;
+  void* kout;
+  const void* ktmp;
+  const uint32_t* vin;
+  uint32_t* vout;
+  const uint32_t* vtmp;
+};
+
+hipError_t launch_ss_init(SsSeg* segs, SsItem* items, uint64_t n, hipStream_t s);
+hipError_t launch_ss_sample(int kk, const void* src, int map_in, const SsSeg* segs, uint32_t nsegs, void* spl,
+                            uint64_t seed, hipStream_t s);
+hipError_t launch_ss_count(int kk, const void* src, int map_in, const SsSeg* segs, uint32_t nsegs, uint32_t ntiles,
+                           const void* spl, uint32_t* counts, int nblocks, hipStream_t s);
+hipError_t launch_ss_plan(const SsSeg* segs, uint32_t nsegs, const uint32_t* counts, uint32_t* offs, uint32_t dst_buf,
+                          int copy_in_place, SsSeg* next, SsItem* items, SsCounters* ctr, uint32_t item_cap,
+                          uint32_t seg_cap, hipStream_t s);
+hipError_t launch_ss_tiles(SsSeg* segs, SsCounters* ctr, uint32_t tile_keys, uint32_t seg_cap, hipStream_t s);
+hipError_t launch_ss_scatter(int kk, int with_vals, const SsScatterArgs& a, uint32_t ntiles, hipStream_t s);
+hipError_t launch_ss_block(int kk, int with_vals, const SsBlockArgs& a, uint32_t nitems, hipStream_t s);
+
+}  // namespace ahs

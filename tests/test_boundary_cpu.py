@@ -1,0 +1,123 @@
+"""CPU checks of the boundary: the C-ABI library loads, exports every call
+include/ahs.h declares, and its pure host functions (config presets, the
+decision engine, the model evaluator, workspace sizing) agree with the
+hand-worked fixtures and with the oracle's independent implementation."""
+import ctypes as C
+import json
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ahs.h")
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+ahs = pytest.importorskip("paper_2506_20677_amd")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ahs_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = ahs.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), f"libahs.so does not export {name}"
+
+
+def test_config_presets():
+    for preset, kc in ((0, 4096), (1, 1000), (2, 1024)):
+        c = ahs.ahs_config_init(preset)
+        assert (c.n_small, c.k_count, c.k_radix, c.h_ratio, c.ml_min_n, c.k_count_cap, c.use_model) == (
+            20, kc, 1000000, 0.7, 1000, 65536, 0)
+    with pytest.raises(ahs.AhsError):
+        ahs.ahs_config_init(7)
+
+
+def _fv(n, span, nbins, H):
+    f = ahs.FeatureVector()
+    f.n, f.span, f.nbins, f.entropy_bits = n, span, nbins, H
+    return f
+
+
+def test_select_matches_fsm_table():
+    tab = json.load(open(os.path.join(GOLDEN, "fsm_table.json")))
+    names = {"insertion": ahs.INSERTION, "counting": ahs.COUNTING, "radix": ahs.RADIX, "quick": ahs.QUICK}
+    for row in tab["rows"]:
+        cfg = ahs.ahs_config_init(tab["presets"][row["preset"]])
+        assert ahs.ahs_select(_fv(row["n"], row["span"], row["nbins"], row["H"]), cfg) == names[row["expect"]], row
+
+
+def test_select_agrees_with_oracle_on_grid():
+    """Dense grid around every threshold, host decision vs the oracle's."""
+    rng = np.random.default_rng(0)
+    spans = [0, 1, 999, 1000, 1023, 1024, 4095, 4096, 4097, 65535, 65536, 999_999, 1_000_000, 1_000_001,
+             2**32 - 1, 2**63, 2**64 - 1]
+    for preset in (0, 1, 2):
+        cfg = ahs.ahs_config_init(preset)
+        ocfg = O.config(preset)
+        for n in (0, 1, 20, 21, 999, 1000, 10**6):
+            for span in spans:
+                s = span
+                shift = max(0, s.bit_length() - 16)
+                nb = (s >> shift) + 1
+                thr = 0.7 * math.log2(nb) if nb > 1 else 0.0
+                for H in (0.0, thr - 1e-9, thr, thr + 1e-9, rng.uniform(0, 16)):
+                    got = ahs.ahs_select(_fv(n, span, nb, H), cfg)
+                    of = O.Features(n=n, span=span, nbins=nb, entropy_bits=H)
+                    assert got == O.select(of, ocfg)[1], (preset, n, span, H)
+
+
+def test_model_matches_fixtures_and_oracle():
+    cases = json.load(open(os.path.join(GOLDEN, "model_cases.json")))
+    names = {"counting": ahs.COUNTING, "radix": ahs.RADIX, "quick": ahs.QUICK}
+    m = ahs.ahs_model_load(os.path.join(GOLDEN, "tiny_model.gbt"))
+    tie = ahs.ahs_model_load(os.path.join(GOLDEN, "tie_model.gbt"))
+    for c in cases["tiny_model"]:
+        assert ahs.ahs_model_predict(m, _fv(c["n"], c["span"], c["nbins"], c["H"])) == names[c["expect"]]
+    for c in cases["tie_model"]:
+        assert ahs.ahs_model_predict(tie, _fv(c["n"], c["span"], c["nbins"], c["H"])) == names[c["expect"]]
+    cfg = ahs.ahs_config_init(0, use_model=1)
+    for c in cases["select_with_tiny_model"]:
+        assert ahs.ahs_select(_fv(c["n"], c["span"], c["nbins"], c["H"]), cfg, m) == names[c["expect"]], c
+    for c in cases["select_with_tie_model_cap"]:
+        assert ahs.ahs_select(_fv(c["n"], c["span"], c["nbins"], c["H"]), cfg, tie) == names[c["expect"]], c
+    with pytest.raises(ahs.AhsError) as e:
+        ahs.ahs_select(_fv(5000, 10, 11, 1.0), cfg, None)
+    assert e.value.status == ahs.E_NO_MODEL
+    om = O.Model(os.path.join(GOLDEN, "tiny_model.gbt"))
+    rng = np.random.default_rng(3)
+    for _ in range(2000):
+        n = int(rng.integers(0, 10**7))
+        span = int(rng.choice([rng.integers(0, 10**4), rng.integers(0, 10**7)]))
+        H = float(rng.uniform(0, 20))
+        assert ahs.ahs_model_predict(m, _fv(n, span, 1, H)) == om.predict(O.Features(n=n, span=span, entropy_bits=H))
+
+
+def test_model_rejects_malformed(tmp_path):
+    p = tmp_path / "bad.gbt"
+    p.write_text("ahs-gbt 1\nnum_class 3\nbase_score 0 0 0\nnum_trees 1\ntree 0 2\n0 split 1 5 0 1\n1 leaf 1\n")
+    with pytest.raises(ahs.AhsError) as e:
+        ahs.ahs_model_load(str(p))
+    assert e.value.status == ahs.E_PARSE
+
+
+def test_workspace_sizes_monotone_and_data_independent():
+    prev = 0
+    for n in (0, 1, 100, 8192, 8193, 10**6, 2**28):
+        b = ahs.ahs_workspace_bytes(n, ahs.U32, False, ahs.AUTO)
+        assert b >= prev and b % 256 == 0
+        prev = b
+        # scratch keys: at least one n-key buffer
+        assert b >= 4 * n
+    assert ahs.ahs_workspace_bytes(1000, ahs.U64, True, ahs.RADIX) > ahs.ahs_workspace_bytes(1000, ahs.U32, False, ahs.RADIX)
+    assert ahs.ahs_workspace_bytes(10, 9, False, ahs.AUTO) == 0

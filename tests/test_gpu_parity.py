@@ -1,0 +1,359 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Bar: keys, payloads, min/max/span/shift/nbins, histograms and the chosen
+strategy bit-exact; entropy within 1e-6 relative (0 exactly when the
+oracle's is 0); strategy disagreement accepted only when the oracle's
+entropy lies within 1e-6 relative of the radix threshold 0.7*log2(nbins).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2506_20677_amd as ahs  # noqa: E402
+
+DEV = torch.device("cuda:0")
+H_RTOL = 1e-6
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def bits(a):
+    return a.view(np.uint32 if a.itemsize == 4 else np.uint64)
+
+
+def check_features(f, rf, hist=None, rhist=None):
+    assert (f.n, f.min_key, f.max_key, f.span, f.nan_count) == (rf.n, rf.min_key, rf.max_key, rf.span, rf.nan_count)
+    assert (f.shift, f.nbins, f.exact) == (rf.shift, rf.nbins, rf.exact)
+    if rf.entropy_bits == 0.0:
+        assert f.entropy_bits == 0.0
+    else:
+        assert abs(f.entropy_bits - rf.entropy_bits) <= H_RTOL * rf.entropy_bits, (f.entropy_bits, rf.entropy_bits)
+    if hist is not None:
+        assert np.array_equal(hist[: rf.nbins], rhist)
+
+
+def near_threshold(rf, cfg=None):
+    if rf.nbins <= 1:
+        return False
+    thr = 0.7 * math.log2(rf.nbins)
+    return abs(rf.entropy_bits - thr) <= H_RTOL * thr
+
+
+def run_pair(keys, vals=None, strategy=ahs.AUTO, cfg_preset=0, in_place=False):
+    """Sorts on the GPU and with the oracle; asserts the bar."""
+    say(f"case n={keys.size} dtype={keys.dtype} payload={vals is not None} strategy={strategy} inplace={in_place}")
+    k = to_dev(keys)
+    v = to_dev(vals) if vals is not None else None
+    cfg = ahs.ahs_config_init(cfg_preset)
+    if in_place:
+        ko, vo, chosen, f = ahs.ahs_sort(k, v, strategy, cfg, out=k, out_values=v, want_features=True)
+    else:
+        ko, vo, chosen, f = ahs.ahs_sort(k, v, strategy, cfg, want_features=True)
+    torch.cuda.synchronize()
+    st, rk, rv, rchosen, rf = O.sort(keys, vals, strategy, O.config(cfg_preset))
+    if st == O.E_DEPTH and strategy == ahs.QUICK:
+        # the oracle's median-of-three quicksort refuses adversarial inputs
+        # (sawtooth); its four sorts are pinned to agree, so radix gives the
+        # same unique stable result
+        st, rk, rv, _, rf = O.sort(keys, vals, O.RADIX, O.config(cfg_preset))
+        rchosen = O.QUICK
+    assert st == O.OK, st
+    assert np.array_equal(bits(ko.cpu().numpy()), bits(rk)), "keys differ"
+    if vals is not None:
+        assert np.array_equal(vo.cpu().numpy(), rv), "payload differs"
+    check_features(f, rf)
+    if chosen != rchosen:
+        assert near_threshold(rf), (chosen, rchosen, rf.as_dict())
+    return chosen
+
+
+# ------------------------------------------------------------------ features
+FEATURE_CASES = [
+    ("pr1", lambda: gen.pr1()),
+    ("u32 uniform4096 1M", lambda: gen.strategy_sweep("uniform4096", n=1 << 20)),
+    ("u32 zipf256 1M", lambda: gen.strategy_sweep("zipf256", n=1 << 20)),
+    ("u32 uniform32 1M", lambda: gen.strategy_sweep("uniform32", n=1 << 20)),
+    ("u64 uniform 300k", lambda: gen.wide_keys("u64uniform", n=300_001)),
+    ("u64 zipf 300k", lambda: gen.wide_keys("u64zipf4096", n=300_001)),
+    ("f32 normal 300k", lambda: gen.wide_keys("f32normal", n=300_001)),
+    ("f64 normal 300k", lambda: gen.wide_keys("f64normal", n=300_001)),
+    ("u32 constant", lambda: np.full(777, 9, np.uint32)),
+    ("u32 span 8191", lambda: (np.arange(100_000) % 8192).astype(np.uint32)),
+    ("u32 span 8192", lambda: (np.arange(100_000) % 8193).astype(np.uint32)),
+    ("u32 span 65535", lambda: (np.arange(200_003) * 7 % 65536).astype(np.uint32)),
+    ("u32 span 65536", lambda: (np.arange(200_003) * 7 % 65537).astype(np.uint32)),
+    ("u32 one hot bin overflow", lambda: np.concatenate([np.zeros(300_000, np.uint32), np.full(300_000, 1, np.uint32),
+                                                         np.array([2**32 - 1], np.uint32)])),
+    ("u64 two", lambda: np.array([0, 2**64 - 1], np.uint64)),
+    ("f32 signed zeros", lambda: np.array([0.0, -0.0] * 50, np.float32)),
+    ("u32 n=1", lambda: np.array([12345], np.uint32)),
+]
+
+
+@pytest.mark.parametrize("name,make", FEATURE_CASES, ids=[c[0] for c in FEATURE_CASES])
+def test_features_parity(name, make):
+    keys = make()
+    say(f"features {name} n={keys.size}")
+    hist = torch.zeros(65536, dtype=torch.int32, device=DEV)
+    f = ahs.ahs_features(to_dev(keys), hist)
+    torch.cuda.synchronize()
+    st, rf, rhist = O.features(keys)
+    assert st == O.OK
+    check_features(f, rf, hist.cpu().numpy().view(np.uint32), rhist)
+
+
+def test_features_bin_overflow_exact():
+    """More than 65,535 keys of one bin inside one block: the packed 16-bit
+    counters wrap and the corrections must restore the exact count."""
+    n = 1 << 21
+    keys = np.zeros(n, np.uint32)
+    keys[::3] = 1
+    keys[-1] = 2**32 - 1  # forces the 65,536-bin histogram (shift 16: keys 0, 1 share bin 0)
+    keys[5] = 70000
+    hist = torch.zeros(65536, dtype=torch.int32, device=DEV)
+    f = ahs.ahs_features(to_dev(keys), hist)
+    st, rf, rhist = O.features(keys)
+    check_features(f, rf, hist.cpu().numpy().view(np.uint32), rhist)
+
+
+def test_features_nan():
+    keys = np.array([1.0, np.nan, 2.0], np.float32)
+    with pytest.raises(ahs.AhsError) as e:
+        ahs.ahs_features(to_dev(keys))
+    assert e.value.status == ahs.E_NAN and e.value.features.nan_count == 1
+
+
+def test_features_empty():
+    f = ahs.ahs_features(torch.empty(0, dtype=torch.uint32, device=DEV))
+    assert f.n == 0 and f.nbins == 0
+
+
+# ------------------------------------------------------------------ sorts
+def test_pr1_auto_radix_parity():
+    """PR1 shape: 1,000,000 u32 uniform on [0, 1023]; AUTO picks counting."""
+    keys = gen.pr1()
+    assert run_pair(keys) == ahs.COUNTING
+    vals = np.arange(keys.size, dtype=np.uint32)
+    assert run_pair(keys, vals) == ahs.COUNTING
+    assert run_pair(keys, vals, ahs.RADIX) == ahs.RADIX
+    assert run_pair(keys, None, ahs.RADIX) == ahs.RADIX
+
+
+SIZES = [1, 2, 19, 20, 21, 100, 4095, 4096, 4097, 8191, 8192, 8193, 3 * 8192 + 17, 65537, 300_001]
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_radix_sizes_u32(n):
+    r = np.random.default_rng(n)
+    keys = r.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    run_pair(keys, np.arange(n, dtype=np.uint32), ahs.RADIX)
+    run_pair(keys, None, ahs.RADIX)
+
+
+@pytest.mark.parametrize("n", [1, 21, 4095, 4097, 100_003])
+@pytest.mark.parametrize("kind", ["u64", "f32", "f64"])
+def test_radix_wide(n, kind):
+    r = np.random.default_rng(n + 7)
+    if kind == "u64":
+        keys = r.integers(0, 2**64, n, dtype=np.uint64)
+    elif kind == "f32":
+        keys = r.normal(0, 1e3, n).astype(np.float32)
+        keys[::97] = -0.0
+        keys[::89] = 0.0
+        keys[::1001] = np.inf
+    else:
+        keys = r.normal(0, 1.0, n)
+        keys[::53] = -np.inf
+        keys[::59] = -0.0
+    vals = np.arange(n, dtype=np.uint32)
+    run_pair(keys, vals, ahs.RADIX)
+    run_pair(keys, None, ahs.RADIX)
+
+
+@pytest.mark.parametrize("n", [21, 1000, 8193, 100_000, 1_000_003])
+@pytest.mark.parametrize("k", [1, 2, 255, 256, 1000, 4096])
+def test_counting(n, k):
+    r = np.random.default_rng(n * 31 + k)
+    keys = (r.integers(0, k, n) + 1_000_000).astype(np.uint32)
+    run_pair(keys, None, ahs.COUNTING)
+    run_pair(keys, np.arange(n, dtype=np.uint32), ahs.COUNTING)
+
+
+@pytest.mark.parametrize("dt", [np.uint64, np.float32, np.float64])
+def test_counting_wide(dt):
+    r = np.random.default_rng(5)
+    if dt == np.uint64:
+        keys = r.integers(0, 3000, 50_001).astype(np.uint64) + np.uint64(2**63)
+    elif dt == np.float32:
+        keys = (r.integers(0, 3000, 50_001).astype(np.uint32) + np.uint32(0x3F800000)).view(np.float32)
+    else:
+        keys = (r.integers(0, 3000, 50_001).astype(np.uint64) + np.uint64(0xC000000000000000)).view(np.float64)
+    run_pair(keys, None, ahs.COUNTING)
+    run_pair(keys, np.arange(keys.size, dtype=np.uint32), ahs.COUNTING)
+
+
+def test_auto_choices_match_oracle():
+    cases = {
+        "uniform4096": ahs.COUNTING,
+        "zipf256": ahs.RADIX,
+    }
+    for case, want in cases.items():
+        keys = gen.strategy_sweep(case, n=1 << 20)
+        assert run_pair(keys) == want
+        assert run_pair(keys, np.arange(keys.size, dtype=np.uint32)) == want
+    for case, want in (("u64zipf4096", ahs.RADIX), ("f32normal", ahs.RADIX), ("f64normal", ahs.RADIX)):
+        keys = gen.wide_keys(case, n=1 << 19)
+        assert run_pair(keys, np.arange(keys.size, dtype=np.uint32)) == want
+
+
+def test_insertion_state():
+    for n in (1, 2, 5, 20):
+        r = np.random.default_rng(n)
+        keys = r.integers(0, 5, n).astype(np.uint32)
+        assert run_pair(keys, np.arange(n, dtype=np.uint32)) == ahs.INSERTION
+    keys = np.array([0.0, -0.0, np.inf, -np.inf, 1.0, -1.0], np.float32)
+    assert run_pair(keys, np.arange(6, dtype=np.uint32)) == ahs.INSERTION
+
+
+@pytest.mark.parametrize("strategy", [ahs.AUTO, ahs.RADIX, ahs.COUNTING])
+def test_in_place(strategy):
+    r = np.random.default_rng(11)
+    keys = r.integers(0, 3000, 70_001).astype(np.uint32)
+    run_pair(keys, np.arange(keys.size, dtype=np.uint32), strategy, in_place=True)
+    run_pair(keys, None, strategy, in_place=True)
+    if strategy == ahs.RADIX:
+        keys = r.integers(0, 2**32, 70_001, dtype=np.uint64).astype(np.uint32)
+        run_pair(keys, np.arange(keys.size, dtype=np.uint32), strategy, in_place=True)
+
+
+def test_edge_patterns():
+    n = 50_000
+    asc = (np.arange(n, dtype=np.uint64) * 86_028_121 % 2**32).astype(np.uint32)
+    asc.sort()
+    pats = {
+        "constant": np.full(n, 5, np.uint32),
+        "ascending": asc,
+        "descending": asc[::-1].copy(),
+        "sawtooth": np.tile(np.concatenate([np.arange(500), np.arange(500)[::-1]]), n // 1000).astype(np.uint32) * 9973,
+        "alternating": np.tile(np.array([1, 2**31], np.uint32), n // 2),
+    }
+    for name, keys in pats.items():
+        say("pattern", name)
+        run_pair(keys, np.arange(n, dtype=np.uint32), ahs.RADIX)
+        run_pair(keys, np.arange(n, dtype=np.uint32), ahs.AUTO) if name in ("constant",) else None
+
+
+def test_errors():
+    k = to_dev(np.array([1.0, np.nan], np.float32))
+    with pytest.raises(ahs.AhsError) as e:
+        ahs.ahs_sort(k)
+    assert e.value.status == ahs.E_NAN
+    k = to_dev(np.array([0, 100_000], np.uint32))
+    with pytest.raises(ahs.AhsError) as e:
+        ahs.ahs_sort(k, strategy=ahs.COUNTING)
+    assert e.value.status == ahs.E_UNSUPPORTED
+    with pytest.raises(ahs.AhsError) as e:
+        ahs.ahs_sort(k, strategy=ahs.INSERTION)
+    assert e.value.status == ahs.E_INVALID_ARG
+    ko, _, chosen, _ = ahs.ahs_sort(torch.empty(0, dtype=torch.uint32, device=DEV))
+    assert ko.numel() == 0 and chosen == ahs.INSERTION
+
+
+def test_repeatability():
+    """Same input, many runs: identical bits (deterministic look-back)."""
+    keys = gen.strategy_sweep("zipf256", n=1 << 20)
+    vals = np.arange(keys.size, dtype=np.uint32)
+    k, v = to_dev(keys), to_dev(vals)
+    ref = None
+    for i in range(20):
+        ko, vo, _, _ = ahs.ahs_sort(k, v, ahs.RADIX)
+        cur = (ko.cpu().numpy().copy(), vo.cpu().numpy().copy())
+        if ref is None:
+            ref = cur
+        assert np.array_equal(cur[0], ref[0]) and np.array_equal(cur[1], ref[1])
+
+
+# ------------------------------------------------------------------ general path (sample sort)
+QUICK_SIZES = [1, 2, 21, 8191, 8192, 8193, 12_289, 100_003, 1_000_001]
+
+
+@pytest.mark.parametrize("n", QUICK_SIZES)
+def test_quick_sizes_u32(n):
+    r = np.random.default_rng(n + 100)
+    keys = r.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    run_pair(keys, np.arange(n, dtype=np.uint32), ahs.QUICK)
+    run_pair(keys, None, ahs.QUICK)
+
+
+@pytest.mark.parametrize("kind", ["u64", "f32", "f64", "u64zipf", "few"])
+@pytest.mark.parametrize("n", [8193, 300_007])
+def test_quick_wide_and_duplicates(kind, n):
+    r = np.random.default_rng(n + len(kind))
+    if kind == "u64":
+        keys = r.integers(0, 2**64, n, dtype=np.uint64)
+    elif kind == "f32":
+        keys = r.normal(0, 1e3, n).astype(np.float32)
+        keys[::97] = -0.0
+        keys[::89] = 0.0
+    elif kind == "f64":
+        keys = r.normal(0, 1.0, n)
+        keys[::53] = -np.inf
+        keys[::59] = -0.0
+    elif kind == "u64zipf":
+        keys = gen.wide_keys("u64zipf4096", n=n)
+    else:
+        keys = r.choice(np.array([7, 7, 7, 9, 2**31, 5], np.uint32), n)
+    run_pair(keys, np.arange(n, dtype=np.uint32), ahs.QUICK)
+    run_pair(keys, None, ahs.QUICK)
+
+
+def test_quick_patterns():
+    n = 400_000
+    base = gen.strategy_sweep("uniform32", n=n)
+    srt = np.sort(base)
+    pats = {
+        "sorted": srt,
+        "reverse": srt[::-1].copy(),
+        "swapped": gen.apply_swaps(srt.copy(), 3, 5, n // 200),
+        "constant": np.full(n, 77, np.uint32),
+        "two-values": np.where(np.arange(n) % 3 == 0, 5, 2**32 - 1).astype(np.uint32),
+        "sawtooth": np.tile(np.concatenate([np.arange(1000), np.arange(1000)[::-1]]), n // 2000).astype(np.uint32),
+    }
+    for name, keys in pats.items():
+        say("pattern", name)
+        run_pair(keys, np.arange(n, dtype=np.uint32), ahs.QUICK)
+
+
+def test_quick_in_place():
+    r = np.random.default_rng(4)
+    for n in (5000, 250_001):
+        keys = r.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+        run_pair(keys, np.arange(n, dtype=np.uint32), ahs.QUICK, in_place=True)
+        keys = r.normal(0, 1, n).astype(np.float32)
+        run_pair(keys, np.arange(n, dtype=np.uint32), ahs.QUICK, in_place=True)
+
+
+def test_auto_general_path():
+    for case in ("uniform32", "sorted32", "reverse32", "swapped32"):
+        keys = gen.strategy_sweep(case, n=1 << 20)
+        assert run_pair(keys) == ahs.QUICK
+    keys = gen.wide_keys("u64uniform", n=1 << 19)
+    assert run_pair(keys, np.arange(keys.size, dtype=np.uint32)) == ahs.QUICK
