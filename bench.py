@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Benchmark of the Adaptive Hybrid Sort hot path on one MI355X.
+
+Workload (default): the strategy sweep at scale -- six arrays of 2^28
+uint32 keys: (a) uniform on [0, 4095] (counting), (b) 256 distinct random
+32-bit values with Zipf(1.1) ranks (radix), (c) uniform 32-bit keys,
+unsorted, sorted, reversed and sorted with n/200 random transpositions
+(general path).  One step sorts all six with AHS AUTO (features, decision,
+the chosen sort); inputs are resident in HBM before the timed region.
+
+Prints one JSON line: whole-job Gkeys/s, the dominant kernel's roofline
+(algorithmic bytes per launch over its average launch time, both measured
+with HIP events on the launch stream), the CPU oracle on a bounded sample,
+and per-array AUTO-vs-forced-strategy timings with %HBM of each path.
+"""
+import argparse
+import json
+import os
+import platform
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Gkeys/s & %HBM peak per strategy, 2^28 uint32; batched p99 latency vs plain"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def host_info():
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--log2n", type=int, default=28, help="keys per array (2^log2n)")
+    ap.add_argument("--reps", type=int, default=5, help="runs per (array, strategy) for medians")
+    ap.add_argument("--cases", action=argparse.BooleanOptionalAction, default=True,
+                    help="per-array AUTO vs forced strategies")
+    ap.add_argument("--cpu-baseline", action=argparse.BooleanOptionalAction, default=True)
+    ap.add_argument("--cpu-sample-log2", type=int, default=22,
+                    help="keys of each array the oracle sorts for the CPU baseline")
+    ap.add_argument("--only", default=None, help="comma list of sweep cases to run")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(how the sort would shard is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2506_20677_amd as ahs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    n = 1 << args.log2n
+    cases = list(gen.SWEEP_CASES) if not args.only else args.only.split(",")
+
+    # ------------------------------------------------------------ inputs
+    host = {}
+    dkeys = {}
+    for c in cases:
+        t = time.time()
+        host[c] = gen.strategy_sweep(c, n=n)
+        dkeys[c] = torch.from_numpy(host[c]).to(dev)
+        log(f"[bench] generated {c} n=2^{args.log2n} in {time.time() - t:.1f}s")
+    out = torch.empty(n, dtype=torch.uint32, device=dev)
+    ctx = ahs.default_context(0)
+    ws_bytes = ahs.ahs_workspace_bytes(n, ahs.U32, False, ahs.AUTO)
+    ctx.workspace(ws_bytes)
+    torch.cuda.synchronize()
+
+    def step():
+        chosen = {}
+        for c in cases:
+            _, _, ch, _ = ahs.ahs_sort(dkeys[c], strategy=ahs.AUTO, out=out, ctx=ctx)
+            chosen[c] = ahs.STRATEGY_NAMES[ch]
+        return chosen
+
+    for _ in range(args.warmup):
+        chosen = step()
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done, AUTO choices {chosen}")
+
+    # ------------------------------------------------------------ timed steps
+    ahs.ahs_profile_enable(ctx, True)
+    ahs.ahs_profile_reset(ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        chosen = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ahs.ahs_profile_dump(ctx)
+    ahs.ahs_profile_enable(ctx, False)
+    elapsed = t1 - t0
+    keys_total = n * len(cases) * args.steps
+    value = keys_total / elapsed / 1e9
+    ms_per_step = elapsed / args.steps * 1e3
+    log(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step, {value:.2f} Gkeys/s")
+
+    dom = max(prof.items(), key=lambda kv: kv[1][1])
+    dname, (dl, dms, dbytes) = dom
+    achieved = dbytes / (dms / 1e3) / 1e9 if dms > 0 else 0.0
+    roofline = {
+        "bound": "hbm", "kernel": dname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "launches": dl, "avg_launch_ms": round(dms / dl, 5) if dl else None,
+        "algo_bytes_per_launch": round(dbytes / dl) if dl else None,
+    }
+    step_kernels = {k: {"launches": v[0], "ms_total": round(v[1], 4), "algo_GB": round(v[2] / 1e9, 4),
+                        "GBps": round(v[2] / (v[1] / 1e3) / 1e9, 1) if v[1] > 0 else None}
+                    for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
+
+    # ------------------------------------------------------------ per array and strategy
+    per_case = []
+    if args.cases:
+        for c in cases:
+            row = {"case": c, "auto_choice": chosen[c]}
+            ref = None
+            for sname, s in (("auto", ahs.AUTO), ("counting", ahs.COUNTING), ("radix", ahs.RADIX),
+                             ("quick", ahs.QUICK)):
+                times = []
+                path_bytes = None
+                try:
+                    for r in range(args.reps):
+                        ahs.ahs_profile_enable(ctx, True)
+                        ahs.ahs_profile_reset(ctx)
+                        torch.cuda.synchronize()
+                        a = time.perf_counter()
+                        _, _, ch, _ = ahs.ahs_sort(dkeys[c], strategy=s, out=out, ctx=ctx)
+                        torch.cuda.synchronize()
+                        times.append(time.perf_counter() - a)
+                        p = ahs.ahs_profile_dump(ctx)
+                        path_bytes = sum(v[2] for v in p.values())
+                    ahs.ahs_profile_enable(ctx, False)
+                except ahs.AhsError as e:
+                    ahs.ahs_profile_enable(ctx, False)
+                    row[sname] = {"status": e.status}
+                    continue
+                # every strategy must produce the same bits (stable sort is unique)
+                o = out.view(torch.int32)
+                if ref is None:
+                    ref = o.clone()
+                    u = o.to(torch.int64) & 0xFFFFFFFF
+                    row["sorted_ok"] = bool((u[1:] >= u[:-1]).all().item())
+                    del u
+                    agree = True
+                else:
+                    agree = bool(torch.equal(ref, o))
+                med = statistics.median(times)
+                row[sname] = {"ms": round(med * 1e3, 4), "Gkeys_s": round(n / med / 1e9, 2),
+                              "path_GB": round(path_bytes / 1e9, 3),
+                              "hbm_frac_path": round(path_bytes / med / 1e9 / HBM_PEAK_GBS, 4),
+                              "agrees": agree, "kernels": {k: [v[0], round(v[1], 4)] for k, v in p.items()}}
+            best = min((row[k]["ms"] for k in ("counting", "radix", "quick") if "ms" in row.get(k, {})),
+                       default=None)
+            if best and "ms" in row.get("auto", {}):
+                row["auto_over_best"] = round(row["auto"]["ms"] / best, 4)
+            per_case.append(row)
+            log(f"[bench] case {c}: " + json.dumps(row))
+            del ref
+
+    # ------------------------------------------------------------ CPU oracle baseline
+    cpu = None
+    if args.cpu_baseline:
+        import oracle
+
+        m = min(n, 1 << args.cpu_sample_log2)
+        tot_t, tot_k = 0.0, 0
+        for c in cases:
+            sample = np.ascontiguousarray(host[c][:m])
+            a = time.perf_counter()
+            st, _, _, _, _ = oracle.sort(sample, None, oracle.AUTO)
+            tot_t += time.perf_counter() - a
+            tot_k += m
+            if st != 0:
+                log(f"[bench] oracle status {st} on {c}")
+        cpu = {"value": round(tot_k / tot_t / 1e9, 6), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+               "sample": f"first 2^{int(np.log2(m))} keys of each of the {len(cases)} arrays, AHS AUTO, "
+                         f"single-threaded C oracle, {tot_t:.1f} s total", **host_info()}
+        log(f"[bench] cpu baseline {cpu}")
+
+    res = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"strategy sweep: {len(cases)} arrays x 2^{args.log2n} uint32 ({', '.join(cases)}), "
+                               "AHS AUTO per array", "n_per_array": n, "arrays": cases, "auto_choices": chosen},
+        "roofline": roofline, "cpu_baseline": cpu, "step_kernels": step_kernels, "per_case": per_case,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -176,15 +176,18 @@ void ahs_model_free(ahs_model* m);
 ahs_status ahs_model_predict(const ahs_model* m, const ahs_feature_vector* f, ahs_strategy* out);
 
 /* Per-kernel timing with HIP events on the launch stream.  When enabled,
- * every kernel launch of the context is bracketed by two events; totals are
- * collected (with a stream synchronisation) by ahs_profile_query.  `kernel`
- * is a family name such as "onesweep_pass", "minmax", "feature_hist". */
+ * every kernel launch of the context is bracketed by two events and tagged
+ * with its algorithmic HBM bytes (the reads and writes the method needs:
+ * keys, payloads, histograms -- not the kernel's own scratch); totals are
+ * collected (with an event synchronisation) by ahs_profile_query.  `kernel`
+ * is a family name such as "onesweep_pass", "minmax", "feature_hist",
+ * "ss_scatter".  Any output pointer may be NULL. */
 ahs_status ahs_profile_enable(ahs_context* ctx, int on);
 ahs_status ahs_profile_reset(ahs_context* ctx);
 ahs_status ahs_profile_query(ahs_context* ctx, const char* kernel, uint64_t* launches,
-                             double* total_ms);
-/* Writes "name launches total_ms\n" lines for every kernel seen; returns the
- * number of bytes needed (including the terminating zero). */
+                             double* total_ms, double* algo_bytes);
+/* Writes "name launches total_ms algo_bytes\n" lines for every kernel seen;
+ * returns the number of bytes needed (including the terminating zero). */
 size_t ahs_profile_dump(ahs_context* ctx, char* buf, size_t len);
 
 const char* ahs_status_str(ahs_status s);

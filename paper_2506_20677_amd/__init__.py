@@ -91,7 +91,8 @@ def lib():
             "ahs_model_predict": (i32, [vp, C.POINTER(FeatureVector), C.POINTER(C.c_int)]),
             "ahs_profile_enable": (i32, [vp, i32]),
             "ahs_profile_reset": (i32, [vp]),
-            "ahs_profile_query": (i32, [vp, C.c_char_p, C.POINTER(C.c_uint64), C.POINTER(C.c_double)]),
+            "ahs_profile_query": (i32, [vp, C.c_char_p, C.POINTER(C.c_uint64), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double)]),
             "ahs_profile_dump": (sz, [vp, C.c_char_p, sz]),
             "ahs_status_str": (C.c_char_p, [i32]),
             "ahs_last_error": (C.c_char_p, [vp]),
@@ -297,18 +298,21 @@ def ahs_profile_reset(ctx: Context):
 
 
 def ahs_profile_query(ctx: Context, kernel: str):
+    """(launches, total_ms, algorithmic_bytes) of one kernel family."""
     n = C.c_uint64()
     ms = C.c_double()
-    lib().ahs_profile_query(ctx.handle, kernel.encode(), C.byref(n), C.byref(ms))
-    return n.value, ms.value
+    b = C.c_double()
+    lib().ahs_profile_query(ctx.handle, kernel.encode(), C.byref(n), C.byref(ms), C.byref(b))
+    return n.value, ms.value, b.value
 
 
 def ahs_profile_dump(ctx: Context) -> dict:
+    """{kernel: (launches, total_ms, algorithmic_bytes)} for every kernel seen."""
     need = lib().ahs_profile_dump(ctx.handle, None, 0)
     buf = C.create_string_buffer(need)
     lib().ahs_profile_dump(ctx.handle, buf, need)
     out = {}
     for line in buf.value.decode().splitlines():
-        name, cnt, ms = line.split()
-        out[name] = (int(cnt), float(ms))
+        name, cnt, ms, nbytes = line.split()
+        out[name] = (int(cnt), float(ms), float(nbytes))
     return out

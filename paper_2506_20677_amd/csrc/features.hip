@@ -51,6 +51,75 @@ __device__ __forceinline__ void for_each_key(const K* __restrict__ keys, uint64_
   for (uint64_t i = head + nvec * V + tid; i < n; i += nthreads) f(keys[i]);
 }
 
+// Same traversal, but hands the callback the V keys of one 16-byte load at
+// once (g(keys, V)); head and tail keys come one at a time (g(keys, 1)).
+template <typename K, int UNROLL, typename G>
+__device__ __forceinline__ void for_each_group(const K* __restrict__ keys, uint64_t n, uint64_t tid,
+                                               uint64_t nthreads, G&& g) {
+  constexpr int V = 16 / sizeof(K);
+  const uintptr_t addr = reinterpret_cast<uintptr_t>(keys);
+  uint64_t head = ((16u - (addr & 15u)) & 15u) / sizeof(K);
+  if (head > n) head = n;
+  for (uint64_t i = tid; i < head; i += nthreads) {
+    K one[V] = {keys[i]};
+    g(one, 1);
+  }
+  const uint64_t nvec = (n - head) / V;
+  const u32x4* __restrict__ vp = reinterpret_cast<const u32x4*>(keys + head);
+  auto unpack = [](const u32x4& v, K (&kb)[V]) {
+    if constexpr (sizeof(K) == 4) {
+      kb[0] = v.x; kb[1] = v.y; kb[2] = v.z; kb[3] = v.w;
+    } else {
+      kb[0] = (uint64_t)v.x | ((uint64_t)v.y << 32);
+      kb[1] = (uint64_t)v.z | ((uint64_t)v.w << 32);
+    }
+  };
+  uint64_t j = tid;
+  for (; j + (UNROLL - 1) * nthreads < nvec; j += UNROLL * nthreads) {
+    u32x4 v[UNROLL];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) v[u] = vp[j + u * nthreads];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      K kb[V];
+      unpack(v[u], kb);
+      g(kb, V);
+    }
+  }
+  for (; j < nvec; j += nthreads) {
+    K kb[V];
+    unpack(vp[j], kb);
+    g(kb, V);
+  }
+  for (uint64_t i = head + nvec * V + tid; i < n; i += nthreads) {
+    K one[V] = {keys[i]};
+    g(one, 1);
+  }
+}
+
+// Counts m values of a run (bins b[0..m) of this lane) into LDS counters:
+// when every active lane holds m values of one and the same bin -- sorted
+// or run-structured input -- a single lane adds the whole wave's count;
+// otherwise each value is added by its own lane.  Returns nothing; used for
+// plain u32 counters.
+template <int V>
+__device__ __forceinline__ void lds_count_group(uint32_t* __restrict__ h, const uint32_t (&b)[V], int m) {
+  bool same = true;
+#pragma unroll
+  for (int i = 1; i < V; ++i)
+    if (i < m) same &= b[i] == b[0];
+  const uint32_t b0 = __builtin_amdgcn_readfirstlane(b[0]);
+  const uint64_t active = __ballot(1);
+  const uint64_t uni = __ballot(same && b[0] == b0 && m == V);
+  if (uni == active) {
+    if (mbcnt(active) == 0) atomicAdd(&h[b0], (uint32_t)popc64(active) * V);
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+      if (i < m) atomicAdd(&h[b[i]], 1u);
+  }
+}
+
 // ------------------------------------------------------------------ min/max
 template <int KK>
 __global__ __launch_bounds__(MINMAX_THREADS) void k_minmax(const typename KeyTraits<KK>::K* __restrict__ keys,
@@ -152,9 +221,12 @@ __global__ __launch_bounds__(HIST_SMALL_THREADS) void k_hist_small(const typenam
   for (uint32_t b = threadIdx.x; b < nbins; b += HIST_SMALL_THREADS) h[b] = 0;
   __syncthreads();
   const uint64_t tid = (uint64_t)blockIdx.x * HIST_SMALL_THREADS + threadIdx.x;
-  for_each_key<K, 4>(keys, n, tid, (uint64_t)gridDim.x * HIST_SMALL_THREADS, [&](K b) {
-    const K off = map_key<KK>(b) - kmin;
-    atomicAdd(&h[(uint32_t)(off >> shift)], 1u);
+  constexpr int V = 16 / sizeof(K);
+  for_each_group<K, 4>(keys, n, tid, (uint64_t)gridDim.x * HIST_SMALL_THREADS, [&](const K (&kb)[V], int m) {
+    uint32_t bins[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) bins[i] = (uint32_t)((map_key<KK>(kb[i]) - kmin) >> shift);
+    lds_count_group<V>(h, bins, m);
   });
   __syncthreads();
   uint32_t* out = partials + (size_t)blockIdx.x * nbins;
@@ -193,26 +265,69 @@ __global__ __launch_bounds__(HIST_LARGE_THREADS) void k_hist_large(const typenam
                                                                    uint32_t* __restrict__ corr, int ndig,
                                                                    uint32_t* __restrict__ digit_partials) {
   using K = typename KeyTraits<KK>::K;
+  constexpr int V = 16 / sizeof(K);  // keys per 16-byte load
   __shared__ uint32_t h[HIST_LARGE_WORDS];
   __shared__ uint32_t dh[DIG ? 8 * 256 : 1];
   for (int i = threadIdx.x; i < HIST_LARGE_WORDS; i += HIST_LARGE_THREADS) h[i] = 0;
   if constexpr (DIG)
     for (int i = threadIdx.x; i < 8 * 256; i += HIST_LARGE_THREADS) dh[i] = 0;
   __syncthreads();
-  const uint64_t tid = (uint64_t)blockIdx.x * HIST_LARGE_THREADS + threadIdx.x;
-  for_each_key<K, 2>(keys, n, tid, (uint64_t)gridDim.x * HIST_LARGE_THREADS, [&](K b) {
-    const K off = map_key<KK>(b) - kmin;
-    const uint32_t bin = (uint32_t)(off >> shift);
+
+  // Adds c to bin `bin` of the packed counters and repairs a 16-bit wrap.
+  auto add_packed = [&](uint32_t bin, uint32_t c) {
     const uint32_t hi = bin & 1u;
-    const uint32_t old = atomicAdd(&h[bin >> 1], hi ? 0x10000u : 1u);
+    const uint32_t old = atomicAdd(&h[bin >> 1], hi ? (c << 16) : c);
     if (hi) {
-      if ((old >> 16) == 0xFFFFu) add_agent(&corr[bin], 65536u);
-    } else if ((old & 0xFFFFu) == 0xFFFFu) {
+      if ((old >> 16) + c > 0xFFFFu) add_agent(&corr[bin], 65536u);
+    } else if ((old & 0xFFFFu) + c > 0xFFFFu) {
       add_agent(&corr[bin], 65536u);
-      add_agent(&corr[bin + 1], old == 0xFFFFFFFFu ? 65535u : 0xFFFFFFFFu);
+      add_agent(&corr[bin + 1], (old >> 16) == 0xFFFFu ? 65535u : 0xFFFFFFFFu);
+    }
+  };
+
+  const uint64_t nthreads = (uint64_t)gridDim.x * HIST_LARGE_THREADS;
+  const uint64_t tid = (uint64_t)blockIdx.x * HIST_LARGE_THREADS + threadIdx.x;
+  for_each_group<K, 4>(keys, n, tid, nthreads, [&](const K (&kb)[V], int m) {
+    K off[V];
+    uint32_t bins[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      off[i] = map_key<KK>(kb[i]) - kmin;
+      bins[i] = (uint32_t)(off[i] >> shift);
+    }
+    bool same = true;
+#pragma unroll
+    for (int i = 1; i < V; ++i)
+      if (i < m) same &= bins[i] == bins[0];
+    const uint32_t b0 = __builtin_amdgcn_readfirstlane(bins[0]);
+    const uint64_t active = __ballot(1);
+    if (__ballot(same && bins[0] == b0 && m == V) == active) {
+      if (mbcnt(active) == 0) add_packed(b0, (uint32_t)popc64(active) * V);
+    } else {
+      // independent returning atomics first, overflow checks after
+      uint32_t olds[V];
+#pragma unroll
+      for (int i = 0; i < V; ++i)
+        if (i < m) olds[i] = atomicAdd(&h[bins[i] >> 1], (bins[i] & 1u) ? 0x10000u : 1u);
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        if (i >= m) continue;
+        const uint32_t bin = bins[i], old = olds[i];
+        if (bin & 1u) {
+          if ((old >> 16) == 0xFFFFu) add_agent(&corr[bin], 65536u);
+        } else if ((old & 0xFFFFu) == 0xFFFFu) {
+          add_agent(&corr[bin], 65536u);
+          add_agent(&corr[bin + 1], old == 0xFFFFFFFFu ? 65535u : 0xFFFFFFFFu);
+        }
+      }
     }
     if constexpr (DIG) {
-      for (int p = 0; p < ndig; ++p) atomicAdd(&dh[p * 256 + (uint32_t)((off >> (8 * p)) & 255u)], 1u);
+      for (int p = 0; p < ndig; ++p) {
+        uint32_t dg[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) dg[i] = (uint32_t)((off[i] >> (8 * p)) & 255u);
+        lds_count_group<V>(dh + p * 256, dg, m);
+      }
     }
   });
   __syncthreads();
@@ -339,9 +454,17 @@ __global__ __launch_bounds__(DIGIT_HIST_THREADS) void k_digit_hist(const typenam
   for (int i = threadIdx.x; i < 8 * 256; i += DIGIT_HIST_THREADS) dh[i] = 0;
   __syncthreads();
   const uint64_t tid = (uint64_t)blockIdx.x * DIGIT_HIST_THREADS + threadIdx.x;
-  for_each_key<K, 4>(keys, n, tid, (uint64_t)gridDim.x * DIGIT_HIST_THREADS, [&](K b) {
-    const K off = map_key<KK>(b) - kmin;
-    for (int p = 0; p < ndig; ++p) atomicAdd(&dh[p * 256 + (uint32_t)((off >> (8 * p)) & 255u)], 1u);
+  constexpr int V = 16 / sizeof(K);
+  for_each_group<K, 4>(keys, n, tid, (uint64_t)gridDim.x * DIGIT_HIST_THREADS, [&](const K (&kb)[V], int m) {
+    K off[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) off[i] = map_key<KK>(kb[i]) - kmin;
+    for (int p = 0; p < ndig; ++p) {
+      uint32_t dg[V];
+#pragma unroll
+      for (int i = 0; i < V; ++i) dg[i] = (uint32_t)((off[i] >> (8 * p)) & 255u);
+      lds_count_group<V>(dh + p * 256, dg, m);
+    }
   });
   __syncthreads();
   uint32_t* out = digit_partials + (size_t)blockIdx.x * ndig * 256;

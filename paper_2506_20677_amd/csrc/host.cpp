@@ -55,10 +55,11 @@ hipEvent_t ahs_context::take_event() {
   return e;
 }
 
-void ahs_context::prof_begin(const char* name, hipStream_t s) {
+void ahs_context::prof_begin(const char* name, hipStream_t s, double bytes) {
   if (!profiling) return;
   Rec r;
   r.name = name;
+  r.bytes = bytes;
   r.a = take_event();
   r.b = take_event();
   hipEventRecord(r.a, s);
@@ -76,8 +77,9 @@ void ahs_context::prof_collect() {
     float ms = 0.f;
     hipEventElapsedTime(&ms, r.a, r.b);
     auto& t = totals[r.name];
-    t.first += 1;
-    t.second += ms;
+    t.launches += 1;
+    t.ms += ms;
+    t.bytes += r.bytes;
     event_pool.push_back(r.a);
     event_pool.push_back(r.b);
   }
@@ -156,12 +158,15 @@ extern "C" ahs_status ahs_profile_reset(ahs_context* ctx) {
   return AHS_OK;
 }
 
-extern "C" ahs_status ahs_profile_query(ahs_context* ctx, const char* kernel, uint64_t* launches, double* total_ms) {
+extern "C" ahs_status ahs_profile_query(ahs_context* ctx, const char* kernel, uint64_t* launches, double* total_ms,
+                                        double* algo_bytes) {
   if (!ctx || !kernel) return AHS_E_INVALID_ARG;
   ctx->prof_collect();
   auto it = ctx->totals.find(kernel);
-  if (launches) *launches = it == ctx->totals.end() ? 0 : it->second.first;
-  if (total_ms) *total_ms = it == ctx->totals.end() ? 0.0 : it->second.second;
+  const bool none = it == ctx->totals.end();
+  if (launches) *launches = none ? 0 : it->second.launches;
+  if (total_ms) *total_ms = none ? 0.0 : it->second.ms;
+  if (algo_bytes) *algo_bytes = none ? 0.0 : it->second.bytes;
   return AHS_OK;
 }
 
@@ -171,8 +176,8 @@ extern "C" size_t ahs_profile_dump(ahs_context* ctx, char* buf, size_t len) {
   std::string s;
   char line[256];
   for (auto& kv : ctx->totals) {
-    snprintf(line, sizeof line, "%s %llu %.6f\n", kv.first.c_str(), (unsigned long long)kv.second.first,
-             kv.second.second);
+    snprintf(line, sizeof line, "%s %llu %.6f %.0f\n", kv.first.c_str(), (unsigned long long)kv.second.launches,
+             kv.second.ms, kv.second.bytes);
     s += line;
   }
   if (buf && len) {

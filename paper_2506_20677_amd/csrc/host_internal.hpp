@@ -27,18 +27,23 @@ struct ahs_context {
   // per-kernel event timing
   struct Rec {
     std::string name;
+    double bytes = 0.0;  // algorithmic HBM bytes of the launch
     hipEvent_t a = nullptr, b = nullptr;
+  };
+  struct Total {
+    uint64_t launches = 0;
+    double ms = 0.0, bytes = 0.0;
   };
   bool profiling = false;
   std::vector<Rec> pending;
   std::vector<hipEvent_t> event_pool;
-  std::map<std::string, std::pair<uint64_t, double>> totals;
+  std::map<std::string, Total> totals;
 
   ~ahs_context();
   ahs_status fail(ahs_status s, const char* fmt, ...);
   ahs_status check(hipError_t e, const char* what);
   hipEvent_t take_event();
-  void prof_begin(const char* name, hipStream_t s);
+  void prof_begin(const char* name, hipStream_t s, double bytes);
   void prof_end(hipStream_t s);
   void prof_collect();
 };
@@ -110,7 +115,9 @@ inline T* at(void* ws, size_t off) {
 struct ProfScope {
   ahs_context* c;
   hipStream_t s;
-  ProfScope(ahs_context* c_, const char* name, hipStream_t s_) : c(c_), s(s_) { c->prof_begin(name, s); }
+  ProfScope(ahs_context* c_, const char* name, hipStream_t s_, double bytes = 0.0) : c(c_), s(s_) {
+    c->prof_begin(name, s, bytes);
+  }
   ~ProfScope() { c->prof_end(s); }
 };
 

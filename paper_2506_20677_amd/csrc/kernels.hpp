@@ -44,13 +44,9 @@ constexpr int OS_WAVES = OS_THREADS / 64;
 inline int os_items(int key_bytes) { return key_bytes == 4 ? 16 : 8; }
 inline int os_tile(int key_bytes) { return OS_THREADS * os_items(key_bytes); }
 
-// Look-back status word: bits 63..62 flag (1 aggregate, 2 inclusive),
-// bits 61..56 epoch (pass number within one call, 1..63), 55..0 value.
-constexpr uint64_t ST_AGG = 1ull << 62;
-constexpr uint64_t ST_INC = 2ull << 62;
-constexpr uint64_t ST_FLAG_MASK = 3ull << 62;
-constexpr int ST_EPOCH_SHIFT = 56;
-constexpr uint64_t ST_VALUE_MASK = (1ull << 56) - 1;
+// Look-back status words are 32-bit below this many keys, 64-bit above.
+constexpr uint64_t STATUS32_MAX_N = 1ull << 30;
+inline size_t status_word_bytes(uint64_t n) { return n < STATUS32_MAX_N ? 4 : 8; }
 
 // ---------------------------------------------------------------- features
 hipError_t launch_minmax(int kk, const void* keys, uint64_t n, MinMaxPartial* partials, int nblocks,
@@ -90,9 +86,8 @@ struct OnesweepArgs {
   uint32_t digit_shift;   // digit = ((key - kmin) >> digit_shift) & 255
   uint32_t map_in;        // keys in src are raw (apply the float map)
   uint32_t unmap_out;     // write raw keys to dst (apply the inverse map)
-  uint32_t epoch;         // 1..63
   const uint32_t* digit_offsets;  // [256] global exclusive offsets of this pass
-  uint64_t* status;       // [tiles][256]
+  void* status;           // [tiles][256] words of status_word_bytes(n), zero before the launch
   uint32_t* tile_counter; // zero before the launch
 };
 hipError_t launch_onesweep(int kk, int with_vals, const OnesweepArgs& a, hipStream_t s);

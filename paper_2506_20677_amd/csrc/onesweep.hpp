@@ -21,35 +21,44 @@
 
 namespace ahs {
 
+// One LDS slot per (wave, digit): the peer mask of the item being ranked
+// and the wave's running count of the digit, read back with one 16-byte
+// load.
+struct __align__(16) RankSlot {
+  uint64_t mask;
+  uint32_t count;
+  uint32_t pad;
+};
+
 template <int IPT>
 __device__ __forceinline__ void rank_wave_items(const uint32_t (&d)[IPT], uint32_t (&r)[IPT],
-                                                uint64_t* __restrict__ wmask /* [256] of this wave */,
-                                                uint32_t* __restrict__ whist /* [256] of this wave */) {
+                                                RankSlot* __restrict__ slots /* [ND] of this wave */) {
   const int lane = lane_id();
   const uint64_t mybit = 1ull << lane;
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
     const uint32_t di = d[i];
     const uint32_t d0 = __builtin_amdgcn_readfirstlane(di);
-    const uint64_t same = __ballot(di == d0);
-    uint64_t peers;
-    const bool uniform = (same == ~0ull);
-    if (uniform) {
-      peers = ~0ull;
+    if (__ballot(di == d0) == ~0ull) {
+      // the whole wave shares one digit
+      const uint32_t base = slots[d0].count;
+      __builtin_amdgcn_wave_barrier();
+      r[i] = base + (uint32_t)lane;
+      if (lane == WAVE - 1) slots[d0].count = base + WAVE;
     } else {
-      __hip_atomic_fetch_or(&wmask[di], mybit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_fetch_or(&slots[di].mask, mybit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       __builtin_amdgcn_wave_barrier();
-      peers = __hip_atomic_load(&wmask[di], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      const u32x4 sv = *reinterpret_cast<const volatile u32x4*>(&slots[di]);
       __builtin_amdgcn_wave_barrier();
-    }
-    const uint32_t lt = mbcnt(peers);
-    const uint32_t cnt = popc64(peers);
-    const uint32_t base = whist[di];
-    __builtin_amdgcn_wave_barrier();
-    r[i] = base + lt;
-    if (lt == cnt - 1) {
-      whist[di] = base + cnt;
-      if (!uniform) wmask[di] = 0ull;
+      const uint64_t peers = (uint64_t)sv.x | ((uint64_t)sv.y << 32);
+      const uint32_t base = sv.z;
+      const uint32_t lt = mbcnt(peers);
+      const uint32_t cnt = popc64(peers);
+      r[i] = base + lt;
+      if (lt == cnt - 1) {
+        const u32x4 nv = {0u, 0u, base + cnt, 0u};
+        *reinterpret_cast<volatile u32x4*>(&slots[di]) = nv;
+      }
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -59,19 +68,31 @@ __device__ __forceinline__ void rank_wave_items(const uint32_t (&d)[IPT], uint32
 // turn the per-wave counts of digit t into per-wave exclusive prefixes
 // (in place) and return the tile's count of digit t (0 for t >= ND).
 template <int NW, int ND = 256>
-__device__ __forceinline__ uint32_t wave_prefix_per_digit(uint32_t (*whist)[ND]) {
+__device__ __forceinline__ uint32_t wave_prefix_per_digit(RankSlot (*slots)[ND]) {
   const int t = threadIdx.x;
   uint32_t run = 0;
   if (t < ND) {
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
-      const uint32_t c = whist[w][t];
-      whist[w][t] = run;
+      const uint32_t c = slots[w][t].count;
+      slots[w][t].count = run;
       run += c;
     }
   }
   return run;
 }
+
+// Look-back status words.  32-bit words (flag in bits 31..30, value in
+// 29..0) serve every array below 2^30 keys and halve the look-back traffic;
+// 64-bit words (flag 63..62, value 55..0) serve the rest.  Status arrays are
+// cleared before every pass, so a zero flag means "not published".
+template <typename ST> struct Status;
+template <> struct Status<uint32_t> {
+  static constexpr uint32_t AGG = 1u << 30, INC = 2u << 30, FLAGS = 3u << 30, VAL = (1u << 30) - 1;
+};
+template <> struct Status<uint64_t> {
+  static constexpr uint64_t AGG = 1ull << 62, INC = 2ull << 62, FLAGS = 3ull << 62, VAL = (1ull << 56) - 1;
+};
 
 // Decoupled look-back over tiles for digit t (called by threads t < ND).
 // Publishes the tile aggregate, walks back to the nearest inclusive prefix
@@ -79,30 +100,123 @@ __device__ __forceinline__ uint32_t wave_prefix_per_digit(uint32_t (*whist)[ND])
 // prefix of this tile for digit t.  The chain starts at first_tile (the
 // first tile of the tile's segment).  Tiles are numbered in launch order
 // from an atomic counter, so every predecessor is resident and progresses.
-template <int ND = 256>
-__device__ __forceinline__ uint64_t lookback(uint64_t* __restrict__ status, uint32_t tile, uint32_t first_tile,
-                                             uint32_t t, uint64_t count, uint32_t epoch) {
-  const uint64_t ep = (uint64_t)epoch << ST_EPOCH_SHIFT;
-  uint64_t* mine = status + (uint64_t)tile * ND + t;
+//
+// The walk first reads the direct predecessor alone (usually enough once
+// the pass is running); if that one only holds an aggregate it reads the
+// next LB_WIDTH predecessors with independent loads per round, so the
+// inclusive frontier is not limited to one tile per load latency.
+constexpr int LB_WIDTH = 8;
+
+template <int ND, typename ST>
+__device__ __forceinline__ uint64_t lookback(ST* __restrict__ status, uint32_t tile, uint32_t first_tile,
+                                             uint32_t t, uint64_t count) {
+  using S = Status<ST>;
+  ST* mine = status + (uint64_t)tile * ND + t;
   if (tile == first_tile) {
-    st_agent(mine, ST_INC | ep | count);
+    st_agent(mine, (ST)(S::INC | (ST)count));
     return 0;
   }
-  st_agent(mine, ST_AGG | ep | count);
+  st_agent(mine, (ST)(S::AGG | (ST)count));
   uint64_t excl = 0;
-  int64_t j = (int64_t)tile - 1;
+  int64_t j = (int64_t)tile - 1;  // next predecessor not yet accounted for
+  // direct predecessor
   for (;;) {
-    const uint64_t s = ld_agent(status + (uint64_t)j * ND + t);
-    const uint64_t flag = s & ST_FLAG_MASK;
-    if (flag == 0 || ((s >> ST_EPOCH_SHIFT) & 63u) != epoch) {
+    const ST s = ld_agent(status + (uint64_t)j * ND + t);
+    if ((s & S::FLAGS) == 0) {
       __builtin_amdgcn_s_sleep(1);
       continue;
     }
-    excl += s & ST_VALUE_MASK;
-    if (flag == ST_INC) break;
+    excl += s & S::VAL;
+    if ((s & S::FLAGS) == S::INC) {
+      st_agent(mine, (ST)(S::INC | (ST)(excl + count)));
+      return excl;
+    }
     --j;
+    break;
   }
-  st_agent(mine, ST_INC | ep | (excl + count));
+  for (;;) {
+    ST s[LB_WIDTH];
+#pragma unroll
+    for (int q = 0; q < LB_WIDTH; ++q)
+      s[q] = (j - q >= (int64_t)first_tile) ? ld_agent(status + (uint64_t)(j - q) * ND + t) : (ST)0;
+    int q = 0;
+    bool done = false;
+    for (; q < LB_WIDTH && j - q >= (int64_t)first_tile; ++q) {
+      const ST flag = s[q] & S::FLAGS;
+      if (flag == 0) break;  // not published yet: re-read from here
+      excl += s[q] & S::VAL;
+      if (flag == S::INC) {
+        done = true;
+        break;
+      }
+    }
+    if (done) break;
+    if (q == 0) __builtin_amdgcn_s_sleep(1);
+    j -= q;
+  }
+  st_agent(mine, (ST)(S::INC | (ST)(excl + count)));
+  return excl;
+}
+
+
+// Split form of lookback() for overlapping the first status read with other
+// work: lookback_begin publishes the aggregate and issues the read of the
+// direct predecessor; lookback_end consumes it, walks further if needed and
+// publishes the inclusive prefix.
+template <int ND, typename ST>
+__device__ __forceinline__ ST lookback_begin(ST* __restrict__ status, uint32_t tile, uint32_t first_tile, uint32_t t,
+                                             uint64_t count) {
+  using S = Status<ST>;
+  ST* mine = status + (uint64_t)tile * ND + t;
+  if (tile == first_tile) {
+    st_agent(mine, (ST)(S::INC | (ST)count));
+    return (ST)0;
+  }
+  st_agent(mine, (ST)(S::AGG | (ST)count));
+  return ld_agent(status + (uint64_t)(tile - 1) * ND + t);
+}
+
+template <int ND, typename ST>
+__device__ __forceinline__ uint64_t lookback_end(ST* __restrict__ status, uint32_t tile, uint32_t first_tile,
+                                                 uint32_t t, uint64_t count, ST first_read) {
+  using S = Status<ST>;
+  if (tile == first_tile) return 0;
+  ST* mine = status + (uint64_t)tile * ND + t;
+  uint64_t excl = 0;
+  int64_t j = (int64_t)tile - 1;
+  ST s0 = first_read;
+  for (;;) {
+    if ((s0 & S::FLAGS) != 0) break;
+    __builtin_amdgcn_s_sleep(1);
+    s0 = ld_agent(status + (uint64_t)j * ND + t);
+  }
+  excl += s0 & S::VAL;
+  if ((s0 & S::FLAGS) == S::INC) {
+    st_agent(mine, (ST)(S::INC | (ST)(excl + count)));
+    return excl;
+  }
+  --j;
+  for (;;) {
+    ST s[LB_WIDTH];
+#pragma unroll
+    for (int q = 0; q < LB_WIDTH; ++q)
+      s[q] = (j - q >= (int64_t)first_tile) ? ld_agent(status + (uint64_t)(j - q) * ND + t) : (ST)0;
+    int q = 0;
+    bool done = false;
+    for (; q < LB_WIDTH && j - q >= (int64_t)first_tile; ++q) {
+      const ST flag = s[q] & S::FLAGS;
+      if (flag == 0) break;
+      excl += s[q] & S::VAL;
+      if (flag == S::INC) {
+        done = true;
+        break;
+      }
+    }
+    if (done) break;
+    if (q == 0) __builtin_amdgcn_s_sleep(1);
+    j -= q;
+  }
+  st_agent(mine, (ST)(S::INC | (ST)(excl + count)));
   return excl;
 }
 

@@ -8,87 +8,105 @@
 
 namespace ahs {
 
-template <int KK, bool PAY, int IPT>
+template <int KK, bool PAY, int IPT, typename ST>
 __global__ __launch_bounds__(OS_THREADS) void k_onesweep(OnesweepArgs a) {
   using K = typename KeyTraits<KK>::K;
   constexpr int TILE = OS_THREADS * IPT;
   constexpr int NW = OS_WAVES;
-  __shared__ uint64_t s_mask[NW][256];
-  __shared__ uint32_t s_whist[NW][256];
+  // The rank slots are only live until every key's local position is in a
+  // register, the key staging only after that, so they share LDS.
+  constexpr size_t SLOT_BYTES = sizeof(RankSlot) * NW * 256;
+  constexpr size_t KEY_BYTES = sizeof(K) * TILE;
+  __shared__ __align__(16) unsigned char s_raw[SLOT_BYTES > KEY_BYTES ? SLOT_BYTES : KEY_BYTES];
+  RankSlot(*s_slot)[256] = reinterpret_cast<RankSlot(*)[256]>(s_raw);
+  K* s_keys = reinterpret_cast<K*>(s_raw);
   __shared__ uint32_t s_tstart[256];
   __shared__ uint32_t s_dbase[256];
-  __shared__ K s_keys[TILE];
   __shared__ uint32_t s_vals[PAY ? TILE : 1];
-  __shared__ uint8_t s_dig[TILE];
   __shared__ uint32_t s_scan[NW + 1];
   __shared__ uint32_t s_tile;
 
   const int t = threadIdx.x, w = t / WAVE, lane = lane_id();
   for (int i = t; i < NW * 256; i += OS_THREADS) {
-    (&s_mask[0][0])[i] = 0ull;
-    (&s_whist[0][0])[i] = 0u;
+    (&s_slot[0][0])[i].mask = 0ull;
+    (&s_slot[0][0])[i].count = 0u;
   }
   if (t == 0) s_tile = add_agent(a.tile_counter, 1u);
+  const uint32_t doff = t < 256 ? a.digit_offsets[t] : 0u;  // in flight early
   __syncthreads();
   const uint32_t tile = s_tile;
   const uint64_t tbase = (uint64_t)tile * TILE;
   const uint64_t wbase = tbase + (uint64_t)w * WAVE * IPT;
   const K* __restrict__ src = (const K*)a.src;
   const K kmin = (K)a.kmin;
+  const uint32_t shift = a.digit_shift;
+  const uint64_t last = a.n - 1;
+  auto digit = [&](K x) { return (uint32_t)(((x - kmin) >> shift) & 255u); };
 
+  // all loads in flight first (indices clamped); padding keys become the
+  // largest key, which sorts last under digit 255 and is never written
   K k[IPT];
   uint32_t v[IPT];
-  uint32_t d[IPT];
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
     const uint64_t idx = wbase + (uint64_t)i * WAVE + lane;
-    if (idx < a.n) {
-      K x = src[idx];
-      if constexpr (KeyTraits<KK>::FLT) x = a.map_in ? fmap(x) : x;
-      k[i] = x;
-      if constexpr (PAY) v[i] = a.vsrc[idx];
-      d[i] = (uint32_t)(((x - kmin) >> a.digit_shift) & 255u);
-    } else {
-      k[i] = ~K(0);
-      if constexpr (PAY) v[i] = 0;
-      d[i] = 255u;
-    }
+    k[i] = src[idx < a.n ? idx : last];
+    if constexpr (PAY) v[i] = a.vsrc[idx < a.n ? idx : last];
+  }
+  const bool full = tbase + TILE <= a.n;
+#pragma unroll
+  for (int i = 0; i < IPT; ++i) {
+    if constexpr (KeyTraits<KK>::FLT) k[i] = a.map_in ? fmap(k[i]) : k[i];
+    if (!full && wbase + (uint64_t)i * WAVE + lane >= a.n) k[i] = kmin + (K)(255ull << shift);
   }
 
   uint32_t r[IPT];
-  rank_wave_items<IPT>(d, r, s_mask[w], s_whist[w]);
-  __syncthreads();
-
-  uint32_t cnt = wave_prefix_per_digit<NW>(s_whist);
-  const uint64_t valid64 = a.n - tbase < (uint64_t)TILE ? a.n - tbase : (uint64_t)TILE;
-  const uint32_t valid = (uint32_t)valid64;
-  if (t == 255) cnt -= (uint32_t)TILE - valid;  // padding sorted last under digit 255
-  uint32_t total;
-  const uint32_t tstart = block_excl_scan<OS_THREADS>(t < 256 ? cnt : 0u, s_scan, total);
-  if (t < 256) {
-    s_tstart[t] = tstart;
-    const uint64_t excl = lookback(a.status, tile, 0u, (uint32_t)t, cnt, a.epoch);
-    s_dbase[t] = a.digit_offsets[t] + (uint32_t)excl;
+  {
+    uint32_t d[IPT];
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) d[i] = digit(k[i]);
+    rank_wave_items<IPT>(d, r, s_slot[w]);
   }
   __syncthreads();
 
+  uint32_t cnt = wave_prefix_per_digit<NW>(s_slot);
+  const uint64_t valid64 = a.n - tbase < (uint64_t)TILE ? a.n - tbase : (uint64_t)TILE;
+  const uint32_t valid = (uint32_t)valid64;
+  if (t == 255) cnt -= (uint32_t)TILE - valid;
+  uint32_t total;
+  const uint32_t tstart = block_excl_scan<OS_THREADS>(t < 256 ? cnt : 0u, s_scan, total);
+  ST pred = 0;
+  if (t < 256) {
+    s_tstart[t] = tstart;
+    pred = lookback_begin<256, ST>((ST*)a.status, tile, 0u, (uint32_t)t, cnt);
+  }
+  __syncthreads();
+  // stage keys in digit order while the predecessor's status is in flight
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
-    const uint32_t lp = s_tstart[d[i]] + s_whist[w][d[i]] + r[i];
-    if (lp < (uint32_t)TILE) {
-      s_keys[lp] = k[i];
-      if constexpr (PAY) s_vals[lp] = v[i];
-      s_dig[lp] = (uint8_t)d[i];
+    const uint32_t di = digit(k[i]);
+    r[i] += s_tstart[di] + s_slot[w][di].count;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < IPT; ++i) {
+    if (r[i] < (uint32_t)TILE) {
+      s_keys[r[i]] = k[i];
+      if constexpr (PAY) s_vals[r[i]] = v[i];
     }
+  }
+  if (t < 256) {
+    const uint64_t excl = lookback_end<256, ST>((ST*)a.status, tile, 0u, (uint32_t)t, cnt, pred);
+    s_dbase[t] = doff + (uint32_t)excl;
   }
   __syncthreads();
 
   K* __restrict__ dst = (K*)a.dst;
   for (uint32_t j = t; j < valid; j += OS_THREADS) {
-    const uint32_t dj = s_dig[j];
+    K x = s_keys[j];
+    const uint32_t dj = digit(x);
     const uint32_t o = s_dbase[dj] + (j - s_tstart[dj]);
     if (o >= a.n) continue;  // unreachable with consistent digit counts
-    K x = s_keys[j];
     if constexpr (KeyTraits<KK>::FLT) x = a.unmap_out ? funmap(x) : x;
     dst[o] = x;
     if constexpr (PAY) a.vdst[o] = s_vals[j];
@@ -100,7 +118,10 @@ static hipError_t onesweep_kk(const OnesweepArgs& a, hipStream_t s) {
   constexpr int IPT = sizeof(typename KeyTraits<KK>::K) == 4 ? 16 : 8;
   constexpr int TILE = OS_THREADS * IPT;
   const uint64_t tiles = (a.n + TILE - 1) / TILE;
-  k_onesweep<KK, PAY, IPT><<<(unsigned)tiles, OS_THREADS, 0, s>>>(a);
+  if (a.n < STATUS32_MAX_N)
+    k_onesweep<KK, PAY, IPT, uint32_t><<<(unsigned)tiles, OS_THREADS, 0, s>>>(a);
+  else
+    k_onesweep<KK, PAY, IPT, uint64_t><<<(unsigned)tiles, OS_THREADS, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -114,6 +114,7 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_count(const typename KeyTrait
   for (uint32_t tile = t0; tile < t1; ++tile) {
     const uint32_t sidx = ss_seg_of_tile(segs, nsegs, tile);
     if ((int64_t)sidx != cur) {
+      __syncthreads();  // every thread has finished counting the previous tile
       if (cur >= 0) {
         for (int b = t; b < SS_NB; b += SS_THREADS)
           if (s_cnt[b]) add_agent(&counts[(size_t)cur * SS_NB + b], s_cnt[b]);
@@ -163,6 +164,7 @@ __global__ __launch_bounds__(SS_NB) void k_ss_plan(const SsSeg* __restrict__ seg
   if (b & 1) {
     if (dst_buf == SS_BUF_OUT && !copy_in_place) return;
     const uint32_t nchunks = (c + SS_CAP - 1) / SS_CAP;
+    atomicAdd(&ctr->item_keys, c);
     const uint32_t at = atomicAdd(&ctr->nitems, nchunks);
     for (uint32_t q = 0; q < nchunks; ++q) {
       if (at + q >= item_cap) { atomicOr(&ctr->overflow, 1u); break; }
@@ -173,6 +175,7 @@ __global__ __launch_bounds__(SS_NB) void k_ss_plan(const SsSeg* __restrict__ seg
       items[at + q] = it;
     }
   } else if (c <= SS_CAP) {
+    atomicAdd(&ctr->item_keys, c);
     const uint32_t at = atomicAdd(&ctr->nitems, 1u);
     if (at >= item_cap) { atomicOr(&ctr->overflow, 1u); return; }
     SsItem it;
@@ -181,6 +184,7 @@ __global__ __launch_bounds__(SS_NB) void k_ss_plan(const SsSeg* __restrict__ seg
     it.flags = dst_buf << 8;
     items[at] = it;
   } else {
+    atomicAdd(&ctr->seg_keys_next, c);
     const uint32_t at = atomicAdd(&ctr->nsegs_next, 1u);
     if (at >= seg_cap) { atomicOr(&ctr->overflow, 2u); return; }
     SsSeg ns;
@@ -219,17 +223,19 @@ __global__ __launch_bounds__(SS_TILES_THREADS) void k_ss_tiles(SsSeg* __restrict
 // Segmented single-pass stable scatter by bucket id (512 ids): the onesweep
 // tile machinery with the splitter classifier as the digit, a look-back
 // chain per segment and per-segment bucket offsets.
-template <int KK, bool PAY, int IPT>
+template <int KK, bool PAY, int IPT, typename ST>
 __global__ __launch_bounds__(SS_THREADS) void k_ss_scatter(SsScatterArgs a) {
   using K = typename KeyTraits<KK>::K;
   constexpr int TILE = SS_THREADS * IPT;
   constexpr int NW = SS_THREADS / WAVE;
-  __shared__ uint64_t s_mask[NW][SS_NB];
-  __shared__ uint32_t s_whist[NW][SS_NB];
+  constexpr size_t SLOT_BYTES = sizeof(RankSlot) * NW * SS_NB;
+  constexpr size_t KEY_BYTES = sizeof(K) * TILE;
+  __shared__ __align__(16) unsigned char s_raw[SLOT_BYTES > KEY_BYTES ? SLOT_BYTES : KEY_BYTES];
+  RankSlot(*s_slot)[SS_NB] = reinterpret_cast<RankSlot(*)[SS_NB]>(s_raw);
+  K* s_keys = reinterpret_cast<K*>(s_raw);
   __shared__ uint32_t s_tstart[SS_NB];
   __shared__ uint32_t s_dbase[SS_NB];
   __shared__ K s_spl[256];
-  __shared__ K s_keys[TILE];
   __shared__ uint32_t s_vals[PAY ? TILE : 1];
   __shared__ uint16_t s_dig[TILE];
   __shared__ uint32_t s_scan[NW + 1];
@@ -237,8 +243,8 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_scatter(SsScatterArgs a) {
 
   const int t = threadIdx.x, w = t / WAVE, lane = lane_id();
   for (int i = t; i < NW * SS_NB; i += SS_THREADS) {
-    (&s_mask[0][0])[i] = 0ull;
-    (&s_whist[0][0])[i] = 0u;
+    (&s_slot[0][0])[i].mask = 0ull;
+    (&s_slot[0][0])[i].count = 0u;
   }
   if (t == 0) s_tile = add_agent(a.tile_counter, 1u);
   __syncthreads();
@@ -250,7 +256,7 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_scatter(SsScatterArgs a) {
   const uint64_t rem = (uint64_t)sg.size - off;
   const uint32_t valid = rem < (uint64_t)TILE ? (uint32_t)rem : (uint32_t)TILE;
   const K* __restrict__ src = (const K*)a.src + sg.start + off;
-  __syncthreads();
+  const uint32_t* __restrict__ vsrc = PAY ? a.vsrc + sg.start + off : nullptr;
 
   K k[IPT];
   uint32_t v[IPT];
@@ -259,39 +265,45 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_scatter(SsScatterArgs a) {
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
     const uint32_t idx = wbase + (uint32_t)i * WAVE + lane;
+    k[i] = src[idx < valid ? idx : valid - 1];
+    if constexpr (PAY) v[i] = vsrc[idx < valid ? idx : valid - 1];
+  }
+  __syncthreads();  // splitters in LDS
+#pragma unroll
+  for (int i = 0; i < IPT; ++i) {
+    const uint32_t idx = wbase + (uint32_t)i * WAVE + lane;
+    K x = k[i];
+    if constexpr (KeyTraits<KK>::FLT) x = a.map_in ? fmap(x) : x;
     if (idx < valid) {
-      K x = src[idx];
-      if constexpr (KeyTraits<KK>::FLT) x = a.map_in ? fmap(x) : x;
       k[i] = x;
-      if constexpr (PAY) v[i] = a.vsrc[sg.start + off + idx];
       d[i] = ss_classify<K>(x, s_spl);
     } else {
       k[i] = ~K(0);
-      if constexpr (PAY) v[i] = 0;
       d[i] = SS_NB - 1;
     }
   }
 
   uint32_t r[IPT];
-  rank_wave_items<IPT>(d, r, s_mask[w], s_whist[w]);
+  rank_wave_items<IPT>(d, r, s_slot[w]);
   __syncthreads();
 
-  uint32_t cnt = wave_prefix_per_digit<NW, SS_NB>(s_whist);
+  uint32_t cnt = wave_prefix_per_digit<NW, SS_NB>(s_slot);
   if (t == SS_NB - 1) cnt -= (uint32_t)TILE - valid;  // padding: last id, sorted last
   uint32_t total;
   const uint32_t tstart = block_excl_scan<SS_THREADS>(cnt, s_scan, total);
   s_tstart[t] = tstart;
-  const uint64_t excl = lookback<SS_NB>(a.status, tile, sg.first_tile, (uint32_t)t, cnt, a.epoch);
+  const uint64_t excl = lookback<SS_NB, ST>((ST*)a.status, tile, sg.first_tile, (uint32_t)t, cnt);
   s_dbase[t] = a.offs[(size_t)sidx * SS_NB + t] + (uint32_t)excl;
   __syncthreads();
-
+#pragma unroll
+  for (int i = 0; i < IPT; ++i) r[i] += s_tstart[d[i]] + s_slot[w][d[i]].count;
+  __syncthreads();
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
-    const uint32_t lp = s_tstart[d[i]] + s_whist[w][d[i]] + r[i];
-    if (lp < (uint32_t)TILE) {
-      s_keys[lp] = k[i];
-      if constexpr (PAY) s_vals[lp] = v[i];
-      s_dig[lp] = (uint16_t)d[i];
+    if (r[i] < (uint32_t)TILE) {
+      s_keys[r[i]] = k[i];
+      if constexpr (PAY) s_vals[r[i]] = v[i];
+      s_dig[r[i]] = (uint16_t)d[i];
     }
   }
   __syncthreads();
@@ -316,8 +328,7 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_block(SsBlockArgs a) {
   using K = typename KeyTraits<KK>::K;
   constexpr int IPT = SS_CAP / SS_THREADS;
   constexpr int NW = SS_THREADS / WAVE;
-  __shared__ uint64_t s_mask[NW][256];
-  __shared__ uint32_t s_whist[NW][256];
+  __shared__ RankSlot s_slot[NW][256];
   __shared__ uint32_t s_tstart[256];
   __shared__ K s_keys[SS_CAP];
   __shared__ uint32_t s_vals[PAY ? SS_CAP : 1];
@@ -356,9 +367,7 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_block(SsBlockArgs a) {
   mn = wave_min(mn);
   mx = wave_max(mx);
   if (lane == 0) { s_red[0][w] = mn; s_red[1][w] = mx; }
-  for (int i = t; i < NW * 256; i += SS_THREADS) {
-    (&s_mask[0][0])[i] = 0ull;
-  }
+  for (int i = t; i < NW * 256; i += SS_THREADS) (&s_slot[0][0])[i].mask = 0ull;
   __syncthreads();
   mn = s_red[0][0];
   mx = s_red[1][0];
@@ -387,19 +396,19 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_block(SsBlockArgs a) {
         d[i] = 255u;
       }
     }
-    for (int i = t; i < NW * 256; i += SS_THREADS) (&s_whist[0][0])[i] = 0u;
+    for (int i = t; i < NW * 256; i += SS_THREADS) (&s_slot[0][0])[i].count = 0u;
     __syncthreads();
     uint32_t r[IPT];
-    rank_wave_items<IPT>(d, r, s_mask[w], s_whist[w]);
+    rank_wave_items<IPT>(d, r, s_slot[w]);
     __syncthreads();
-    const uint32_t cnt = wave_prefix_per_digit<NW>(s_whist);
+    const uint32_t cnt = wave_prefix_per_digit<NW>(s_slot);
     uint32_t total;
     const uint32_t tstart = block_excl_scan<SS_THREADS>(t < 256 ? cnt : 0u, s_scan, total);
     if (t < 256) s_tstart[t] = tstart;
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-      const uint32_t lp = s_tstart[d[i]] + s_whist[w][d[i]] + r[i];
+      const uint32_t lp = s_tstart[d[i]] + s_slot[w][d[i]].count + r[i];
       if (lp < (uint32_t)SS_CAP) {
         s_keys[lp] = k[i];
         if constexpr (PAY) s_vals[lp] = v[i];
@@ -462,7 +471,10 @@ hipError_t launch_ss_tiles(SsSeg* segs, SsCounters* ctr, uint32_t tile_keys, uin
 template <int KK, bool PAY>
 static hipError_t scatter_kk(const SsScatterArgs& a, uint32_t ntiles, hipStream_t s) {
   constexpr int IPT = sizeof(typename KeyTraits<KK>::K) == 4 ? 16 : 8;
-  k_ss_scatter<KK, PAY, IPT><<<ntiles, SS_THREADS, 0, s>>>(a);
+  if (a.n < STATUS32_MAX_N)
+    k_ss_scatter<KK, PAY, IPT, uint32_t><<<ntiles, SS_THREADS, 0, s>>>(a);
+  else
+    k_ss_scatter<KK, PAY, IPT, uint64_t><<<ntiles, SS_THREADS, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -32,6 +32,7 @@ struct SsItem {       // a finished bucket: sort in LDS, or copy
 };
 struct SsCounters {   // per level, written by the device, read by the host
   uint32_t nsegs_next, nitems, ntiles_next, overflow;
+  uint32_t item_keys, seg_keys_next, pad0, pad1;
 };
 
 struct SsScatterArgs {
@@ -44,9 +45,9 @@ struct SsScatterArgs {
   const SsSeg* segs;
   const void* spl;
   const uint32_t* offs;
-  uint64_t* status;
+  void* status;        // [tiles][SS_NB] words of status_word_bytes(n), zero before the launch
   uint32_t* tile_counter;
-  uint32_t epoch;
+  uint64_t n;          // total keys (selects the status word size)
 };
 
 struct SsBlockArgs {

@@ -63,7 +63,8 @@ ahs_status run_samplesort(SortJob& j) {
   uint32_t* offs = reinterpret_cast<uint32_t*>(base + S.offs);
   SsItem* items = reinterpret_cast<SsItem*>(base + S.items);
   SsCounters* ctr = reinterpret_cast<SsCounters*>(base + S.ctr);
-  uint64_t* status = reinterpret_cast<uint64_t*>(base + S.status);
+  void* status = base + S.status;
+  const size_t sw = status_word_bytes(j.n);
   uint32_t* tilectr = reinterpret_cast<uint32_t*>(base + S.tilectr);
   const bool flt = j.kk == KK_F32 || j.kk == KK_F64;
   const int pay = j.vin != nullptr;
@@ -78,12 +79,13 @@ ahs_status run_samplesort(SortJob& j) {
   ba.vtmp = pay ? at<uint32_t>(j.ws, j.L.tmpv) : nullptr;
 
   SS_HIP(launch_ss_init(segs[0], items, j.n, j.s), "sample sort init");
+  const double rec_bytes = 2.0 * j.key_bytes + (pay ? 8.0 : 0.0);  // read + write per key
   if (j.n <= (uint64_t)SS_CAP) {
-    ProfScope p(j.ctx, "ss_block_sort", j.s);
+    ProfScope p(j.ctx, "ss_block_sort", j.s, rec_bytes * j.n);
     SS_HIP(launch_ss_block(j.kk, pay, ba, 1, j.s), "block sort");
     return AHS_OK;
   }
-  SS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ctr), 4 * SS_MAX_LEVELS, 0u, j.s), "fill");
+  SS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ctr), sizeof(SsCounters) / 4 * SS_MAX_LEVELS, 0u, j.s), "fill");
   SS_HIP(launch_fill_u32(tilectr, SS_MAX_LEVELS, 0u, j.s), "fill");
 
   const void* bufs[3] = {j.kin, j.kout, at<void>(j.ws, j.L.tmpk)};
@@ -92,19 +94,20 @@ ahs_status run_samplesort(SortJob& j) {
   uint32_t nsegs = 1;
   uint32_t ntiles = (uint32_t)ceil_div(j.n, tile_keys);
   uint32_t src_buf = SS_BUF_IN;
+  uint64_t level_keys = j.n;
   int cur = 0;
   for (int level = 0; level < SS_MAX_LEVELS; ++level) {
     const uint32_t dst_buf = (level % 2 == 0) ? SS_BUF_TMP : SS_BUF_OUT;
     const int map_in = (flt && src_buf == SS_BUF_IN) ? 1 : 0;
     SS_HIP(launch_fill_u32(counts, (uint64_t)nsegs * SS_NB, 0u, j.s), "fill");
-    SS_HIP(launch_fill_u64(status, (uint64_t)ntiles * SS_NB, 0ull, j.s), "fill");
+    SS_HIP(launch_fill_u32(static_cast<uint32_t*>(status), (uint64_t)ntiles * SS_NB * sw / 4, 0u, j.s), "fill");
     {
       ProfScope p(j.ctx, "ss_sample", j.s);
       SS_HIP(launch_ss_sample(j.kk, bufs[src_buf], map_in, segs[cur], nsegs, spl, 0x5EEDull + (uint64_t)level, j.s),
              "sample");
     }
     {
-      ProfScope p(j.ctx, "ss_count", j.s);
+      ProfScope p(j.ctx, "ss_count", j.s, (double)j.key_bytes * level_keys);
       const int nb = (int)(ntiles < 2048u ? ntiles : 2048u);
       SS_HIP(launch_ss_count(j.kk, bufs[src_buf], map_in, segs[cur], nsegs, ntiles, spl, counts, nb, j.s), "count");
     }
@@ -123,9 +126,9 @@ ahs_status run_samplesort(SortJob& j) {
     sa.offs = offs;
     sa.status = status;
     sa.tile_counter = tilectr + level;
-    sa.epoch = 1;
+    sa.n = j.n;
     {
-      ProfScope p(j.ctx, "ss_scatter", j.s);
+      ProfScope p(j.ctx, "ss_scatter", j.s, rec_bytes * level_keys);
       SS_HIP(launch_ss_scatter(j.kk, pay, sa, ntiles, j.s), "scatter");
     }
     SS_HIP(launch_ss_tiles(segs[cur ^ 1], ctr + level, tile_keys, (uint32_t)S.seg_cap, j.s), "tiles");
@@ -135,12 +138,13 @@ ahs_status run_samplesort(SortJob& j) {
     memcpy(&c, j.ctx->pinned, sizeof c);
     if (c.overflow) return j.ctx->fail(AHS_E_DEVICE, "sample sort table overflow (%u)", c.overflow);
     if (c.nitems) {
-      ProfScope p(j.ctx, "ss_block_sort", j.s);
+      ProfScope p(j.ctx, "ss_block_sort", j.s, rec_bytes * c.item_keys);
       SS_HIP(launch_ss_block(j.kk, pay, ba, c.nitems, j.s), "block sort");
     }
     if (c.nsegs_next == 0) return AHS_OK;
     nsegs = c.nsegs_next;
     ntiles = c.ntiles_next;
+    level_keys = c.seg_keys_next;
     src_buf = dst_buf;
     cur ^= 1;
   }

@@ -31,7 +31,7 @@ static bool partial_overlap(const void* a, const void* b, size_t bytes) {
 static ahs_status step_minmax(SortJob& j) {
   DevFeatures* df = at<DevFeatures>(j.ws, j.L.df);
   {
-    ProfScope p(j.ctx, "minmax", j.s);
+    ProfScope p(j.ctx, "minmax", j.s, (double)j.key_bytes * j.n);
     AHS_HIP(j, launch_minmax(j.kk, j.kin, j.n, at<MinMaxPartial>(j.ws, j.L.mm), minmax_blocks(j.n), df, j.s),
             "minmax launch");
   }
@@ -53,19 +53,19 @@ static ahs_status step_hist(SortJob& j, uint32_t* hist_out, int ndig_fused) {
   if (large) {
     groups = hist_large_blocks(j.n);
     AHS_HIP(j, launch_fill_u32(corr, 65536, 0u, j.s), "fill");
-    ProfScope p(j.ctx, "feature_hist", j.s);
+    ProfScope p(j.ctx, "feature_hist", j.s, (double)j.key_bytes * j.n);
     AHS_HIP(j, launch_hist_large(j.kk, j.kin, j.n, j.f.min_key, j.f.shift, parts, corr, groups, ndig_fused,
                                  at<uint32_t>(j.ws, j.L.dparts), j.s),
             "histogram launch");
   } else {
     groups = hist_small_blocks(j.n);
-    ProfScope p(j.ctx, "feature_hist", j.s);
+    ProfScope p(j.ctx, "feature_hist", j.s, (double)j.key_bytes * j.n);
     AHS_HIP(j, launch_hist_small(j.kk, j.kin, j.n, j.f.min_key, j.f.shift, nbins, parts, groups, j.s),
             "histogram launch");
   }
   int nparts = 0;
   {
-    ProfScope p(j.ctx, "hist_reduce", j.s);
+    ProfScope p(j.ctx, "hist_reduce", j.s, 4.0 * nbins);
     AHS_HIP(j, launch_hist_reduce(parts, groups, nbins, large ? 1 : 0, corr, hist_out, j.n,
                                   at<double>(j.ws, j.L.hpart), &nparts, j.s),
             "histogram reduce");
@@ -117,7 +117,7 @@ static ahs_status run_radix(SortJob& j, const std::vector<uint32_t>* ready_count
   } else {
     const int nb = digit_hist_blocks(j.n);
     {
-      ProfScope p(j.ctx, "digit_hist", j.s);
+      ProfScope p(j.ctx, "digit_hist", j.s, (double)j.key_bytes * j.n);
       AHS_HIP(j, launch_digit_hist(j.kk, j.kin, j.n, j.f.min_key, ndig, at<uint32_t>(j.ws, j.L.dparts), nb, j.s),
               "digit histogram");
     }
@@ -156,9 +156,9 @@ static ahs_status run_radix(SortJob& j, const std::vector<uint32_t>* ready_count
     vsrc = tmpv;
   }
   const uint64_t tiles = ceil_div(j.n, (uint64_t)os_tile(j.key_bytes));
-  uint64_t* status = at<uint64_t>(j.ws, j.L.status);
+  uint32_t* status = at<uint32_t>(j.ws, j.L.status);
+  const uint64_t status_words32 = tiles * 256 * status_word_bytes(j.n) / 4;
   uint32_t* counters = at<uint32_t>(j.ws, j.L.counters);
-  AHS_HIP(j, launch_fill_u64(status, tiles * 256, 0ull, j.s), "fill");
   AHS_HIP(j, launch_fill_u32(counters, 64, 0u, j.s), "fill");
   const bool flt = j.kk == KK_F32 || j.kk == KK_F64;
   for (int q = 0; q < m; ++q) {
@@ -175,12 +175,12 @@ static ahs_status run_radix(SortJob& j, const std::vector<uint32_t>* ready_count
     a.digit_shift = 8u * (uint32_t)passes[q];
     a.map_in = (flt && q == 0) ? 1u : 0u;
     a.unmap_out = (flt && q == m - 1) ? 1u : 0u;
-    a.epoch = (uint32_t)q + 1u;
     a.digit_offsets = at<uint32_t>(j.ws, j.L.doffs) + 256 * passes[q];
     a.status = status;
     a.tile_counter = counters + q;
+    AHS_HIP(j, launch_fill_u32(status, status_words32, 0u, j.s), "fill");
     {
-      ProfScope p(j.ctx, "onesweep_pass", j.s);
+      ProfScope p(j.ctx, "onesweep_pass", j.s, (2.0 * j.key_bytes + (j.vin ? 8.0 : 0.0)) * j.n);
       AHS_HIP(j, launch_onesweep(j.kk, j.vin != nullptr, a, j.s), "onesweep launch");
     }
     src = dst;
@@ -199,16 +199,16 @@ static ahs_status run_counting(SortJob& j, bool hist_ready) {
   if (!hist_ready) AHS_TRY(step_hist(j, hist, 0));
   uint32_t* offs = at<uint32_t>(j.ws, j.L.offs);
   {
-    ProfScope p(j.ctx, "counting_scan", j.s);
+    ProfScope p(j.ctx, "counting_scan", j.s, 8.0 * j.f.nbins);
     AHS_HIP(j, launch_scan_bins(hist, j.f.nbins, offs, j.s), "scan");
   }
-  ProfScope p(j.ctx, "counting_expand", j.s);
+  ProfScope p(j.ctx, "counting_expand", j.s, (double)j.key_bytes * j.n);
   AHS_HIP(j, launch_expand(j.kk, offs, j.f.nbins, j.f.min_key, j.kout, j.n, j.s), "expand");
   return AHS_OK;
 }
 
 static ahs_status run_small(SortJob& j) {
-  ProfScope p(j.ctx, "small_sort", j.s);
+  ProfScope p(j.ctx, "small_sort", j.s, (2.0 * j.key_bytes + (j.vin ? 8.0 : 0.0)) * j.n);
   AHS_HIP(j, launch_small_sort(j.kk, j.kin, j.kout, j.vin, j.vout, (uint32_t)j.n, j.s), "small sort");
   return AHS_OK;
 }

@@ -357,3 +357,36 @@ def test_auto_general_path():
         assert run_pair(keys) == ahs.QUICK
     keys = gen.wide_keys("u64uniform", n=1 << 19)
     assert run_pair(keys, np.arange(keys.size, dtype=np.uint32)) == ahs.QUICK
+
+
+@pytest.mark.parametrize("kind,log2n", [("u32", 25), ("u64", 24), ("f32", 24)])
+def test_quick_multilevel(kind, log2n):
+    """Large enough that level 0 leaves buckets above the block-sort
+    capacity, so later levels run with many segments at once."""
+    n = 1 << log2n
+    if kind == "u32":
+        keys = gen.strategy_sweep("uniform32", n=n)
+    elif kind == "u64":
+        keys = gen.wide_keys("u64uniform", n=n)
+    else:
+        keys = gen.wide_keys("f32normal", n=n)
+    vals = np.arange(n, dtype=np.uint32)
+    say(f"multilevel quick {kind} n=2^{log2n}")
+    ko, vo, chosen, _ = ahs.ahs_sort(to_dev(keys), to_dev(vals), ahs.QUICK)
+    torch.cuda.synchronize()
+    st, rk, rv, _, _ = O.sort(keys, vals, O.RADIX)  # same unique stable result, faster oracle
+    assert st == O.OK
+    assert np.array_equal(bits(ko.cpu().numpy()), bits(rk))
+    assert np.array_equal(vo.cpu().numpy(), rv)
+
+
+@pytest.mark.parametrize("case", ["zipf256", "uniform32", "uniform4096"])
+def test_radix_counting_large(case):
+    n = 1 << 25
+    keys = gen.strategy_sweep(case, n=n)
+    say(f"large {case}")
+    ko, _, _, _ = ahs.ahs_sort(to_dev(keys), None, ahs.RADIX)
+    st, rk, _, _, _ = O.sort(keys, None, O.RADIX)
+    assert np.array_equal(ko.cpu().numpy(), rk)
+    ko, _, chosen, _ = ahs.ahs_sort(to_dev(keys), None, ahs.AUTO)
+    assert np.array_equal(ko.cpu().numpy(), rk)
