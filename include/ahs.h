@@ -164,6 +164,32 @@ ahs_status ahs_sort(ahs_context* ctx, const void* d_keys_in, void* d_keys_out,
                     ahs_strategy requested, const ahs_config* cfg, void* d_ws, size_t ws_bytes,
                     void* stream, ahs_strategy* h_chosen, ahs_feature_vector* h_feats);
 
+/* Batched segmented sort: nseg independent arrays stored back to back,
+ * segment s occupying [d_offsets[s], d_offsets[s+1]) of the key (and
+ * payload) arrays; d_offsets is a device array of nseg + 1 non-decreasing
+ * uint64 with d_offsets[nseg] == n_total.  Each segment's output equals
+ * ahs_sort on that segment alone (stable ascending order), and its decision
+ * is the FSM of Sec. III-A on its own features.  Segments of at most 8,192
+ * keys are sorted wholly in LDS by one fused kernel that also computes the
+ * segment's features and decision; larger segments go through the
+ * sample-sort levels, all segments together, and get their features from
+ * their sorted output (the features do not depend on key order).
+ * d_chosen (nullable, nseg bytes) receives each segment's strategy code
+ * (AHS_* values; 0xFD marks a segment holding NaN keys, whose output is its
+ * keys ordered by the bit map with NaNs at the ends).  d_feats (nullable,
+ * nseg entries) receives each segment's feature vector.  cfg->use_model is
+ * not supported here (AHS_E_UNSUPPORTED).  A forced strategy is reported
+ * for every segment.  Invalid offsets give AHS_E_INVALID_ARG before any
+ * output is written.  Synchronises the stream once per sample-sort level
+ * (2-3 times for segments up to 2^20 keys).  n_total may exceed 2^32;
+ * each segment must hold fewer than 2^32 keys. */
+size_t ahs_segmented_workspace_bytes(uint64_t n_total, uint32_t nseg, ahs_dtype dtype, int with_payload);
+ahs_status ahs_sort_segmented(ahs_context* ctx, const void* d_keys_in, void* d_keys_out,
+                              const uint32_t* d_vals_in, uint32_t* d_vals_out, const uint64_t* d_offsets,
+                              uint32_t nseg, uint64_t n_total, ahs_dtype dtype, ahs_strategy requested,
+                              const ahs_config* cfg, void* d_ws, size_t ws_bytes, void* stream,
+                              uint8_t* d_chosen, ahs_feature_vector* d_feats);
+
 /* Learned predictor (Sec. III-H, Listing 5): gradient-boosted trees over
  * (n, k, H) in the project's text format
  *   ahs-gbt 1 / num_class 3 / base_score s0 s1 s2 / num_trees T /

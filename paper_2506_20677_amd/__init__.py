@@ -86,6 +86,9 @@ def lib():
             "ahs_select": (i32, [C.POINTER(FeatureVector), C.POINTER(Config), vp, C.POINTER(C.c_int)]),
             "ahs_sort": (i32, [vp, vp, vp, vp, vp, u64, i32, i32, C.POINTER(Config), vp, sz, vp,
                                C.POINTER(C.c_int), C.POINTER(FeatureVector)]),
+            "ahs_segmented_workspace_bytes": (sz, [u64, u32, i32, i32]),
+            "ahs_sort_segmented": (i32, [vp, vp, vp, vp, vp, vp, u32, u64, i32, i32, C.POINTER(Config), vp, sz,
+                                         vp, vp, vp]),
             "ahs_model_load": (i32, [C.c_char_p, C.POINTER(vp)]),
             "ahs_model_free": (None, [vp]),
             "ahs_model_predict": (i32, [vp, C.POINTER(FeatureVector), C.POINTER(C.c_int)]),
@@ -287,6 +290,66 @@ def ahs_sort(keys: torch.Tensor, values: torch.Tensor | None = None, strategy: i
     if st != OK:
         _raise(st, ctx, f if want_features else None)
     return out, out_values, chosen.value, (f if want_features else None)
+
+
+SEG_NAN = 0xFD  # per-segment decision code of a segment that holds NaN keys
+
+
+def ahs_segmented_workspace_bytes(n_total: int, nseg: int, dtype: int, with_payload: bool) -> int:
+    return lib().ahs_segmented_workspace_bytes(n_total, nseg, dtype, 1 if with_payload else 0)
+
+
+def ahs_sort_segmented(keys: torch.Tensor, offsets: torch.Tensor, values: torch.Tensor | None = None,
+                       strategy: int | str = AUTO, cfg: Config | None = None, out: torch.Tensor | None = None,
+                       out_values: torch.Tensor | None = None, dtype: int | None = None,
+                       ctx: Context | None = None, stream=None, want_chosen: bool = True,
+                       want_features: bool = False):
+    """Sorts nseg independent segments of one device array in one call.
+
+    ``offsets`` is a device int64/uint64 tensor of nseg + 1 non-decreasing
+    boundaries ending at keys.numel().  Returns (keys_out, values_out or None,
+    chosen (device uint8 tensor of nseg decisions) or None, features (device
+    tensor of nseg FeatureVector records, viewed as bytes) or None)."""
+    if isinstance(strategy, str):
+        strategy = STRATEGY_CODES[strategy]
+    code = dtype_code(keys, dtype)
+    _check_keys(keys, code)
+    if not offsets.is_cuda or not offsets.is_contiguous() or offsets.element_size() != 8 or offsets.dim() != 1:
+        raise ValueError("offsets must be a contiguous 1-D device tensor of 64-bit elements")
+    nseg = offsets.numel() - 1
+    if nseg < 0:
+        raise ValueError("offsets needs at least one element")
+    ctx = ctx or default_context(keys.device.index)
+    n = keys.numel()
+    if out is None:
+        out = torch.empty_like(keys)
+    if values is not None:
+        if values.numel() != n or values.element_size() != 4 or not values.is_cuda or not values.is_contiguous():
+            raise ValueError("values must be a contiguous device tensor of n 32-bit elements")
+        if out_values is None:
+            out_values = torch.empty_like(values)
+    elif out_values is not None:
+        raise ValueError("out_values given without values")
+    wsb = ahs_segmented_workspace_bytes(n, nseg, code, values is not None)
+    ws = ctx.workspace(wsb)
+    chosen = torch.empty(nseg, dtype=torch.uint8, device=keys.device) if want_chosen else None
+    feats = (torch.empty(nseg * C.sizeof(FeatureVector), dtype=torch.uint8, device=keys.device)
+             if want_features else None)
+    vp = (lambda t: C.c_void_p(t.data_ptr()) if t is not None else None)
+    st = lib().ahs_sort_segmented(ctx.handle, vp(keys), vp(out), vp(values), vp(out_values), vp(offsets), nseg, n,
+                                  code, strategy, C.byref(cfg) if cfg is not None else None,
+                                  C.c_void_p(ws.data_ptr()), ws.numel(), _stream_handle(stream), vp(chosen),
+                                  vp(feats))
+    if st != OK:
+        _raise(st, ctx)
+    return out, out_values, chosen, feats
+
+
+def feature_records(feats: torch.Tensor) -> list:
+    """Host list of FeatureVector from the byte tensor ahs_sort_segmented returns."""
+    raw = feats.cpu().numpy().tobytes()
+    sz = C.sizeof(FeatureVector)
+    return [FeatureVector.from_buffer_copy(raw[i:i + sz]) for i in range(0, len(raw), sz)]
 
 
 def ahs_profile_enable(ctx: Context, on: bool = True):

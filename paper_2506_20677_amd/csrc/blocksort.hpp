@@ -1,0 +1,172 @@
+// In-LDS stable sort of up to SS_CAP keys by one workgroup, and the run
+// statistics of a sorted key array (for features computed after sorting).
+#pragma once
+
+#include "onesweep.hpp"
+#include "samplesort.hpp"
+
+namespace ahs {
+
+template <typename K, bool PAY>
+struct BlockSortSmem {
+  RankSlot slot[SS_THREADS / WAVE][256];
+  uint32_t tstart[256];
+  K keys[SS_CAP];
+  uint32_t vals[PAY ? SS_CAP : 1];
+  uint32_t scan[SS_THREADS / WAVE + 1];
+  K red[2][SS_THREADS / WAVE];
+  double dred[SS_THREADS / WAVE];
+  uint32_t misc[4];
+};
+
+// Loads `size` keys (mapping raw float bit patterns when `raw`) and
+// payloads into LDS.  Ends with a barrier.
+template <int KK, bool PAY>
+__device__ __forceinline__ void lds_load_mapped(BlockSortSmem<typename KeyTraits<KK>::K, PAY>& sm,
+                                                const typename KeyTraits<KK>::K* __restrict__ src,
+                                                const uint32_t* __restrict__ vsrc, uint32_t size, bool raw) {
+  using K = typename KeyTraits<KK>::K;
+  for (uint32_t j = threadIdx.x; j < size; j += SS_THREADS) {
+    K x = src[j];
+    if constexpr (KeyTraits<KK>::FLT) x = raw ? fmap(x) : x;
+    sm.keys[j] = x;
+    if constexpr (PAY) sm.vals[j] = vsrc[j];
+  }
+  __syncthreads();
+}
+
+// Stable LSD sort of sm.keys[0, size) (mapped keys) by 8-bit digits of
+// (key - min), as many passes as the span needs; payloads move along.
+// Returns min and max (mapped).  Ends with a barrier.
+template <typename K, bool PAY>
+__device__ __forceinline__ void lds_sort_loaded(BlockSortSmem<K, PAY>& sm, uint32_t size, K& out_min, K& out_max) {
+  constexpr int IPT = SS_CAP / SS_THREADS;
+  constexpr int NW = SS_THREADS / WAVE;
+  const int t = threadIdx.x, w = t / WAVE, lane = lane_id();
+  K mn = ~K(0), mx = K(0);
+  for (uint32_t j = t; j < size; j += SS_THREADS) {
+    const K x = sm.keys[j];
+    mn = x < mn ? x : mn;
+    mx = x > mx ? x : mx;
+  }
+  mn = wave_min(mn);
+  mx = wave_max(mx);
+  if (lane == 0) { sm.red[0][w] = mn; sm.red[1][w] = mx; }
+  for (int i = t; i < NW * 256; i += SS_THREADS) (&sm.slot[0][0])[i].mask = 0ull;
+  __syncthreads();
+  mn = sm.red[0][0];
+  mx = sm.red[1][0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) {
+    mn = sm.red[0][i] < mn ? sm.red[0][i] : mn;
+    mx = sm.red[1][i] > mx ? sm.red[1][i] : mx;
+  }
+  out_min = mn;
+  out_max = mx;
+  const int npass = (bitlen64((uint64_t)(mx - mn)) + 7) / 8;
+
+  for (int p = 0; p < npass; ++p) {
+    K k[IPT];
+    uint32_t v[IPT];
+    uint32_t d[IPT];
+    const uint32_t wbase = (uint32_t)w * WAVE * IPT;
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+      const uint32_t idx = wbase + (uint32_t)i * WAVE + lane;
+      if (idx < size) {
+        k[i] = sm.keys[idx];
+        if constexpr (PAY) v[i] = sm.vals[idx];
+        d[i] = (uint32_t)(((k[i] - mn) >> (8 * p)) & 255u);
+      } else {
+        k[i] = ~K(0);
+        if constexpr (PAY) v[i] = 0;
+        d[i] = 255u;
+      }
+    }
+    for (int i = t; i < NW * 256; i += SS_THREADS) (&sm.slot[0][0])[i].count = 0u;
+    __syncthreads();
+    uint32_t r[IPT];
+    rank_wave_items<IPT>(d, r, sm.slot[w]);
+    __syncthreads();
+    const uint32_t cnt = wave_prefix_per_digit<NW>(sm.slot);
+    uint32_t total;
+    const uint32_t tstart = block_excl_scan<SS_THREADS>(t < 256 ? cnt : 0u, sm.scan, total);
+    if (t < 256) sm.tstart[t] = tstart;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+      const uint32_t lp = sm.tstart[d[i]] + sm.slot[w][d[i]].count + r[i];
+      if (lp < (uint32_t)SS_CAP) {
+        sm.keys[lp] = k[i];
+        if constexpr (PAY) sm.vals[lp] = v[i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Sum over the runs of equal bins (key - kmin) >> shift inside one chunk of
+// a sorted array of mapped keys: each run of c keys of a segment of n keys
+// contributes -(c/n) log2(c/n).  The chunk holds cnt keys (in LDS) starting
+// at segment position pos0; prev_key / next_key are the keys just before
+// and after the chunk (has_prev / has_next false at the segment ends).
+// carry_start is the segment position where the run open at the chunk's
+// start began; it is updated to the start of the run open at the chunk's end.
+// Returns the block's FP64 sum (valid in every thread).  Uses sm.slot as
+// scratch for run starts (SS_CAP u32 entries fit in it).
+template <typename K, bool PAY>
+__device__ __forceinline__ double lds_run_entropy(BlockSortSmem<K, PAY>& sm, uint32_t cnt, uint64_t pos0, K prev_key,
+                                                  bool has_prev, K next_key, bool has_next, K kmin, uint32_t shift,
+                                                  uint64_t n, uint64_t& carry_start) {
+  constexpr int CH = SS_CAP / SS_THREADS;  // consecutive positions per thread
+  const int t = threadIdx.x;
+  uint32_t* s_start = reinterpret_cast<uint32_t*>(&sm.slot[0][0]);  // run starts (chunk-relative)
+  const uint32_t j0 = (uint32_t)t * CH;
+  auto binof = [&](K x) { return (uint64_t)((x - kmin) >> shift); };
+  // run starts in my positions
+  uint32_t nst = 0;
+  uint32_t startbits = 0;
+  for (int q = 0; q < CH; ++q) {
+    const uint32_t j = j0 + q;
+    if (j >= cnt) break;
+    bool st;
+    if (j == 0) st = !has_prev || binof(prev_key) != binof(sm.keys[0]);
+    else st = binof(sm.keys[j - 1]) != binof(sm.keys[j]);
+    if (st) { ++nst; startbits |= 1u << q; }
+  }
+  uint32_t total;
+  uint32_t r = block_excl_scan<SS_THREADS>(nst, sm.scan, total);
+  for (int q = 0; q < CH; ++q)
+    if (startbits >> q & 1u) s_start[r++] = j0 + q;
+  __syncthreads();
+  const uint64_t carry_in = carry_start;
+  double acc = 0.0;
+  const double inv_n = 1.0 / (double)n;
+  r = r - nst;  // runs started before my first position
+  for (int q = 0; q < CH; ++q) {
+    const uint32_t j = j0 + q;
+    if (j >= cnt) break;
+    if (startbits >> q & 1u) ++r;
+    bool end;
+    if (j + 1 == cnt) end = !has_next || binof(next_key) != binof(sm.keys[j]);
+    else end = binof(sm.keys[j + 1]) != binof(sm.keys[j]);
+    if (end) {
+      const uint64_t start = r == 0 ? carry_in : pos0 + s_start[r - 1];
+      const double c = (double)(pos0 + j + 1 - start);
+      const double p = c * inv_n;
+      acc -= p * log2(p);
+    }
+  }
+  // new carry: start of the last run in the chunk
+  if (total > 0) carry_start = pos0 + s_start[total - 1];
+  acc = wave_sum(acc);
+  if (lane_id() == 0) sm.dred[t / WAVE] = acc;
+  __syncthreads();
+  double sum = 0.0;
+#pragma unroll
+  for (int i = 0; i < SS_THREADS / WAVE; ++i) sum += sm.dred[i];
+  __syncthreads();
+  return sum;
+}
+
+}  // namespace ahs

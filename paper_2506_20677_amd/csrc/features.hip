@@ -304,14 +304,30 @@ __global__ __launch_bounds__(HIST_LARGE_THREADS) void k_hist_large(const typenam
     if (__ballot(same && bins[0] == b0 && m == V) == active) {
       if (mbcnt(active) == 0) add_packed(b0, (uint32_t)popc64(active) * V);
     } else {
+      // per key slot: lanes sharing the first pending lane's bin (a hot or
+      // run-length bin) add together through one lane, if there are enough
+      bool pend[V];
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        pend[i] = i < m;
+        const uint64_t pm = __ballot(pend[i]);
+        if (pm) {
+          const uint32_t c = __builtin_amdgcn_readlane(bins[i], __builtin_ctzll(pm));
+          const uint64_t sm = __ballot(pend[i] && bins[i] == c);
+          if (popc64(sm) >= 8) {
+            if (mbcnt(sm) == 0 && (sm >> lane_id()) & 1ull) add_packed(c, popc64(sm));
+            pend[i] = pend[i] && bins[i] != c;
+          }
+        }
+      }
       // independent returning atomics first, overflow checks after
       uint32_t olds[V];
 #pragma unroll
       for (int i = 0; i < V; ++i)
-        if (i < m) olds[i] = atomicAdd(&h[bins[i] >> 1], (bins[i] & 1u) ? 0x10000u : 1u);
+        if (pend[i]) olds[i] = atomicAdd(&h[bins[i] >> 1], (bins[i] & 1u) ? 0x10000u : 1u);
 #pragma unroll
       for (int i = 0; i < V; ++i) {
-        if (i >= m) continue;
+        if (!pend[i]) continue;
         const uint32_t bin = bins[i], old = olds[i];
         if (bin & 1u) {
           if ((old >> 16) == 0xFFFFu) add_agent(&corr[bin], 65536u);
@@ -365,39 +381,57 @@ hipError_t launch_hist_large(int kk, const void* keys, uint64_t n, uint64_t kmin
 
 // Folds the per-block histograms into the final counts, writes them (when
 // hist_out is non-null) and sums the entropy terms -(c/n) log2(c/n) of the
-// block's bins in FP64 into hpart[block].  Large histograms: one thread per
-// packed word (two bins); small: one thread per bin.
+// block's bins in FP64 into hpart[block].  Each block covers HRED_ITEMS
+// items (packed words for large histograms, bins for small ones) with
+// HRED_SLICES threads per item splitting the per-block partials.
 constexpr int HRED_THREADS = 256;
+constexpr int HRED_SLICES = 8;
+constexpr int HRED_ITEMS = HRED_THREADS / HRED_SLICES;
 
 __global__ __launch_bounds__(HRED_THREADS) void k_hist_reduce(const uint32_t* __restrict__ partials, int ngroups,
                                                               uint32_t nbins, int large,
                                                               const uint32_t* __restrict__ corr,
                                                               uint32_t* __restrict__ hist_out, uint64_t n,
                                                               double* __restrict__ hpart) {
-  const double inv_n = 1.0 / (double)n;
-  double term = 0.0;
-  const uint32_t t = blockIdx.x * HRED_THREADS + threadIdx.x;
-  if (large) {
-    const uint32_t nwords = (nbins + 1u) / 2u;
-    if (t < nwords) {
-      uint32_t c0 = corr[2 * t], c1 = corr[2 * t + 1];
-      for (int g = 0; g < ngroups; ++g) {
-        const uint32_t w = partials[(size_t)g * HIST_LARGE_WORDS + t];
+  __shared__ uint32_t s0[HRED_SLICES][HRED_ITEMS], s1[HRED_SLICES][HRED_ITEMS];
+  const int it = threadIdx.x % HRED_ITEMS, sl = threadIdx.x / HRED_ITEMS;
+  const uint32_t item = blockIdx.x * HRED_ITEMS + it;
+  const uint32_t nitems = large ? (nbins + 1u) / 2u : nbins;
+  uint32_t c0 = 0, c1 = 0;
+  if (item < nitems) {
+    if (large) {
+      for (int g = sl; g < ngroups; g += HRED_SLICES) {
+        const uint32_t w = partials[(size_t)g * HIST_LARGE_WORDS + item];
         c0 += w & 0xFFFFu;
         c1 += w >> 16;
       }
+    } else {
+      for (int g = sl; g < ngroups; g += HRED_SLICES) c0 += partials[(size_t)g * nbins + item];
+    }
+  }
+  s0[sl][it] = c0;
+  s1[sl][it] = c1;
+  __syncthreads();
+  const double inv_n = 1.0 / (double)n;
+  double term = 0.0;
+  if (sl == 0 && item < nitems) {
+    for (int q = 1; q < HRED_SLICES; ++q) {
+      c0 += s0[q][it];
+      c1 += s1[q][it];
+    }
+    if (large) {
+      c0 += corr[2 * item];
+      c1 += corr[2 * item + 1];
       if (hist_out) {
-        hist_out[2 * t] = c0;
-        if (2 * t + 1 < nbins) hist_out[2 * t + 1] = c1;
+        hist_out[2 * item] = c0;
+        if (2 * item + 1 < nbins) hist_out[2 * item + 1] = c1;
       }
       if (c0) { const double p = (double)c0 * inv_n; term -= p * log2(p); }
-      if (2 * t + 1 < nbins && c1) { const double p = (double)c1 * inv_n; term -= p * log2(p); }
+      if (2 * item + 1 < nbins && c1) { const double p = (double)c1 * inv_n; term -= p * log2(p); }
+    } else {
+      if (hist_out) hist_out[item] = c0;
+      if (c0) { const double p = (double)c0 * inv_n; term -= p * log2(p); }
     }
-  } else if (t < nbins) {
-    uint32_t c = 0;
-    for (int g = 0; g < ngroups; ++g) c += partials[(size_t)g * nbins + t];
-    if (hist_out) hist_out[t] = c;
-    if (c) { const double p = (double)c * inv_n; term -= p * log2(p); }
   }
   term = wave_sum(term);
   __shared__ double s[HRED_THREADS / WAVE];
@@ -414,7 +448,7 @@ hipError_t launch_hist_reduce(const uint32_t* partials, int ngroups, uint32_t nb
                               const uint32_t* corr, uint32_t* hist_out, uint64_t n, double* hpart,
                               int* nparts_out, hipStream_t s) {
   const uint32_t items = large ? (nbins + 1u) / 2u : nbins;
-  const int nb = (int)((items + HRED_THREADS - 1) / HRED_THREADS);
+  const int nb = (int)((items + HRED_ITEMS - 1) / HRED_ITEMS);
   *nparts_out = nb;
   k_hist_reduce<<<nb, HRED_THREADS, 0, s>>>(partials, ngroups, nbins, large, corr, hist_out, n, hpart);
   return hipGetLastError();

@@ -83,7 +83,7 @@ inline Layout plan_layout(uint64_t n, int key_bytes, int with_payload, bool need
   const uint64_t tiles = ceil_div(n ? n : 1, tile);
   L.df = take(sizeof(DevFeatures));
   L.mm = take(sizeof(MinMaxPartial) * (size_t)minmax_blocks(n));
-  L.hpart = take(sizeof(double) * 256);
+  L.hpart = take(sizeof(double) * 2048);  // one partial per reduce block (<= 65,536 / 32)
   const size_t small_parts = (size_t)hist_small_blocks(n) * HIST_SMALL_MAX_BINS;
   const size_t large_parts = (size_t)hist_large_blocks(n) * HIST_LARGE_WORDS;
   L.hist_parts = take(4 * std::max(small_parts, large_parts));

@@ -11,6 +11,7 @@
 //   r = #{i : s_i < x};  id = 2r + (r < 255 && x == s_r)
 // so ids ascend with the key and duplicate splitters only leave buckets
 // empty.
+#include "blocksort.hpp"
 #include "onesweep.hpp"
 #include "samplesort.hpp"
 
@@ -130,10 +131,21 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_count(const typename KeyTrait
     const uint64_t rem = (uint64_t)sg.size - off;
     const uint32_t cnt = rem < tile_keys ? (uint32_t)rem : tile_keys;
     const K* p = src + sg.start + off;
-    for (uint32_t i = t; i < cnt; i += SS_THREADS) {
-      K x = p[i];
-      if constexpr (KeyTraits<KK>::FLT) x = map_in ? fmap(x) : x;
-      atomicAdd(&s_cnt[ss_classify<K>(x, s_spl)], 1u);
+    constexpr int IPT = 16;
+    for (uint32_t b0 = 0; b0 < cnt; b0 += SS_THREADS * IPT) {
+      K x[IPT];
+#pragma unroll
+      for (int i = 0; i < IPT; ++i) {
+        const uint32_t idx = b0 + (uint32_t)i * SS_THREADS + t;
+        x[i] = p[idx < cnt ? idx : cnt - 1];
+      }
+#pragma unroll
+      for (int i = 0; i < IPT; ++i) {
+        const uint32_t idx = b0 + (uint32_t)i * SS_THREADS + t;
+        K y = x[i];
+        if constexpr (KeyTraits<KK>::FLT) y = map_in ? fmap(y) : y;
+        if (idx < cnt) atomicAdd(&s_cnt[ss_classify<K>(y, s_spl)], 1u);
+      }
     }
   }
   __syncthreads();
@@ -159,12 +171,12 @@ __global__ __launch_bounds__(SS_NB) void k_ss_plan(const SsSeg* __restrict__ seg
   uint32_t total;
   const uint32_t ex = block_excl_scan<SS_NB>(c, sm, total);
   const uint64_t pos = sg.start + ex;
-  offs[(size_t)blockIdx.x * SS_NB + b] = (uint32_t)pos;
+  offs[(size_t)blockIdx.x * SS_NB + b] = ex;  // relative to the segment start
   if (c == 0) return;
   if (b & 1) {
     if (dst_buf == SS_BUF_OUT && !copy_in_place) return;
     const uint32_t nchunks = (c + SS_CAP - 1) / SS_CAP;
-    atomicAdd(&ctr->item_keys, c);
+    atomicAdd(&ctr->item_keys, (unsigned long long)c);
     const uint32_t at = atomicAdd(&ctr->nitems, nchunks);
     for (uint32_t q = 0; q < nchunks; ++q) {
       if (at + q >= item_cap) { atomicOr(&ctr->overflow, 1u); break; }
@@ -175,7 +187,7 @@ __global__ __launch_bounds__(SS_NB) void k_ss_plan(const SsSeg* __restrict__ seg
       items[at + q] = it;
     }
   } else if (c <= SS_CAP) {
-    atomicAdd(&ctr->item_keys, c);
+    atomicAdd(&ctr->item_keys, (unsigned long long)c);
     const uint32_t at = atomicAdd(&ctr->nitems, 1u);
     if (at >= item_cap) { atomicOr(&ctr->overflow, 1u); return; }
     SsItem it;
@@ -184,7 +196,7 @@ __global__ __launch_bounds__(SS_NB) void k_ss_plan(const SsSeg* __restrict__ seg
     it.flags = dst_buf << 8;
     items[at] = it;
   } else {
-    atomicAdd(&ctr->seg_keys_next, c);
+    atomicAdd(&ctr->seg_keys_next, (unsigned long long)c);
     const uint32_t at = atomicAdd(&ctr->nsegs_next, 1u);
     if (at >= seg_cap) { atomicOr(&ctr->overflow, 2u); return; }
     SsSeg ns;
@@ -309,11 +321,11 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_scatter(SsScatterArgs a) {
   __syncthreads();
 
   K* __restrict__ dst = (K*)a.dst;
-  const uint64_t lim = sg.start + sg.size;
   for (uint32_t j = t; j < valid; j += SS_THREADS) {
     const uint32_t dj = s_dig[j];
-    const uint64_t o = (uint64_t)s_dbase[dj] + (j - s_tstart[dj]);
-    if (o < sg.start || o >= lim) continue;  // unreachable with consistent counts
+    const uint32_t rel = s_dbase[dj] + (j - s_tstart[dj]);
+    if (rel >= sg.size) continue;  // unreachable with consistent counts
+    const uint64_t o = sg.start + rel;
     dst[o] = s_keys[j];
     if constexpr (PAY) a.vdst[o] = s_vals[j];
   }
@@ -321,19 +333,11 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_scatter(SsScatterArgs a) {
 
 // ------------------------------------------------------------------ block sort
 // One block per item.  COPY items move (and unmap) keys.  SORT items (at
-// most SS_CAP keys) are loaded into LDS and sorted stably by LSD passes over
-// 8-bit digits of (key - min) using the same wave ranking, then written out.
+// most SS_CAP keys) are loaded into LDS and sorted by lds_sort_loaded.
 template <int KK, bool PAY>
 __global__ __launch_bounds__(SS_THREADS) void k_ss_block(SsBlockArgs a) {
   using K = typename KeyTraits<KK>::K;
-  constexpr int IPT = SS_CAP / SS_THREADS;
-  constexpr int NW = SS_THREADS / WAVE;
-  __shared__ RankSlot s_slot[NW][256];
-  __shared__ uint32_t s_tstart[256];
-  __shared__ K s_keys[SS_CAP];
-  __shared__ uint32_t s_vals[PAY ? SS_CAP : 1];
-  __shared__ uint32_t s_scan[NW + 1];
-  __shared__ K s_red[2][NW];
+  __shared__ BlockSortSmem<K, PAY> sm;
 
   const SsItem it = a.items[blockIdx.x];
   const uint32_t buf = (it.flags >> 8) & 0xFFu;
@@ -341,7 +345,7 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_block(SsBlockArgs a) {
   const uint32_t* __restrict__ vsrc = buf == SS_BUF_IN ? a.vin : (buf == SS_BUF_OUT ? a.vout : a.vtmp);
   const bool raw = buf == SS_BUF_IN;
   K* __restrict__ dst = (K*)a.kout;
-  const int t = threadIdx.x, w = t / WAVE, lane = lane_id();
+  const int t = threadIdx.x;
   const uint64_t base = it.start;
   const uint32_t size = it.size;
 
@@ -354,74 +358,14 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_block(SsBlockArgs a) {
     }
     return;
   }
-
-  K mn = ~K(0), mx = K(0);
+  lds_load_mapped<KK, PAY>(sm, src + base, PAY ? vsrc + base : nullptr, size, raw);
+  K mn, mx;
+  lds_sort_loaded<K, PAY>(sm, size, mn, mx);
   for (uint32_t j = t; j < size; j += SS_THREADS) {
-    K x = src[base + j];
-    if constexpr (KeyTraits<KK>::FLT) x = raw ? fmap(x) : x;
-    s_keys[j] = x;
-    if constexpr (PAY) s_vals[j] = vsrc[base + j];
-    mn = x < mn ? x : mn;
-    mx = x > mx ? x : mx;
-  }
-  mn = wave_min(mn);
-  mx = wave_max(mx);
-  if (lane == 0) { s_red[0][w] = mn; s_red[1][w] = mx; }
-  for (int i = t; i < NW * 256; i += SS_THREADS) (&s_slot[0][0])[i].mask = 0ull;
-  __syncthreads();
-  mn = s_red[0][0];
-  mx = s_red[1][0];
-#pragma unroll
-  for (int i = 1; i < NW; ++i) {
-    mn = s_red[0][i] < mn ? s_red[0][i] : mn;
-    mx = s_red[1][i] > mx ? s_red[1][i] : mx;
-  }
-  const int npass = (bitlen64((uint64_t)(mx - mn)) + 7) / 8;
-
-  for (int p = 0; p < npass; ++p) {
-    K k[IPT];
-    uint32_t v[IPT];
-    uint32_t d[IPT];
-    const uint32_t wbase = (uint32_t)w * WAVE * IPT;
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-      const uint32_t idx = wbase + (uint32_t)i * WAVE + lane;
-      if (idx < size) {
-        k[i] = s_keys[idx];
-        if constexpr (PAY) v[i] = s_vals[idx];
-        d[i] = (uint32_t)(((k[i] - mn) >> (8 * p)) & 255u);
-      } else {
-        k[i] = ~K(0);
-        if constexpr (PAY) v[i] = 0;
-        d[i] = 255u;
-      }
-    }
-    for (int i = t; i < NW * 256; i += SS_THREADS) (&s_slot[0][0])[i].count = 0u;
-    __syncthreads();
-    uint32_t r[IPT];
-    rank_wave_items<IPT>(d, r, s_slot[w]);
-    __syncthreads();
-    const uint32_t cnt = wave_prefix_per_digit<NW>(s_slot);
-    uint32_t total;
-    const uint32_t tstart = block_excl_scan<SS_THREADS>(t < 256 ? cnt : 0u, s_scan, total);
-    if (t < 256) s_tstart[t] = tstart;
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-      const uint32_t lp = s_tstart[d[i]] + s_slot[w][d[i]].count + r[i];
-      if (lp < (uint32_t)SS_CAP) {
-        s_keys[lp] = k[i];
-        if constexpr (PAY) s_vals[lp] = v[i];
-      }
-    }
-    __syncthreads();
-  }
-
-  for (uint32_t j = t; j < size; j += SS_THREADS) {
-    K x = s_keys[j];
+    K x = sm.keys[j];
     if constexpr (KeyTraits<KK>::FLT) x = funmap(x);
     dst[base + j] = x;
-    if constexpr (PAY) a.vout[base + j] = s_vals[j];
+    if constexpr (PAY) a.vout[base + j] = sm.vals[j];
   }
 }
 
@@ -471,7 +415,7 @@ hipError_t launch_ss_tiles(SsSeg* segs, SsCounters* ctr, uint32_t tile_keys, uin
 template <int KK, bool PAY>
 static hipError_t scatter_kk(const SsScatterArgs& a, uint32_t ntiles, hipStream_t s) {
   constexpr int IPT = sizeof(typename KeyTraits<KK>::K) == 4 ? 16 : 8;
-  if (a.n < STATUS32_MAX_N)
+  if (a.max_seg < STATUS32_MAX_N)
     k_ss_scatter<KK, PAY, IPT, uint32_t><<<ntiles, SS_THREADS, 0, s>>>(a);
   else
     k_ss_scatter<KK, PAY, IPT, uint64_t><<<ntiles, SS_THREADS, 0, s>>>(a);

@@ -32,7 +32,7 @@ struct SsItem {       // a finished bucket: sort in LDS, or copy
 };
 struct SsCounters {   // per level, written by the device, read by the host
   uint32_t nsegs_next, nitems, ntiles_next, overflow;
-  uint32_t item_keys, seg_keys_next, pad0, pad1;
+  unsigned long long item_keys, seg_keys_next;
 };
 
 struct SsScatterArgs {
@@ -45,9 +45,9 @@ struct SsScatterArgs {
   const SsSeg* segs;
   const void* spl;
   const uint32_t* offs;
-  void* status;        // [tiles][SS_NB] words of status_word_bytes(n), zero before the launch
+  void* status;        // [tiles][SS_NB] words of status_word_bytes(max_seg), zero before the launch
   uint32_t* tile_counter;
-  uint64_t n;          // total keys (selects the status word size)
+  uint64_t max_seg;    // largest segment (selects the status word size)
 };
 
 struct SsBlockArgs {
@@ -59,6 +59,14 @@ struct SsBlockArgs {
   uint32_t* vout;
   const uint32_t* vtmp;
 };
+
+// Sample-sort scratch layout inside the workspace.
+struct SsLayout {
+  uint64_t seg_cap = 0, tile_cap = 0, item_cap = 0;
+  size_t segA = 0, segB = 0, spl = 0, counts = 0, offs = 0, items = 0, ctr = 0, status = 0, tilectr = 0;
+  size_t total = 0;
+};
+SsLayout ss_layout(uint64_t n, int key_bytes);
 
 hipError_t launch_ss_init(SsSeg* segs, SsItem* items, uint64_t n, hipStream_t s);
 hipError_t launch_ss_sample(int kk, const void* src, int map_in, const SsSeg* segs, uint32_t nsegs, void* spl,

@@ -121,3 +121,20 @@ def test_workspace_sizes_monotone_and_data_independent():
         assert b >= 4 * n
     assert ahs.ahs_workspace_bytes(1000, ahs.U64, True, ahs.RADIX) > ahs.ahs_workspace_bytes(1000, ahs.U32, False, ahs.RADIX)
     assert ahs.ahs_workspace_bytes(10, 9, False, ahs.AUTO) == 0
+
+
+def test_segmented_workspace_sizes():
+    prev = 0
+    for n in (0, 1, 8192, 10**6, 2**30):
+        b = ahs.ahs_segmented_workspace_bytes(n, 1000, ahs.U32, False)
+        assert b >= prev and b % 256 == 0 and b >= 4 * n
+        prev = b
+    # more segments need longer id tables; payload and wider keys need more scratch
+    assert ahs.ahs_segmented_workspace_bytes(10**6, 100_000, ahs.U32, False) > \
+        ahs.ahs_segmented_workspace_bytes(10**6, 10, ahs.U32, False)
+    assert ahs.ahs_segmented_workspace_bytes(10**6, 10, ahs.F64, True) > \
+        ahs.ahs_segmented_workspace_bytes(10**6, 10, ahs.U32, False)
+    # the batched sort never needs less than the single-array sort of all keys
+    assert ahs.ahs_segmented_workspace_bytes(10**6, 1, ahs.U32, False) >= \
+        ahs.ahs_workspace_bytes(10**6, ahs.U32, False, ahs.AUTO)
+    assert ahs.ahs_segmented_workspace_bytes(10, 1, 9, False) == 0

@@ -1,0 +1,233 @@
+"""GPU parity of the batched segmented sort against the CPU oracle.
+
+Each segment is checked as an independent array: its keys and payload
+bit-exact against the oracle's sort of that segment alone, its decision
+equal to the oracle's (up to the documented entropy-threshold tie), and its
+feature vector to the same bar as the single-array path.  A segment holding
+NaN keys has no oracle decision; its expected output is the stable order of
+the oracle's bit map and its decision code is 0xFD.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2506_20677_amd as ahs  # noqa: E402
+
+DEV = torch.device("cuda:0")
+H_RTOL = 1e-6
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def bits(a):
+    return a.view(np.uint32 if a.itemsize == 4 else np.uint64)
+
+
+def offsets_of(sizes):
+    offs = np.zeros(len(sizes) + 1, np.uint64)
+    np.cumsum(np.asarray(sizes, np.uint64), out=offs[1:])
+    return offs
+
+
+def check_features(f, rf):
+    assert (f.n, f.min_key, f.max_key, f.span, f.nan_count) == (rf.n, rf.min_key, rf.max_key, rf.span, rf.nan_count)
+    assert (f.shift, f.nbins, f.exact) == (rf.shift, rf.nbins, rf.exact)
+    if rf.entropy_bits == 0.0:
+        assert f.entropy_bits == 0.0
+    else:
+        assert abs(f.entropy_bits - rf.entropy_bits) <= H_RTOL * rf.entropy_bits, (f.entropy_bits, rf.entropy_bits)
+        assert abs(f.entropy_ratio - rf.entropy_ratio) <= 2 * H_RTOL * rf.entropy_ratio
+
+
+def near_threshold(rf):
+    if rf.nbins <= 1:
+        return False
+    thr = 0.7 * math.log2(rf.nbins)
+    return abs(rf.entropy_bits - thr) <= H_RTOL * thr
+
+
+def run_segments(keys, offs, vals=None, strategy=ahs.AUTO, preset=0, in_place=False):
+    """Sorts all segments in one call and checks every segment against the
+    oracle.  Returns the host array of decisions."""
+    nseg = len(offs) - 1
+    say(f"segmented nseg={nseg} n={keys.size} dtype={keys.dtype} payload={vals is not None} "
+        f"strategy={strategy} inplace={in_place} max_seg={int(np.max(np.diff(offs.astype(np.int64)), initial=0))}")
+    k = to_dev(keys)
+    v = to_dev(vals) if vals is not None else None
+    o = to_dev(offs)
+    cfg = ahs.ahs_config_init(preset)
+    if in_place:
+        ko, vo, chosen, feats = ahs.ahs_sort_segmented(k, o, v, strategy, cfg, out=k, out_values=v,
+                                                       want_features=True)
+    else:
+        ko, vo, chosen, feats = ahs.ahs_sort_segmented(k, o, v, strategy, cfg, want_features=True)
+    torch.cuda.synchronize()
+    ko = ko.cpu().numpy()
+    vo = vo.cpu().numpy() if vals is not None else None
+    chosen = chosen.cpu().numpy()
+    fs = ahs.feature_records(feats)
+    ocfg = O.config(preset)
+    for s in range(nseg):
+        a, b = int(offs[s]), int(offs[s + 1])
+        seg = keys[a:b]
+        sv = vals[a:b] if vals is not None else None
+        st, rk, rv, rchosen, rf = O.sort(seg, sv, O.AUTO, ocfg)
+        if st == O.E_NAN:
+            _, mapped, nans = O.map_keys(seg)
+            order = np.argsort(mapped, kind="stable")
+            rk = seg[order]
+            rv = sv[order] if sv is not None else None
+            assert chosen[s] == ahs.SEG_NAN, (s, chosen[s])
+            assert fs[s].n == b - a and fs[s].nan_count == nans
+        else:
+            assert st == O.OK, (s, st)
+            check_features(fs[s], rf)
+            if strategy != ahs.AUTO:
+                assert chosen[s] == strategy, (s, chosen[s])
+            elif chosen[s] != rchosen:
+                assert near_threshold(rf), (s, chosen[s], rchosen)
+        assert np.array_equal(bits(ko[a:b]), bits(rk)), f"segment {s} keys differ (size {b - a})"
+        if vals is not None:
+            assert np.array_equal(vo[a:b], rv), f"segment {s} payload differs"
+    return chosen
+
+
+def mixed_sizes(nseg, seed, cap):
+    sizes = gen.segment_sizes(nseg, seed=seed, lo_exp=0, span_exp=math.log2(cap), cap=cap, lo=0)
+    # boundaries of the method (n_small) and of the LDS path, and empty segments
+    special = [0, 0, 1, 20, 21, 8191, 8192, 8193, 0]
+    sizes[: len(special)] = special
+    return sizes
+
+
+def test_segmented_u32_mixed_auto():
+    keys, offs, _ = gen.segments(nseg=400, seed=21, sizes=mixed_sizes(400, 21, 1 << 15))
+    chosen = run_segments(keys, offs)
+    # every decision occurs in this mix
+    assert {ahs.INSERTION, ahs.COUNTING, ahs.QUICK} <= set(chosen.tolist())
+
+
+def test_segmented_u32_payload():
+    keys, offs, _ = gen.segments(nseg=150, seed=22, sizes=mixed_sizes(150, 22, 1 << 14))
+    run_segments(keys, offs, np.arange(keys.size, dtype=np.uint32))
+
+
+def test_segmented_large_multilevel():
+    """Several segments above the LDS size, one needing more than one level,
+    sorted by the same sample-sort levels together with small ones."""
+    sizes = [(1 << 21) + 3, 9000, 0, 7, 300_000, 8193, 65_536, 5000]
+    keys, offs, _ = gen.segments(nseg=len(sizes), seed=23, sizes=np.array(sizes))
+    run_segments(keys, offs, np.arange(keys.size, dtype=np.uint32))
+    run_segments(keys, offs)
+
+
+def test_segmented_radix_decision():
+    """Large low-entropy segments (few distinct 32-bit values) decide RADIX."""
+    sizes = [200_000, 50_000, 20_000]
+    parts = [gen.zipf_keys(31 + i, s, 64, 1.1, 32) for i, s in enumerate(sizes)]
+    keys = np.concatenate(parts).astype(np.uint32)
+    chosen = run_segments(keys, offsets_of(sizes))
+    assert (chosen == ahs.RADIX).all(), chosen
+
+
+@pytest.mark.parametrize("strategy", [ahs.COUNTING, ahs.RADIX, ahs.QUICK])
+def test_segmented_forced(strategy):
+    keys, offs, _ = gen.segments(nseg=60, seed=24, sizes=mixed_sizes(60, 24, 1 << 15))
+    run_segments(keys, offs, np.arange(keys.size, dtype=np.uint32), strategy=strategy)
+
+
+def test_segmented_u64_payload():
+    sizes = mixed_sizes(80, 25, 1 << 15)
+    sizes[-1] = 40_000
+    n = int(np.sum(sizes))
+    keys = gen.wide_keys("u64zipf4096", n=n)
+    keys[: n // 2] = gen.wide_keys("u64uniform", n=n // 2)
+    run_segments(keys, offsets_of(sizes), np.arange(n, dtype=np.uint32))
+
+
+@pytest.mark.parametrize("case", ["f32normal", "f64normal"])
+def test_segmented_float_with_nan(case):
+    sizes = mixed_sizes(60, 26, 1 << 14)
+    sizes[-2:] = [30_000, 12_000]
+    sizes[10] = 500
+    n = int(np.sum(sizes))
+    keys = gen.wide_keys(case, n=n)
+    offs = offsets_of(sizes)
+    # a small and a large segment with NaNs of both signs
+    for s in (10, len(sizes) - 1):
+        a, b = int(offs[s]), int(offs[s + 1])
+        keys[a + 3] = np.nan
+        keys[b - 2] = -np.nan
+        keys[a + 5] = np.inf
+    chosen = run_segments(keys, offs, np.arange(n, dtype=np.uint32))
+    assert chosen[10] == ahs.SEG_NAN and chosen[-1] == ahs.SEG_NAN
+    assert (chosen[:10] != ahs.SEG_NAN).all()
+
+
+def test_segmented_in_place():
+    keys, offs, _ = gen.segments(nseg=50, seed=27, sizes=mixed_sizes(50, 27, 1 << 15))
+    run_segments(keys, offs, np.arange(keys.size, dtype=np.uint32), in_place=True)
+
+
+def test_segmented_paper_preset():
+    keys, offs, _ = gen.segments(nseg=80, seed=28, sizes=mixed_sizes(80, 28, 1 << 14))
+    run_segments(keys, offs, preset=ahs.PRESET_PAPER_TABLE2)
+
+
+def test_segmented_repeat_and_shrink():
+    """Two calls on one context and workspace, the second smaller: the
+    workspace's counters and tables carry nothing from the first."""
+    k1, o1, _ = gen.segments(nseg=40, seed=29, sizes=mixed_sizes(40, 29, 1 << 16))
+    run_segments(k1, o1)
+    k2, o2, _ = gen.segments(nseg=7, seed=30, sizes=np.array([9000, 3, 0, 12_000, 100, 8192, 8193]))
+    run_segments(k2, o2)
+
+
+def test_segmented_matches_single_array_calls():
+    keys, offs, _ = gen.segments(nseg=12, seed=31, sizes=np.array([5, 20, 21, 3000, 8192, 8193, 20_000, 70_000,
+                                                                   1, 0, 4096, 100_000]))
+    k = to_dev(keys)
+    ko, _, chosen, _ = ahs.ahs_sort_segmented(k, to_dev(offs))
+    chosen = chosen.cpu().tolist()
+    for s in range(len(offs) - 1):
+        a, b = int(offs[s]), int(offs[s + 1])
+        so, _, ch, _ = ahs.ahs_sort(k[a:b].contiguous())
+        assert torch.equal(so, ko[a:b])
+        assert ch == chosen[s], (s, ch, chosen[s])
+
+
+def test_segmented_errors():
+    k = to_dev(np.arange(100, dtype=np.uint32))
+    bad = [np.array([0, 60, 50, 100], np.uint64),   # decreasing
+           np.array([0, 50, 99], np.uint64),        # does not end at n
+           np.array([0, 50, 101], np.uint64)]       # past the end
+    for offs in bad:
+        with pytest.raises(ahs.AhsError) as e:
+            ahs.ahs_sort_segmented(k, to_dev(offs))
+        assert e.value.status == ahs.E_INVALID_ARG
+    cfg = ahs.ahs_config_init()
+    cfg.use_model = 1
+    with pytest.raises(ahs.AhsError) as e:
+        ahs.ahs_sort_segmented(k, to_dev(np.array([0, 100], np.uint64)), cfg=cfg)
+    assert e.value.status == ahs.E_UNSUPPORTED
+    # zero segments is a no-op
+    out, _, chosen, _ = ahs.ahs_sort_segmented(k[:0], to_dev(np.array([0], np.uint64)))
+    assert out.numel() == 0 and chosen.numel() == 0
