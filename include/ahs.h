@@ -169,26 +169,78 @@ ahs_status ahs_sort(ahs_context* ctx, const void* d_keys_in, void* d_keys_out,
  * payload) arrays; d_offsets is a device array of nseg + 1 non-decreasing
  * uint64 with d_offsets[nseg] == n_total.  Each segment's output equals
  * ahs_sort on that segment alone (stable ascending order), and its decision
- * is the FSM of Sec. III-A on its own features.  Segments of at most 8,192
- * keys are sorted wholly in LDS by one fused kernel that also computes the
- * segment's features and decision; larger segments go through the
- * sample-sort levels, all segments together, and get their features from
- * their sorted output (the features do not depend on key order).
+ * is the FSM of Sec. III-A on its own features (the entropy test uses the
+ * device's FP64 log2, so a decision may differ from ahs_select only where
+ * H lies within rounding of h_ratio * log2(nbins)).  Segments of at most
+ * 8,192 keys are queued by size class (up to 1,024 / 2,048 / 4,096 / 8,192
+ * keys) and each class is sorted wholly in LDS by one fused kernel that also
+ * computes the segment's features and decision; larger segments go through
+ * the sample-sort levels (Sec. III-G.1), all of them together, and get their
+ * features from their sorted output (features do not depend on key order).
  * d_chosen (nullable, nseg bytes) receives each segment's strategy code
  * (AHS_* values; 0xFD marks a segment holding NaN keys, whose output is its
- * keys ordered by the bit map with NaNs at the ends).  d_feats (nullable,
- * nseg entries) receives each segment's feature vector.  cfg->use_model is
- * not supported here (AHS_E_UNSUPPORTED).  A forced strategy is reported
- * for every segment.  Invalid offsets give AHS_E_INVALID_ARG before any
- * output is written.  Synchronises the stream once per sample-sort level
- * (2-3 times for segments up to 2^20 keys).  n_total may exceed 2^32;
- * each segment must hold fewer than 2^32 keys. */
+ * keys ordered by the bit map, NaNs at the ends).  d_feats (nullable, nseg
+ * entries) receives each segment's feature vector.  cfg->use_model is not
+ * supported here (AHS_E_UNSUPPORTED).  A forced strategy is reported for
+ * every segment.  In-place (in == out) is allowed.  n_total may exceed
+ * 2^32; each segment must hold fewer than 2^32 keys.  Workspace:
+ * ahs_segmented_workspace_bytes(n_total, nseg, dtype, with_payload).
+ *
+ * ahs_sort_segmented blocks: it reads the classification back once (invalid
+ * offsets give AHS_E_INVALID_ARG before any output is written) and once per
+ * sample-sort level (2-3 reads for segments up to 2^20 keys). */
 size_t ahs_segmented_workspace_bytes(uint64_t n_total, uint32_t nseg, ahs_dtype dtype, int with_payload);
 ahs_status ahs_sort_segmented(ahs_context* ctx, const void* d_keys_in, void* d_keys_out,
                               const uint32_t* d_vals_in, uint32_t* d_vals_out, const uint64_t* d_offsets,
                               uint32_t nseg, uint64_t n_total, ahs_dtype dtype, ahs_strategy requested,
                               const ahs_config* cfg, void* d_ws, size_t ws_bytes, void* stream,
                               uint8_t* d_chosen, ahs_feature_vector* d_feats);
+
+/* Enqueue-only form of ahs_sort_segmented: never synchronises, so it can be
+ * captured in a hipGraph.  Every kernel reads its work count from the
+ * device; the sample sort launches enough levels for segments of at most
+ * max_seg_hint keys (0: n_total) to shrink 64-fold per level, plus one.
+ * Errors found on the device are reported in *d_status (a device uint32,
+ * required), written by the last kernel: 0 success; bit 0 invalid offsets
+ * (nothing else was written); bit 1 sample-sort table overflow; bit 2 a
+ * segment larger than max_seg_hint remained unsplit (its output is not
+ * sorted).  Host-side argument errors return a status as usual. */
+ahs_status ahs_sort_segmented_async(ahs_context* ctx, const void* d_keys_in, void* d_keys_out,
+                                    const uint32_t* d_vals_in, uint32_t* d_vals_out, const uint64_t* d_offsets,
+                                    uint32_t nseg, uint64_t n_total, uint64_t max_seg_hint, ahs_dtype dtype,
+                                    ahs_strategy requested, const ahs_config* cfg, void* d_ws, size_t ws_bytes,
+                                    void* stream, uint8_t* d_chosen, ahs_feature_vector* d_feats,
+                                    uint32_t* d_status);
+
+/* hipGraph of one ahs_sort_segmented_async call with these exact pointers
+ * and sizes (captured on a private stream; the library's event timer is
+ * off while capturing).  ahs_graph_launch replays it on `stream`; the
+ * buffers must stay allocated while the graph lives.  Replays sort whatever
+ * the input buffers hold at replay time. */
+typedef struct ahs_graph ahs_graph;
+ahs_status ahs_sort_segmented_capture(ahs_context* ctx, const void* d_keys_in, void* d_keys_out,
+                                      const uint32_t* d_vals_in, uint32_t* d_vals_out, const uint64_t* d_offsets,
+                                      uint32_t nseg, uint64_t n_total, uint64_t max_seg_hint, ahs_dtype dtype,
+                                      ahs_strategy requested, const ahs_config* cfg, void* d_ws, size_t ws_bytes,
+                                      uint8_t* d_chosen, ahs_feature_vector* d_feats, uint32_t* d_status,
+                                      ahs_graph** out);
+ahs_status ahs_graph_launch(ahs_graph* graph, void* stream);
+void ahs_graph_destroy(ahs_graph* graph);
+
+/* Size-class kernel variants of the batched sort.  h_caps[4] holds, for the
+ * classes up to 1,024 / 2,048 / 4,096 / 8,192 keys, the LDS capacity of the
+ * kernel variant that sorts it (1,024 / 2,048 / 4,096 with 256 threads, or
+ * 8,192 with 512 threads; a class's variant must cover it).  Every variant
+ * gives identical results; only speed differs.  ahs_segmented_autotune
+ * times every admissible variant per class on synthetic segments (about
+ * 2^22 keys per class, allocated and freed inside the call), keeps the
+ * fastest in the context for (dtype, with_payload) and reports the choice
+ * (h_caps, nullable) and its kernel time in ms (h_ms[4], nullable).  It
+ * synchronises the stream. */
+ahs_status ahs_segmented_autotune(ahs_context* ctx, ahs_dtype dtype, int with_payload, void* stream, int* h_caps,
+                                  double* h_ms);
+ahs_status ahs_segmented_get_variants(ahs_context* ctx, ahs_dtype dtype, int with_payload, int* h_caps);
+ahs_status ahs_segmented_set_variants(ahs_context* ctx, ahs_dtype dtype, int with_payload, const int* h_caps);
 
 /* Learned predictor (Sec. III-H, Listing 5): gradient-boosted trees over
  * (n, k, H) in the project's text format

@@ -89,6 +89,15 @@ def lib():
             "ahs_segmented_workspace_bytes": (sz, [u64, u32, i32, i32]),
             "ahs_sort_segmented": (i32, [vp, vp, vp, vp, vp, vp, u32, u64, i32, i32, C.POINTER(Config), vp, sz,
                                          vp, vp, vp]),
+            "ahs_sort_segmented_async": (i32, [vp, vp, vp, vp, vp, vp, u32, u64, u64, i32, i32, C.POINTER(Config),
+                                               vp, sz, vp, vp, vp, vp]),
+            "ahs_sort_segmented_capture": (i32, [vp, vp, vp, vp, vp, vp, u32, u64, u64, i32, i32,
+                                                 C.POINTER(Config), vp, sz, vp, vp, vp, C.POINTER(vp)]),
+            "ahs_graph_launch": (i32, [vp, vp]),
+            "ahs_graph_destroy": (None, [vp]),
+            "ahs_segmented_autotune": (i32, [vp, i32, i32, vp, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+            "ahs_segmented_get_variants": (i32, [vp, i32, i32, C.POINTER(C.c_int)]),
+            "ahs_segmented_set_variants": (i32, [vp, i32, i32, C.POINTER(C.c_int)]),
             "ahs_model_load": (i32, [C.c_char_p, C.POINTER(vp)]),
             "ahs_model_free": (None, [vp]),
             "ahs_model_predict": (i32, [vp, C.POINTER(FeatureVector), C.POINTER(C.c_int)]),
@@ -299,17 +308,10 @@ def ahs_segmented_workspace_bytes(n_total: int, nseg: int, dtype: int, with_payl
     return lib().ahs_segmented_workspace_bytes(n_total, nseg, dtype, 1 if with_payload else 0)
 
 
-def ahs_sort_segmented(keys: torch.Tensor, offsets: torch.Tensor, values: torch.Tensor | None = None,
-                       strategy: int | str = AUTO, cfg: Config | None = None, out: torch.Tensor | None = None,
-                       out_values: torch.Tensor | None = None, dtype: int | None = None,
-                       ctx: Context | None = None, stream=None, want_chosen: bool = True,
-                       want_features: bool = False):
-    """Sorts nseg independent segments of one device array in one call.
+SEG_ERR_OFFSETS, SEG_ERR_OVERFLOW, SEG_ERR_LEVELS = 1, 2, 4  # bits of the enqueue-only status word
 
-    ``offsets`` is a device int64/uint64 tensor of nseg + 1 non-decreasing
-    boundaries ending at keys.numel().  Returns (keys_out, values_out or None,
-    chosen (device uint8 tensor of nseg decisions) or None, features (device
-    tensor of nseg FeatureVector records, viewed as bytes) or None)."""
+
+def _seg_prepare(keys, offsets, values, strategy, out, out_values, dtype, ctx, want_chosen, want_features):
     if isinstance(strategy, str):
         strategy = STRATEGY_CODES[strategy]
     code = dtype_code(keys, dtype)
@@ -330,11 +332,27 @@ def ahs_sort_segmented(keys: torch.Tensor, offsets: torch.Tensor, values: torch.
             out_values = torch.empty_like(values)
     elif out_values is not None:
         raise ValueError("out_values given without values")
-    wsb = ahs_segmented_workspace_bytes(n, nseg, code, values is not None)
-    ws = ctx.workspace(wsb)
     chosen = torch.empty(nseg, dtype=torch.uint8, device=keys.device) if want_chosen else None
     feats = (torch.empty(nseg * C.sizeof(FeatureVector), dtype=torch.uint8, device=keys.device)
              if want_features else None)
+    return strategy, code, nseg, n, ctx, out, out_values, chosen, feats
+
+
+def ahs_sort_segmented(keys: torch.Tensor, offsets: torch.Tensor, values: torch.Tensor | None = None,
+                       strategy: int | str = AUTO, cfg: Config | None = None, out: torch.Tensor | None = None,
+                       out_values: torch.Tensor | None = None, dtype: int | None = None,
+                       ctx: Context | None = None, stream=None, want_chosen: bool = True,
+                       want_features: bool = False):
+    """Sorts nseg independent segments of one device array in one call.
+
+    ``offsets`` is a device int64/uint64 tensor of nseg + 1 non-decreasing
+    boundaries ending at keys.numel().  Returns (keys_out, values_out or None,
+    chosen (device uint8 tensor of nseg decisions) or None, features (device
+    tensor of nseg FeatureVector records, viewed as bytes) or None)."""
+    strategy, code, nseg, n, ctx, out, out_values, chosen, feats = _seg_prepare(
+        keys, offsets, values, strategy, out, out_values, dtype, ctx, want_chosen, want_features)
+    wsb = ahs_segmented_workspace_bytes(n, nseg, code, values is not None)
+    ws = ctx.workspace(wsb)
     vp = (lambda t: C.c_void_p(t.data_ptr()) if t is not None else None)
     st = lib().ahs_sort_segmented(ctx.handle, vp(keys), vp(out), vp(values), vp(out_values), vp(offsets), nseg, n,
                                   code, strategy, C.byref(cfg) if cfg is not None else None,
@@ -343,6 +361,97 @@ def ahs_sort_segmented(keys: torch.Tensor, offsets: torch.Tensor, values: torch.
     if st != OK:
         _raise(st, ctx)
     return out, out_values, chosen, feats
+
+
+def ahs_sort_segmented_async(keys: torch.Tensor, offsets: torch.Tensor, values: torch.Tensor | None = None,
+                             strategy: int | str = AUTO, cfg: Config | None = None, out: torch.Tensor | None = None,
+                             out_values: torch.Tensor | None = None, dtype: int | None = None,
+                             ctx: Context | None = None, stream=None, max_seg_hint: int = 0,
+                             want_chosen: bool = True, want_features: bool = False, ws: torch.Tensor | None = None):
+    """Enqueue-only batched sort (no host synchronisation).  Returns (keys_out,
+    values_out, chosen, features, status) where status is a device uint32
+    tensor of one element: 0 on success, else SEG_ERR_* bits.  ``ws`` (a
+    device byte tensor of at least ahs_segmented_workspace_bytes) keeps the
+    workspace fixed across calls; by default the context's is used."""
+    strategy, code, nseg, n, ctx, out, out_values, chosen, feats = _seg_prepare(
+        keys, offsets, values, strategy, out, out_values, dtype, ctx, want_chosen, want_features)
+    wsb = ahs_segmented_workspace_bytes(n, nseg, code, values is not None)
+    if ws is None:
+        ws = ctx.workspace(wsb)
+    status = torch.empty(1, dtype=torch.int32, device=keys.device)
+    vp = (lambda t: C.c_void_p(t.data_ptr()) if t is not None else None)
+    st = lib().ahs_sort_segmented_async(ctx.handle, vp(keys), vp(out), vp(values), vp(out_values), vp(offsets), nseg,
+                                        n, max_seg_hint, code, strategy,
+                                        C.byref(cfg) if cfg is not None else None, C.c_void_p(ws.data_ptr()),
+                                        ws.numel(), _stream_handle(stream), vp(chosen), vp(feats), vp(status))
+    if st != OK:
+        _raise(st, ctx)
+    return out, out_values, chosen, feats, status
+
+
+class SegmentedGraph:
+    """hipGraph of one enqueue-only batched sort over fixed buffers.  The
+    object keeps every buffer the graph uses alive; launch() replays it."""
+
+    def __init__(self, keys, offsets, values=None, strategy=AUTO, cfg=None, out=None, out_values=None, dtype=None,
+                 ctx=None, max_seg_hint=0, want_chosen=True, want_features=False):
+        strategy, code, nseg, n, ctx, out, out_values, chosen, feats = _seg_prepare(
+            keys, offsets, values, strategy, out, out_values, dtype, ctx, want_chosen, want_features)
+        self.ws = torch.empty(ahs_segmented_workspace_bytes(n, nseg, code, values is not None), dtype=torch.uint8,
+                              device=keys.device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=keys.device)
+        self.keys, self.offsets, self.values, self.out, self.out_values = keys, offsets, values, out, out_values
+        self.chosen, self.feats, self.ctx, self.cfg = chosen, feats, ctx, cfg
+        torch.cuda.synchronize(keys.device)
+        vp = (lambda t: C.c_void_p(t.data_ptr()) if t is not None else None)
+        h = C.c_void_p()
+        st = lib().ahs_sort_segmented_capture(ctx.handle, vp(keys), vp(out), vp(values), vp(out_values),
+                                              vp(offsets), nseg, n, max_seg_hint, code, strategy,
+                                              C.byref(cfg) if cfg is not None else None,
+                                              C.c_void_p(self.ws.data_ptr()), self.ws.numel(), vp(chosen),
+                                              vp(feats), vp(self.status), C.byref(h))
+        if st != OK:
+            _raise(st, ctx)
+        self.handle = h
+
+    def launch(self, stream=None):
+        st = lib().ahs_graph_launch(self.handle, _stream_handle(stream))
+        if st != OK:
+            _raise(st)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.ahs_graph_destroy(self.handle)
+            self.handle = None
+
+
+def ahs_segmented_autotune(dtype: int, with_payload: bool = False, ctx: Context | None = None, stream=None):
+    """Times every admissible LDS kernel variant per size class and keeps the
+    fastest in the context.  Returns ([capacity per class], [ms per class])."""
+    ctx = ctx or default_context()
+    caps = (C.c_int * 4)()
+    ms = (C.c_double * 4)()
+    st = lib().ahs_segmented_autotune(ctx.handle, dtype, 1 if with_payload else 0, _stream_handle(stream), caps, ms)
+    if st != OK:
+        _raise(st, ctx)
+    return list(caps), list(ms)
+
+
+def ahs_segmented_get_variants(dtype: int, with_payload: bool = False, ctx: Context | None = None):
+    ctx = ctx or default_context()
+    caps = (C.c_int * 4)()
+    st = lib().ahs_segmented_get_variants(ctx.handle, dtype, 1 if with_payload else 0, caps)
+    if st != OK:
+        _raise(st, ctx)
+    return list(caps)
+
+
+def ahs_segmented_set_variants(dtype: int, caps, with_payload: bool = False, ctx: Context | None = None):
+    ctx = ctx or default_context()
+    arr = (C.c_int * 4)(*caps)
+    st = lib().ahs_segmented_set_variants(ctx.handle, dtype, 1 if with_payload else 0, arr)
+    if st != OK:
+        _raise(st, ctx)
 
 
 def feature_records(feats: torch.Tensor) -> list:

@@ -1,5 +1,7 @@
-// In-LDS stable sort of up to SS_CAP keys by one workgroup, and the run
-// statistics of a sorted key array (for features computed after sorting).
+// In-LDS stable sort of up to CAP keys by one workgroup of NT threads, and
+// the run statistics of a sorted key array (for features computed after
+// sorting).  NT >= 256 (one thread per digit) and CAP / NT <= 16 (the run
+// scratch of CAP words reuses the rank slots).
 #pragma once
 
 #include "onesweep.hpp"
@@ -7,26 +9,27 @@
 
 namespace ahs {
 
-template <typename K, bool PAY>
+template <typename K, bool PAY, int CAP = SS_CAP, int NT = SS_THREADS>
 struct BlockSortSmem {
-  RankSlot slot[SS_THREADS / WAVE][256];
+  static_assert(NT >= 256 && CAP % NT == 0 && CAP / NT <= 16, "block sort shape");
+  static constexpr int cap = CAP, nt = NT, nw = NT / WAVE;
+  RankSlot slot[NT / WAVE][256];
   uint32_t tstart[256];
-  K keys[SS_CAP];
-  uint32_t vals[PAY ? SS_CAP : 1];
-  uint32_t scan[SS_THREADS / WAVE + 1];
-  K red[2][SS_THREADS / WAVE];
-  double dred[SS_THREADS / WAVE];
+  K keys[CAP];
+  uint32_t vals[PAY ? CAP : 1];
+  uint32_t scan[NT / WAVE + 1];
+  K red[2][NT / WAVE];
+  double dred[NT / WAVE];
   uint32_t misc[4];
 };
 
 // Loads `size` keys (mapping raw float bit patterns when `raw`) and
 // payloads into LDS.  Ends with a barrier.
-template <int KK, bool PAY>
-__device__ __forceinline__ void lds_load_mapped(BlockSortSmem<typename KeyTraits<KK>::K, PAY>& sm,
-                                                const typename KeyTraits<KK>::K* __restrict__ src,
+template <int KK, bool PAY, typename SM>
+__device__ __forceinline__ void lds_load_mapped(SM& sm, const typename KeyTraits<KK>::K* __restrict__ src,
                                                 const uint32_t* __restrict__ vsrc, uint32_t size, bool raw) {
   using K = typename KeyTraits<KK>::K;
-  for (uint32_t j = threadIdx.x; j < size; j += SS_THREADS) {
+  for (uint32_t j = threadIdx.x; j < size; j += SM::nt) {
     K x = src[j];
     if constexpr (KeyTraits<KK>::FLT) x = raw ? fmap(x) : x;
     sm.keys[j] = x;
@@ -38,13 +41,14 @@ __device__ __forceinline__ void lds_load_mapped(BlockSortSmem<typename KeyTraits
 // Stable LSD sort of sm.keys[0, size) (mapped keys) by 8-bit digits of
 // (key - min), as many passes as the span needs; payloads move along.
 // Returns min and max (mapped).  Ends with a barrier.
-template <typename K, bool PAY>
-__device__ __forceinline__ void lds_sort_loaded(BlockSortSmem<K, PAY>& sm, uint32_t size, K& out_min, K& out_max) {
-  constexpr int IPT = SS_CAP / SS_THREADS;
-  constexpr int NW = SS_THREADS / WAVE;
+template <typename K, bool PAY, int CAP, int NT>
+__device__ __forceinline__ void lds_sort_loaded(BlockSortSmem<K, PAY, CAP, NT>& sm, uint32_t size, K& out_min,
+                                                K& out_max) {
+  constexpr int IPT = CAP / NT;
+  constexpr int NW = NT / WAVE;
   const int t = threadIdx.x, w = t / WAVE, lane = lane_id();
   K mn = ~K(0), mx = K(0);
-  for (uint32_t j = t; j < size; j += SS_THREADS) {
+  for (uint32_t j = t; j < size; j += NT) {
     const K x = sm.keys[j];
     mn = x < mn ? x : mn;
     mx = x > mx ? x : mx;
@@ -52,7 +56,7 @@ __device__ __forceinline__ void lds_sort_loaded(BlockSortSmem<K, PAY>& sm, uint3
   mn = wave_min(mn);
   mx = wave_max(mx);
   if (lane == 0) { sm.red[0][w] = mn; sm.red[1][w] = mx; }
-  for (int i = t; i < NW * 256; i += SS_THREADS) (&sm.slot[0][0])[i].mask = 0ull;
+  for (int i = t; i < NW * 256; i += NT) (&sm.slot[0][0])[i].mask = 0ull;
   __syncthreads();
   mn = sm.red[0][0];
   mx = sm.red[1][0];
@@ -83,20 +87,20 @@ __device__ __forceinline__ void lds_sort_loaded(BlockSortSmem<K, PAY>& sm, uint3
         d[i] = 255u;
       }
     }
-    for (int i = t; i < NW * 256; i += SS_THREADS) (&sm.slot[0][0])[i].count = 0u;
+    for (int i = t; i < NW * 256; i += NT) (&sm.slot[0][0])[i].count = 0u;
     __syncthreads();
     uint32_t r[IPT];
     rank_wave_items<IPT>(d, r, sm.slot[w]);
     __syncthreads();
     const uint32_t cnt = wave_prefix_per_digit<NW>(sm.slot);
     uint32_t total;
-    const uint32_t tstart = block_excl_scan<SS_THREADS>(t < 256 ? cnt : 0u, sm.scan, total);
+    const uint32_t tstart = block_excl_scan<NT>(t < 256 ? cnt : 0u, sm.scan, total);
     if (t < 256) sm.tstart[t] = tstart;
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
       const uint32_t lp = sm.tstart[d[i]] + sm.slot[w][d[i]].count + r[i];
-      if (lp < (uint32_t)SS_CAP) {
+      if (lp < (uint32_t)CAP) {
         sm.keys[lp] = k[i];
         if constexpr (PAY) sm.vals[lp] = v[i];
       }
@@ -113,12 +117,12 @@ __device__ __forceinline__ void lds_sort_loaded(BlockSortSmem<K, PAY>& sm, uint3
 // carry_start is the segment position where the run open at the chunk's
 // start began; it is updated to the start of the run open at the chunk's end.
 // Returns the block's FP64 sum (valid in every thread).  Uses sm.slot as
-// scratch for run starts (SS_CAP u32 entries fit in it).
-template <typename K, bool PAY>
-__device__ __forceinline__ double lds_run_entropy(BlockSortSmem<K, PAY>& sm, uint32_t cnt, uint64_t pos0, K prev_key,
-                                                  bool has_prev, K next_key, bool has_next, K kmin, uint32_t shift,
-                                                  uint64_t n, uint64_t& carry_start) {
-  constexpr int CH = SS_CAP / SS_THREADS;  // consecutive positions per thread
+// scratch for run starts (CAP u32 entries fit in it).
+template <typename K, bool PAY, int CAP, int NT>
+__device__ __forceinline__ double lds_run_entropy(BlockSortSmem<K, PAY, CAP, NT>& sm, uint32_t cnt, uint64_t pos0,
+                                                  K prev_key, bool has_prev, K next_key, bool has_next, K kmin,
+                                                  uint32_t shift, uint64_t n, uint64_t& carry_start) {
+  constexpr int CH = CAP / NT;  // consecutive positions per thread
   const int t = threadIdx.x;
   uint32_t* s_start = reinterpret_cast<uint32_t*>(&sm.slot[0][0]);  // run starts (chunk-relative)
   const uint32_t j0 = (uint32_t)t * CH;
@@ -135,7 +139,7 @@ __device__ __forceinline__ double lds_run_entropy(BlockSortSmem<K, PAY>& sm, uin
     if (st) { ++nst; startbits |= 1u << q; }
   }
   uint32_t total;
-  uint32_t r = block_excl_scan<SS_THREADS>(nst, sm.scan, total);
+  uint32_t r = block_excl_scan<NT>(nst, sm.scan, total);
   for (int q = 0; q < CH; ++q)
     if (startbits >> q & 1u) s_start[r++] = j0 + q;
   __syncthreads();
@@ -164,7 +168,7 @@ __device__ __forceinline__ double lds_run_entropy(BlockSortSmem<K, PAY>& sm, uin
   __syncthreads();
   double sum = 0.0;
 #pragma unroll
-  for (int i = 0; i < SS_THREADS / WAVE; ++i) sum += sm.dred[i];
+  for (int i = 0; i < NT / WAVE; ++i) sum += sm.dred[i];
   __syncthreads();
   return sum;
 }

@@ -56,7 +56,7 @@ hipEvent_t ahs_context::take_event() {
 }
 
 void ahs_context::prof_begin(const char* name, hipStream_t s, double bytes) {
-  if (!profiling) return;
+  if (!profiling || capturing) return;
   Rec r;
   r.name = name;
   r.bytes = bytes;
@@ -67,7 +67,7 @@ void ahs_context::prof_begin(const char* name, hipStream_t s, double bytes) {
 }
 
 void ahs_context::prof_end(hipStream_t s) {
-  if (!profiling || pending.empty()) return;
+  if (!profiling || capturing || pending.empty()) return;
   hipEventRecord(pending.back().b, s);
 }
 

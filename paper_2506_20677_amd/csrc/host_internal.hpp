@@ -35,9 +35,17 @@ struct ahs_context {
     double ms = 0.0, bytes = 0.0;
   };
   bool profiling = false;
+  bool capturing = false;  // a stream capture is recording: no timing events
   std::vector<Rec> pending;
   std::vector<hipEvent_t> event_pool;
   std::map<std::string, Total> totals;
+
+  // Batched sort: LDS kernel variant (0..3, capacity 1024 << v) per key
+  // type, payload flag and size class; set by the autotuner.
+  int seg_variant[4][2][4] = {{{0, 1, 2, 3}, {0, 1, 2, 3}},
+                              {{0, 1, 2, 3}, {0, 1, 2, 3}},
+                              {{0, 1, 2, 3}, {0, 1, 2, 3}},
+                              {{0, 1, 2, 3}, {0, 1, 2, 3}}};
 
   ~ahs_context();
   ahs_status fail(ahs_status s, const char* fmt, ...);
@@ -47,6 +55,14 @@ struct ahs_context {
   void prof_end(hipStream_t s);
   void prof_collect();
 };
+
+#define AHS_TRY(expr)                    \
+  do {                                   \
+    ahs_status st__ = (expr);            \
+    if (st__ != AHS_OK) return st__;     \
+  } while (0)
+
+#define AHS_HIP(j, call, what) AHS_TRY((j).ctx->check((call), (what)))
 
 namespace ahs {
 

@@ -58,40 +58,54 @@ __global__ void k_ss_init(SsSeg* segs, SsItem* items, uint64_t n) {
 }
 
 // ------------------------------------------------------------------ sample + splitters
-// One block per segment: SS_SAMPLES keys at pseudo-random positions, sorted
-// in LDS by a bitonic network; splitter i is sample (i + 1) * 32.
+// One block per segment (grid stride): SS_SAMPLES keys at pseudo-random
+// positions, sorted in LDS by a bitonic network; splitter i is sample
+// (i + 1) * 32.  Also clears the segment's bucket counts.
 template <int KK>
 __global__ __launch_bounds__(SS_THREADS) void k_ss_sample(const typename KeyTraits<KK>::K* __restrict__ src,
-                                                          int map_in, const SsSeg* __restrict__ segs,
+                                                          int map_in, const SsSeg* __restrict__ segs, SsLevelIn lv,
                                                           typename KeyTraits<KK>::K* __restrict__ spl,
-                                                          uint64_t seed) {
+                                                          uint32_t* __restrict__ counts, uint64_t seed) {
   using K = typename KeyTraits<KK>::K;
   __shared__ K s[SS_SAMPLES];
-  const SsSeg sg = segs[blockIdx.x];
   const int t = threadIdx.x;
-  const uint64_t base = ss_mix(seed ^ (sg.start * 0x9E3779B97F4A7C15ull));
-  for (int j = t; j < SS_SAMPLES; j += SS_THREADS) {
-    const uint64_t h = ss_mix(base + (uint64_t)(j + 1) * 0x9E3779B97F4A7C15ull);
-    const uint64_t pos = sg.start + (((h >> 32) * (uint64_t)sg.size) >> 32);
-    K x = src[pos];
-    if constexpr (KeyTraits<KK>::FLT) x = map_in ? fmap(x) : x;
-    s[j] = x;
-  }
-  __syncthreads();
-  for (int k = 2; k <= SS_SAMPLES; k <<= 1) {
-    for (int jj = k >> 1; jj > 0; jj >>= 1) {
-      for (int i = t; i < SS_SAMPLES; i += SS_THREADS) {
-        const int ixj = i ^ jj;
-        if (ixj > i) {
-          const K a = s[i], b = s[ixj];
-          const bool up = (i & k) == 0;
-          if ((a > b) == up) { s[i] = b; s[ixj] = a; }
-        }
-      }
-      __syncthreads();
+  const uint32_t nsegs = lv.segs_n();
+  for (uint32_t sidx = blockIdx.x; sidx < nsegs; sidx += gridDim.x) {
+    __syncthreads();  // the previous segment's splitters have been read
+    const SsSeg sg = segs[sidx];
+    for (int b = t; b < SS_NB; b += SS_THREADS) counts[(size_t)sidx * SS_NB + b] = 0u;
+    const uint64_t base = ss_mix(seed ^ (sg.start * 0x9E3779B97F4A7C15ull));
+    for (int j = t; j < SS_SAMPLES; j += SS_THREADS) {
+      const uint64_t h = ss_mix(base + (uint64_t)(j + 1) * 0x9E3779B97F4A7C15ull);
+      const uint64_t pos = sg.start + (((h >> 32) * (uint64_t)sg.size) >> 32);
+      K x = src[pos];
+      if constexpr (KeyTraits<KK>::FLT) x = map_in ? fmap(x) : x;
+      s[j] = x;
     }
+    __syncthreads();
+    for (int k = 2; k <= SS_SAMPLES; k <<= 1) {
+      for (int jj = k >> 1; jj > 0; jj >>= 1) {
+        for (int i = t; i < SS_SAMPLES; i += SS_THREADS) {
+          const int ixj = i ^ jj;
+          if (ixj > i) {
+            const K a = s[i], b = s[ixj];
+            const bool up = (i & k) == 0;
+            if ((a > b) == up) { s[i] = b; s[ixj] = a; }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int i = t; i < SS_P; i += SS_THREADS) spl[(size_t)sidx * 256 + i] = s[(i + 1) * (SS_SAMPLES / 256)];
   }
-  for (int i = t; i < SS_P; i += SS_THREADS) spl[(size_t)blockIdx.x * 256 + i] = s[(i + 1) * (SS_SAMPLES / 256)];
+}
+
+// Clears the status words of the level's tiles.
+__global__ __launch_bounds__(256) void k_ss_zero_status(u32x4* __restrict__ status, SsLevelIn lv,
+                                                        uint32_t words_per_tile) {
+  const uint64_t nvec = (uint64_t)lv.tiles_n() * words_per_tile / 4;
+  const u32x4 z = {0u, 0u, 0u, 0u};
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < nvec; i += (uint64_t)gridDim.x * 256) status[i] = z;
 }
 
 // ------------------------------------------------------------------ counting
@@ -100,14 +114,15 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_sample(const typename KeyTrai
 // counters whenever the segment changes.
 template <int KK>
 __global__ __launch_bounds__(SS_THREADS) void k_ss_count(const typename KeyTraits<KK>::K* __restrict__ src, int map_in,
-                                                         const SsSeg* __restrict__ segs, uint32_t nsegs,
-                                                         uint32_t ntiles, uint32_t tile_keys,
+                                                         const SsSeg* __restrict__ segs, SsLevelIn lv,
+                                                         uint32_t tile_keys,
                                                          const typename KeyTraits<KK>::K* __restrict__ spl,
                                                          uint32_t* __restrict__ counts) {
   using K = typename KeyTraits<KK>::K;
   __shared__ K s_spl[256];
   __shared__ uint32_t s_cnt[SS_NB];
   const int t = threadIdx.x;
+  const uint32_t nsegs = lv.segs_n(), ntiles = lv.tiles_n();
   const uint32_t per = (ntiles + gridDim.x - 1) / gridDim.x;
   const uint32_t t0 = blockIdx.x * per;
   const uint32_t t1 = t0 + per < ntiles ? t0 + per : ntiles;
@@ -155,23 +170,16 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_count(const typename KeyTrait
 }
 
 // ------------------------------------------------------------------ plan
-// One block per segment: bucket start positions (exclusive scan of the
-// counts from the segment start) and the fate of every bucket: equal-key
-// buckets are final (copied out unless already in place), buckets of at
-// most SS_CAP keys become block-sort items, larger ones next-level segments.
-__global__ __launch_bounds__(SS_NB) void k_ss_plan(const SsSeg* __restrict__ segs, const uint32_t* __restrict__ counts,
-                                                   uint32_t* __restrict__ offs, uint32_t dst_buf, int copy_in_place,
-                                                   SsSeg* __restrict__ next, SsItem* __restrict__ items,
-                                                   SsCounters* __restrict__ ctr, uint32_t item_cap,
-                                                   uint32_t seg_cap) {
-  __shared__ uint32_t sm[SS_NB / WAVE + 1];
-  const SsSeg sg = segs[blockIdx.x];
-  const int b = threadIdx.x;
-  const uint32_t c = counts[(size_t)blockIdx.x * SS_NB + b];
-  uint32_t total;
-  const uint32_t ex = block_excl_scan<SS_NB>(c, sm, total);
+// One block per segment (grid stride): bucket start positions (exclusive
+// scan of the counts from the segment start) and the fate of every bucket:
+// equal-key buckets are final (copied out unless already in place), buckets
+// of at most SS_CAP keys become block-sort items, larger ones next-level
+// segments.
+__device__ __forceinline__ void ss_plan_bucket(const SsSeg& sg, uint32_t b, uint32_t c, uint32_t ex, uint32_t dst_buf,
+                                               int copy_in_place, SsSeg* __restrict__ next,
+                                               SsItem* __restrict__ items, SsCounters* __restrict__ ctr,
+                                               uint32_t item_cap, uint32_t seg_cap) {
   const uint64_t pos = sg.start + ex;
-  offs[(size_t)blockIdx.x * SS_NB + b] = ex;  // relative to the segment start
   if (c == 0) return;
   if (b & 1) {
     if (dst_buf == SS_BUF_OUT && !copy_in_place) return;
@@ -207,6 +215,24 @@ __global__ __launch_bounds__(SS_NB) void k_ss_plan(const SsSeg* __restrict__ seg
   }
 }
 
+__global__ __launch_bounds__(SS_NB) void k_ss_plan(const SsSeg* __restrict__ segs, SsLevelIn lv,
+                                                   const uint32_t* __restrict__ counts, uint32_t* __restrict__ offs,
+                                                   uint32_t dst_buf, int copy_in_place, SsSeg* __restrict__ next,
+                                                   SsItem* __restrict__ items, SsCounters* __restrict__ ctr,
+                                                   uint32_t item_cap, uint32_t seg_cap) {
+  __shared__ uint32_t sm[SS_NB / WAVE + 1];
+  const uint32_t nsegs = lv.segs_n();
+  const int b = threadIdx.x;
+  for (uint32_t sidx = blockIdx.x; sidx < nsegs; sidx += gridDim.x) {
+    const SsSeg sg = segs[sidx];
+    const uint32_t c = counts[(size_t)sidx * SS_NB + b];
+    uint32_t total;
+    const uint32_t ex = block_excl_scan<SS_NB>(c, sm, total);  // ends with a barrier
+    offs[(size_t)sidx * SS_NB + b] = ex;  // relative to the segment start
+    ss_plan_bucket(sg, (uint32_t)b, c, ex, dst_buf, copy_in_place, next, items, ctr, item_cap, seg_cap);
+  }
+}
+
 // One block: first_tile of every next-level segment (exclusive scan of its
 // tile count) and the level's total tile count.
 constexpr int SS_TILES_THREADS = 1024;
@@ -234,7 +260,10 @@ __global__ __launch_bounds__(SS_TILES_THREADS) void k_ss_tiles(SsSeg* __restrict
 // ------------------------------------------------------------------ scatter
 // Segmented single-pass stable scatter by bucket id (512 ids): the onesweep
 // tile machinery with the splitter classifier as the digit, a look-back
-// chain per segment and per-segment bucket offsets.
+// chain per segment and per-segment bucket offsets.  Workgroups take tiles
+// in order from an atomic counter until none is left (one tile each when
+// the grid has one workgroup per tile); a workgroup only ever waits on
+// tiles taken earlier by running workgroups, so any grid size is safe.
 template <int KK, bool PAY, int IPT, typename ST>
 __global__ __launch_bounds__(SS_THREADS) void k_ss_scatter(SsScatterArgs a) {
   using K = typename KeyTraits<KK>::K;
@@ -254,118 +283,130 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_scatter(SsScatterArgs a) {
   __shared__ uint32_t s_tile;
 
   const int t = threadIdx.x, w = t / WAVE, lane = lane_id();
-  for (int i = t; i < NW * SS_NB; i += SS_THREADS) {
-    (&s_slot[0][0])[i].mask = 0ull;
-    (&s_slot[0][0])[i].count = 0u;
-  }
-  if (t == 0) s_tile = add_agent(a.tile_counter, 1u);
-  __syncthreads();
-  const uint32_t tile = s_tile;
-  const uint32_t sidx = ss_seg_of_tile(a.segs, a.nsegs, tile);
-  const SsSeg sg = a.segs[sidx];
-  for (int i = t; i < SS_P; i += SS_THREADS) s_spl[i] = ((const K*)a.spl)[(size_t)sidx * 256 + i];
-  const uint64_t off = (uint64_t)(tile - sg.first_tile) * TILE;
-  const uint64_t rem = (uint64_t)sg.size - off;
-  const uint32_t valid = rem < (uint64_t)TILE ? (uint32_t)rem : (uint32_t)TILE;
-  const K* __restrict__ src = (const K*)a.src + sg.start + off;
-  const uint32_t* __restrict__ vsrc = PAY ? a.vsrc + sg.start + off : nullptr;
-
-  K k[IPT];
-  uint32_t v[IPT];
-  uint32_t d[IPT];
-  const uint32_t wbase = (uint32_t)w * WAVE * IPT;
-#pragma unroll
-  for (int i = 0; i < IPT; ++i) {
-    const uint32_t idx = wbase + (uint32_t)i * WAVE + lane;
-    k[i] = src[idx < valid ? idx : valid - 1];
-    if constexpr (PAY) v[i] = vsrc[idx < valid ? idx : valid - 1];
-  }
-  __syncthreads();  // splitters in LDS
-#pragma unroll
-  for (int i = 0; i < IPT; ++i) {
-    const uint32_t idx = wbase + (uint32_t)i * WAVE + lane;
-    K x = k[i];
-    if constexpr (KeyTraits<KK>::FLT) x = a.map_in ? fmap(x) : x;
-    if (idx < valid) {
-      k[i] = x;
-      d[i] = ss_classify<K>(x, s_spl);
-    } else {
-      k[i] = ~K(0);
-      d[i] = SS_NB - 1;
+  const uint32_t ntiles = a.lv.tiles_n(), nsegs = a.lv.segs_n();
+  for (;;) {
+    __syncthreads();  // the previous tile's LDS contents have been consumed
+    for (int i = t; i < NW * SS_NB; i += SS_THREADS) {
+      (&s_slot[0][0])[i].mask = 0ull;
+      (&s_slot[0][0])[i].count = 0u;
     }
-  }
+    if (t == 0) s_tile = add_agent(a.tile_counter, 1u);
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    if (tile >= ntiles) break;
+    const uint32_t sidx = ss_seg_of_tile(a.segs, nsegs, tile);
+    const SsSeg sg = a.segs[sidx];
+    for (int i = t; i < SS_P; i += SS_THREADS) s_spl[i] = ((const K*)a.spl)[(size_t)sidx * 256 + i];
+    const uint64_t off = (uint64_t)(tile - sg.first_tile) * TILE;
+    const uint64_t rem = (uint64_t)sg.size - off;
+    const uint32_t valid = rem < (uint64_t)TILE ? (uint32_t)rem : (uint32_t)TILE;
+    const K* __restrict__ src = (const K*)a.src + sg.start + off;
+    const uint32_t* __restrict__ vsrc = PAY ? a.vsrc + sg.start + off : nullptr;
 
-  uint32_t r[IPT];
-  rank_wave_items<IPT>(d, r, s_slot[w]);
-  __syncthreads();
-
-  uint32_t cnt = wave_prefix_per_digit<NW, SS_NB>(s_slot);
-  if (t == SS_NB - 1) cnt -= (uint32_t)TILE - valid;  // padding: last id, sorted last
-  uint32_t total;
-  const uint32_t tstart = block_excl_scan<SS_THREADS>(cnt, s_scan, total);
-  s_tstart[t] = tstart;
-  const uint64_t excl = lookback<SS_NB, ST>((ST*)a.status, tile, sg.first_tile, (uint32_t)t, cnt);
-  s_dbase[t] = a.offs[(size_t)sidx * SS_NB + t] + (uint32_t)excl;
-  __syncthreads();
+    K k[IPT];
+    uint32_t v[IPT];
+    uint32_t d[IPT];
+    const uint32_t wbase = (uint32_t)w * WAVE * IPT;
 #pragma unroll
-  for (int i = 0; i < IPT; ++i) r[i] += s_tstart[d[i]] + s_slot[w][d[i]].count;
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < IPT; ++i) {
-    if (r[i] < (uint32_t)TILE) {
-      s_keys[r[i]] = k[i];
-      if constexpr (PAY) s_vals[r[i]] = v[i];
-      s_dig[r[i]] = (uint16_t)d[i];
+    for (int i = 0; i < IPT; ++i) {
+      const uint32_t idx = wbase + (uint32_t)i * WAVE + lane;
+      k[i] = src[idx < valid ? idx : valid - 1];
+      if constexpr (PAY) v[i] = vsrc[idx < valid ? idx : valid - 1];
     }
-  }
-  __syncthreads();
+    __syncthreads();  // splitters in LDS
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+      const uint32_t idx = wbase + (uint32_t)i * WAVE + lane;
+      K x = k[i];
+      if constexpr (KeyTraits<KK>::FLT) x = a.map_in ? fmap(x) : x;
+      if (idx < valid) {
+        k[i] = x;
+        d[i] = ss_classify<K>(x, s_spl);
+      } else {
+        k[i] = ~K(0);
+        d[i] = SS_NB - 1;
+      }
+    }
 
-  K* __restrict__ dst = (K*)a.dst;
-  for (uint32_t j = t; j < valid; j += SS_THREADS) {
-    const uint32_t dj = s_dig[j];
-    const uint32_t rel = s_dbase[dj] + (j - s_tstart[dj]);
-    if (rel >= sg.size) continue;  // unreachable with consistent counts
-    const uint64_t o = sg.start + rel;
-    dst[o] = s_keys[j];
-    if constexpr (PAY) a.vdst[o] = s_vals[j];
+    uint32_t r[IPT];
+    rank_wave_items<IPT>(d, r, s_slot[w]);
+    __syncthreads();
+
+    uint32_t cnt = wave_prefix_per_digit<NW, SS_NB>(s_slot);
+    if (t == SS_NB - 1) cnt -= (uint32_t)TILE - valid;  // padding: last id, sorted last
+    uint32_t total;
+    const uint32_t tstart = block_excl_scan<SS_THREADS>(cnt, s_scan, total);
+    s_tstart[t] = tstart;
+    const uint64_t excl = lookback<SS_NB, ST>((ST*)a.status, tile, sg.first_tile, (uint32_t)t, cnt);
+    s_dbase[t] = a.offs[(size_t)sidx * SS_NB + t] + (uint32_t)excl;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) r[i] += s_tstart[d[i]] + s_slot[w][d[i]].count;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+      if (r[i] < (uint32_t)TILE) {
+        s_keys[r[i]] = k[i];
+        if constexpr (PAY) s_vals[r[i]] = v[i];
+        s_dig[r[i]] = (uint16_t)d[i];
+      }
+    }
+    __syncthreads();
+
+    K* __restrict__ dst = (K*)a.dst;
+    for (uint32_t j = t; j < valid; j += SS_THREADS) {
+      const uint32_t dj = s_dig[j];
+      const uint32_t rel = s_dbase[dj] + (j - s_tstart[dj]);
+      if (rel >= sg.size) continue;  // unreachable with consistent counts
+      const uint64_t o = sg.start + rel;
+      dst[o] = s_keys[j];
+      if constexpr (PAY) a.vdst[o] = s_vals[j];
+    }
   }
 }
 
 // ------------------------------------------------------------------ block sort
-// One block per item.  COPY items move (and unmap) keys.  SORT items (at
-// most SS_CAP keys) are loaded into LDS and sorted by lds_sort_loaded.
+// Workgroups stride over the items.  COPY items move (and unmap) keys.
+// SORT items (at most SS_CAP keys) are loaded into LDS and sorted by
+// lds_sort_loaded.
 template <int KK, bool PAY>
 __global__ __launch_bounds__(SS_THREADS) void k_ss_block(SsBlockArgs a) {
   using K = typename KeyTraits<KK>::K;
   __shared__ BlockSortSmem<K, PAY> sm;
-
-  const SsItem it = a.items[blockIdx.x];
-  const uint32_t buf = (it.flags >> 8) & 0xFFu;
-  const K* __restrict__ src = (const K*)(buf == SS_BUF_IN ? a.kin : (buf == SS_BUF_OUT ? a.kout : a.ktmp));
-  const uint32_t* __restrict__ vsrc = buf == SS_BUF_IN ? a.vin : (buf == SS_BUF_OUT ? a.vout : a.vtmp);
-  const bool raw = buf == SS_BUF_IN;
-  K* __restrict__ dst = (K*)a.kout;
   const int t = threadIdx.x;
-  const uint64_t base = it.start;
-  const uint32_t size = it.size;
-
-  if (it.flags & SS_ITEM_COPY) {
-    for (uint32_t j = t; j < size; j += SS_THREADS) {
-      K x = src[base + j];
-      if constexpr (KeyTraits<KK>::FLT) x = raw ? x : funmap(x);
-      dst[base + j] = x;
-      if constexpr (PAY) a.vout[base + j] = vsrc[base + j];
-    }
-    return;
+  uint32_t nitems = a.nitems;
+  if (a.lvl) {
+    nitems = a.lvl->nitems;
+    nitems = nitems < a.item_cap ? nitems : a.item_cap;
   }
-  lds_load_mapped<KK, PAY>(sm, src + base, PAY ? vsrc + base : nullptr, size, raw);
-  K mn, mx;
-  lds_sort_loaded<K, PAY>(sm, size, mn, mx);
-  for (uint32_t j = t; j < size; j += SS_THREADS) {
-    K x = sm.keys[j];
-    if constexpr (KeyTraits<KK>::FLT) x = funmap(x);
-    dst[base + j] = x;
-    if constexpr (PAY) a.vout[base + j] = sm.vals[j];
+  K* __restrict__ dst = (K*)a.kout;
+  for (uint32_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+    __syncthreads();  // the previous item's LDS contents have been stored
+    const SsItem it = a.items[item];
+    const uint32_t buf = (it.flags >> 8) & 0xFFu;
+    const K* __restrict__ src = (const K*)(buf == SS_BUF_IN ? a.kin : (buf == SS_BUF_OUT ? a.kout : a.ktmp));
+    const uint32_t* __restrict__ vsrc = buf == SS_BUF_IN ? a.vin : (buf == SS_BUF_OUT ? a.vout : a.vtmp);
+    const bool raw = buf == SS_BUF_IN;
+    const uint64_t base = it.start;
+    const uint32_t size = it.size;
+    if (it.flags & SS_ITEM_COPY) {
+      for (uint32_t j = t; j < size; j += SS_THREADS) {
+        K x = src[base + j];
+        if constexpr (KeyTraits<KK>::FLT) x = raw ? x : funmap(x);
+        dst[base + j] = x;
+        if constexpr (PAY) a.vout[base + j] = vsrc[base + j];
+      }
+      continue;
+    }
+    lds_load_mapped<KK, PAY>(sm, src + base, PAY ? vsrc + base : nullptr, size, raw);
+    K mn, mx;
+    lds_sort_loaded(sm, size, mn, mx);
+    for (uint32_t j = t; j < size; j += SS_THREADS) {
+      K x = sm.keys[j];
+      if constexpr (KeyTraits<KK>::FLT) x = funmap(x);
+      dst[base + j] = x;
+      if constexpr (PAY) a.vout[base + j] = sm.vals[j];
+    }
   }
 }
 
@@ -375,35 +416,49 @@ hipError_t launch_ss_init(SsSeg* segs, SsItem* items, uint64_t n, hipStream_t s)
   return hipGetLastError();
 }
 
-hipError_t launch_ss_sample(int kk, const void* src, int map_in, const SsSeg* segs, uint32_t nsegs, void* spl,
-                            uint64_t seed, hipStream_t s) {
+hipError_t launch_ss_sample(int kk, const void* src, int map_in, const SsSeg* segs, const SsLevelIn& lv, void* spl,
+                            uint32_t* counts, uint64_t seed, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
   switch (kk) {
-    case KK_U32: k_ss_sample<KK_U32><<<nsegs, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, (uint32_t*)spl, seed); break;
-    case KK_U64: k_ss_sample<KK_U64><<<nsegs, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, (uint64_t*)spl, seed); break;
-    case KK_F32: k_ss_sample<KK_F32><<<nsegs, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, (uint32_t*)spl, seed); break;
-    case KK_F64: k_ss_sample<KK_F64><<<nsegs, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, (uint64_t*)spl, seed); break;
+    case KK_U32: k_ss_sample<KK_U32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, lv, (uint32_t*)spl, counts, seed); break;
+    case KK_U64: k_ss_sample<KK_U64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, lv, (uint64_t*)spl, counts, seed); break;
+    case KK_F32: k_ss_sample<KK_F32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, lv, (uint32_t*)spl, counts, seed); break;
+    case KK_F64: k_ss_sample<KK_F64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, lv, (uint64_t*)spl, counts, seed); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_ss_count(int kk, const void* src, int map_in, const SsSeg* segs, uint32_t nsegs, uint32_t ntiles,
+hipError_t launch_ss_zero_status(void* status, const SsLevelIn& lv, uint32_t words_per_tile, hipStream_t s) {
+  // host-driven: exact grid; device-driven: a fixed grid that strides
+  uint64_t nvec = lv.in ? (uint64_t)lv.tile_cap * words_per_tile / 4 : (uint64_t)lv.ntiles * words_per_tile / 4;
+  if (nvec == 0) return hipSuccess;
+  const uint64_t nb = (nvec + 255) / 256;
+  const uint32_t grid = (uint32_t)(nb < 4096 ? nb : 4096);
+  k_ss_zero_status<<<grid, 256, 0, s>>>(static_cast<u32x4*>(status), lv, words_per_tile);
+  return hipGetLastError();
+}
+
+hipError_t launch_ss_count(int kk, const void* src, int map_in, const SsSeg* segs, const SsLevelIn& lv,
                            const void* spl, uint32_t* counts, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
   const uint32_t tk = (uint32_t)ss_tile(kk == KK_U32 || kk == KK_F32 ? 4 : 8);
   switch (kk) {
-    case KK_U32: k_ss_count<KK_U32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, nsegs, ntiles, tk, (const uint32_t*)spl, counts); break;
-    case KK_U64: k_ss_count<KK_U64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, nsegs, ntiles, tk, (const uint64_t*)spl, counts); break;
-    case KK_F32: k_ss_count<KK_F32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, nsegs, ntiles, tk, (const uint32_t*)spl, counts); break;
-    case KK_F64: k_ss_count<KK_F64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, nsegs, ntiles, tk, (const uint64_t*)spl, counts); break;
+    case KK_U32: k_ss_count<KK_U32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, lv, tk, (const uint32_t*)spl, counts); break;
+    case KK_U64: k_ss_count<KK_U64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, lv, tk, (const uint64_t*)spl, counts); break;
+    case KK_F32: k_ss_count<KK_F32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, lv, tk, (const uint32_t*)spl, counts); break;
+    case KK_F64: k_ss_count<KK_F64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, lv, tk, (const uint64_t*)spl, counts); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_ss_plan(const SsSeg* segs, uint32_t nsegs, const uint32_t* counts, uint32_t* offs, uint32_t dst_buf,
-                          int copy_in_place, SsSeg* next, SsItem* items, SsCounters* ctr, uint32_t item_cap,
-                          uint32_t seg_cap, hipStream_t s) {
-  k_ss_plan<<<nsegs, SS_NB, 0, s>>>(segs, counts, offs, dst_buf, copy_in_place, next, items, ctr, item_cap, seg_cap);
+hipError_t launch_ss_plan(const SsSeg* segs, const SsLevelIn& lv, const uint32_t* counts, uint32_t* offs,
+                          uint32_t dst_buf, int copy_in_place, SsSeg* next, SsItem* items, SsCounters* ctr,
+                          uint32_t item_cap, uint32_t seg_cap, int nblocks, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  k_ss_plan<<<nblocks, SS_NB, 0, s>>>(segs, lv, counts, offs, dst_buf, copy_in_place, next, items, ctr, item_cap,
+                                      seg_cap);
   return hipGetLastError();
 }
 
@@ -412,45 +467,90 @@ hipError_t launch_ss_tiles(SsSeg* segs, SsCounters* ctr, uint32_t tile_keys, uin
   return hipGetLastError();
 }
 
+template <int KK, bool PAY, typename ST>
+static const void* scatter_fn() {
+  constexpr int IPT = sizeof(typename KeyTraits<KK>::K) == 4 ? 16 : 8;
+  return reinterpret_cast<const void*>(&k_ss_scatter<KK, PAY, IPT, ST>);
+}
+
 template <int KK, bool PAY>
-static hipError_t scatter_kk(const SsScatterArgs& a, uint32_t ntiles, hipStream_t s) {
+static hipError_t scatter_kk(const SsScatterArgs& a, uint32_t grid, hipStream_t s) {
   constexpr int IPT = sizeof(typename KeyTraits<KK>::K) == 4 ? 16 : 8;
   if (a.max_seg < STATUS32_MAX_N)
-    k_ss_scatter<KK, PAY, IPT, uint32_t><<<ntiles, SS_THREADS, 0, s>>>(a);
+    k_ss_scatter<KK, PAY, IPT, uint32_t><<<grid, SS_THREADS, 0, s>>>(a);
   else
-    k_ss_scatter<KK, PAY, IPT, uint64_t><<<ntiles, SS_THREADS, 0, s>>>(a);
+    k_ss_scatter<KK, PAY, IPT, uint64_t><<<grid, SS_THREADS, 0, s>>>(a);
   return hipGetLastError();
 }
 
-hipError_t launch_ss_scatter(int kk, int with_vals, const SsScatterArgs& a, uint32_t ntiles, hipStream_t s) {
-  if (ntiles == 0) return hipSuccess;
+hipError_t launch_ss_scatter(int kk, int with_vals, const SsScatterArgs& a, uint32_t nblocks, hipStream_t s) {
+  const uint32_t grid = nblocks ? nblocks : a.lv.ntiles;
+  if (grid == 0) return hipSuccess;
   switch (kk * 2 + (with_vals ? 1 : 0)) {
-    case KK_U32 * 2: return scatter_kk<KK_U32, false>(a, ntiles, s);
-    case KK_U32 * 2 + 1: return scatter_kk<KK_U32, true>(a, ntiles, s);
-    case KK_U64 * 2: return scatter_kk<KK_U64, false>(a, ntiles, s);
-    case KK_U64 * 2 + 1: return scatter_kk<KK_U64, true>(a, ntiles, s);
-    case KK_F32 * 2: return scatter_kk<KK_F32, false>(a, ntiles, s);
-    case KK_F32 * 2 + 1: return scatter_kk<KK_F32, true>(a, ntiles, s);
-    case KK_F64 * 2: return scatter_kk<KK_F64, false>(a, ntiles, s);
-    case KK_F64 * 2 + 1: return scatter_kk<KK_F64, true>(a, ntiles, s);
+    case KK_U32 * 2: return scatter_kk<KK_U32, false>(a, grid, s);
+    case KK_U32 * 2 + 1: return scatter_kk<KK_U32, true>(a, grid, s);
+    case KK_U64 * 2: return scatter_kk<KK_U64, false>(a, grid, s);
+    case KK_U64 * 2 + 1: return scatter_kk<KK_U64, true>(a, grid, s);
+    case KK_F32 * 2: return scatter_kk<KK_F32, false>(a, grid, s);
+    case KK_F32 * 2 + 1: return scatter_kk<KK_F32, true>(a, grid, s);
+    case KK_F64 * 2: return scatter_kk<KK_F64, false>(a, grid, s);
+    case KK_F64 * 2 + 1: return scatter_kk<KK_F64, true>(a, grid, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_ss_block(int kk, int with_vals, const SsBlockArgs& a, uint32_t nitems, hipStream_t s) {
-  if (nitems == 0) return hipSuccess;
+hipError_t launch_ss_block(int kk, int with_vals, const SsBlockArgs& a, uint32_t nblocks, hipStream_t s) {
+  const uint32_t grid = nblocks ? nblocks : a.nitems;
+  if (grid == 0) return hipSuccess;
   switch (kk * 2 + (with_vals ? 1 : 0)) {
-    case KK_U32 * 2: k_ss_block<KK_U32, false><<<nitems, SS_THREADS, 0, s>>>(a); break;
-    case KK_U32 * 2 + 1: k_ss_block<KK_U32, true><<<nitems, SS_THREADS, 0, s>>>(a); break;
-    case KK_U64 * 2: k_ss_block<KK_U64, false><<<nitems, SS_THREADS, 0, s>>>(a); break;
-    case KK_U64 * 2 + 1: k_ss_block<KK_U64, true><<<nitems, SS_THREADS, 0, s>>>(a); break;
-    case KK_F32 * 2: k_ss_block<KK_F32, false><<<nitems, SS_THREADS, 0, s>>>(a); break;
-    case KK_F32 * 2 + 1: k_ss_block<KK_F32, true><<<nitems, SS_THREADS, 0, s>>>(a); break;
-    case KK_F64 * 2: k_ss_block<KK_F64, false><<<nitems, SS_THREADS, 0, s>>>(a); break;
-    case KK_F64 * 2 + 1: k_ss_block<KK_F64, true><<<nitems, SS_THREADS, 0, s>>>(a); break;
+    case KK_U32 * 2: k_ss_block<KK_U32, false><<<grid, SS_THREADS, 0, s>>>(a); break;
+    case KK_U32 * 2 + 1: k_ss_block<KK_U32, true><<<grid, SS_THREADS, 0, s>>>(a); break;
+    case KK_U64 * 2: k_ss_block<KK_U64, false><<<grid, SS_THREADS, 0, s>>>(a); break;
+    case KK_U64 * 2 + 1: k_ss_block<KK_U64, true><<<grid, SS_THREADS, 0, s>>>(a); break;
+    case KK_F32 * 2: k_ss_block<KK_F32, false><<<grid, SS_THREADS, 0, s>>>(a); break;
+    case KK_F32 * 2 + 1: k_ss_block<KK_F32, true><<<grid, SS_THREADS, 0, s>>>(a); break;
+    case KK_F64 * 2: k_ss_block<KK_F64, false><<<grid, SS_THREADS, 0, s>>>(a); break;
+    case KK_F64 * 2 + 1: k_ss_block<KK_F64, true><<<grid, SS_THREADS, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+static uint32_t resident(const void* fn, int threads, uint32_t cu_count) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  return (uint32_t)per_cu * (cu_count ? cu_count : 1);
+}
+
+uint32_t ss_scatter_resident(int kk, int with_vals, uint64_t max_seg, uint32_t cu_count) {
+  const bool s32 = max_seg < STATUS32_MAX_N;
+  const void* fn = nullptr;
+  switch (kk * 2 + (with_vals ? 1 : 0)) {
+    case KK_U32 * 2: fn = s32 ? scatter_fn<KK_U32, false, uint32_t>() : scatter_fn<KK_U32, false, uint64_t>(); break;
+    case KK_U32 * 2 + 1: fn = s32 ? scatter_fn<KK_U32, true, uint32_t>() : scatter_fn<KK_U32, true, uint64_t>(); break;
+    case KK_U64 * 2: fn = s32 ? scatter_fn<KK_U64, false, uint32_t>() : scatter_fn<KK_U64, false, uint64_t>(); break;
+    case KK_U64 * 2 + 1: fn = s32 ? scatter_fn<KK_U64, true, uint32_t>() : scatter_fn<KK_U64, true, uint64_t>(); break;
+    case KK_F32 * 2: fn = s32 ? scatter_fn<KK_F32, false, uint32_t>() : scatter_fn<KK_F32, false, uint64_t>(); break;
+    case KK_F32 * 2 + 1: fn = s32 ? scatter_fn<KK_F32, true, uint32_t>() : scatter_fn<KK_F32, true, uint64_t>(); break;
+    case KK_F64 * 2: fn = s32 ? scatter_fn<KK_F64, false, uint32_t>() : scatter_fn<KK_F64, false, uint64_t>(); break;
+    default: fn = s32 ? scatter_fn<KK_F64, true, uint32_t>() : scatter_fn<KK_F64, true, uint64_t>(); break;
+  }
+  return resident(fn, SS_THREADS, cu_count);
+}
+
+uint32_t ss_block_resident(int kk, int with_vals, uint32_t cu_count) {
+  const void* fn = nullptr;
+  switch (kk * 2 + (with_vals ? 1 : 0)) {
+    case KK_U32 * 2: fn = reinterpret_cast<const void*>(&k_ss_block<KK_U32, false>); break;
+    case KK_U32 * 2 + 1: fn = reinterpret_cast<const void*>(&k_ss_block<KK_U32, true>); break;
+    case KK_U64 * 2: fn = reinterpret_cast<const void*>(&k_ss_block<KK_U64, false>); break;
+    case KK_U64 * 2 + 1: fn = reinterpret_cast<const void*>(&k_ss_block<KK_U64, true>); break;
+    case KK_F32 * 2: fn = reinterpret_cast<const void*>(&k_ss_block<KK_F32, false>); break;
+    case KK_F32 * 2 + 1: fn = reinterpret_cast<const void*>(&k_ss_block<KK_F32, true>); break;
+    case KK_F64 * 2: fn = reinterpret_cast<const void*>(&k_ss_block<KK_F64, false>); break;
+    default: fn = reinterpret_cast<const void*>(&k_ss_block<KK_F64, true>); break;
+  }
+  return resident(fn, SS_THREADS, cu_count);
 }
 
 }  // namespace ahs

@@ -35,13 +35,32 @@ struct SsCounters {   // per level, written by the device, read by the host
   unsigned long long item_keys, seg_keys_next;
 };
 
+// Level sizes: the host passes them (host-driven levels), or a kernel reads
+// them from the previous level's counter record `in` (device-driven levels,
+// enqueue-only), clamped to the table capacities.
+struct SsLevelIn {
+  const SsCounters* in;  // null: use the host values
+  uint32_t nsegs, ntiles;
+  uint32_t seg_cap, tile_cap;
+  __device__ __forceinline__ uint32_t segs_n() const {
+    if (!in) return nsegs;
+    const uint32_t v = in->nsegs_next;
+    return v < seg_cap ? v : seg_cap;
+  }
+  __device__ __forceinline__ uint32_t tiles_n() const {
+    if (!in) return ntiles;
+    const uint32_t v = in->ntiles_next;
+    return v < tile_cap ? v : tile_cap;
+  }
+};
+
 struct SsScatterArgs {
   const void* src;
   void* dst;
   const uint32_t* vsrc;
   uint32_t* vdst;
   uint32_t map_in;
-  uint32_t nsegs;
+  SsLevelIn lv;
   const SsSeg* segs;
   const void* spl;
   const uint32_t* offs;
@@ -52,6 +71,8 @@ struct SsScatterArgs {
 
 struct SsBlockArgs {
   const SsItem* items;
+  const SsCounters* lvl;   // device item count (nitems), or null: host count
+  uint32_t nitems, item_cap;
   const void* kin;
   void* kout;
   const void* ktmp;
@@ -69,15 +90,23 @@ struct SsLayout {
 SsLayout ss_layout(uint64_t n, int key_bytes);
 
 hipError_t launch_ss_init(SsSeg* segs, SsItem* items, uint64_t n, hipStream_t s);
-hipError_t launch_ss_sample(int kk, const void* src, int map_in, const SsSeg* segs, uint32_t nsegs, void* spl,
-                            uint64_t seed, hipStream_t s);
-hipError_t launch_ss_count(int kk, const void* src, int map_in, const SsSeg* segs, uint32_t nsegs, uint32_t ntiles,
+// Every level kernel loops over its work (segments, tiles, items) with a
+// grid stride, so device-driven levels launch fixed grids.  The sample
+// kernel also clears the level's bucket counts.
+hipError_t launch_ss_sample(int kk, const void* src, int map_in, const SsSeg* segs, const SsLevelIn& lv, void* spl,
+                            uint32_t* counts, uint64_t seed, int nblocks, hipStream_t s);
+hipError_t launch_ss_zero_status(void* status, const SsLevelIn& lv, uint32_t words_per_tile, hipStream_t s);
+hipError_t launch_ss_count(int kk, const void* src, int map_in, const SsSeg* segs, const SsLevelIn& lv,
                            const void* spl, uint32_t* counts, int nblocks, hipStream_t s);
-hipError_t launch_ss_plan(const SsSeg* segs, uint32_t nsegs, const uint32_t* counts, uint32_t* offs, uint32_t dst_buf,
-                          int copy_in_place, SsSeg* next, SsItem* items, SsCounters* ctr, uint32_t item_cap,
-                          uint32_t seg_cap, hipStream_t s);
+hipError_t launch_ss_plan(const SsSeg* segs, const SsLevelIn& lv, const uint32_t* counts, uint32_t* offs,
+                          uint32_t dst_buf, int copy_in_place, SsSeg* next, SsItem* items, SsCounters* ctr,
+                          uint32_t item_cap, uint32_t seg_cap, int nblocks, hipStream_t s);
 hipError_t launch_ss_tiles(SsSeg* segs, SsCounters* ctr, uint32_t tile_keys, uint32_t seg_cap, hipStream_t s);
-hipError_t launch_ss_scatter(int kk, int with_vals, const SsScatterArgs& a, uint32_t ntiles, hipStream_t s);
-hipError_t launch_ss_block(int kk, int with_vals, const SsBlockArgs& a, uint32_t nitems, hipStream_t s);
+// nblocks 0: one block per tile (host-driven); else a persistent grid.
+hipError_t launch_ss_scatter(int kk, int with_vals, const SsScatterArgs& a, uint32_t nblocks, hipStream_t s);
+hipError_t launch_ss_block(int kk, int with_vals, const SsBlockArgs& a, uint32_t nblocks, hipStream_t s);
+// Resident workgroups of the scatter and block-sort kernels on the device.
+uint32_t ss_scatter_resident(int kk, int with_vals, uint64_t max_seg, uint32_t cu_count);
+uint32_t ss_block_resident(int kk, int with_vals, uint32_t cu_count);
 
 }  // namespace ahs

@@ -1,23 +1,23 @@
 // Batched segmented sort on gfx950: many independent arrays in one call.
-// Segments of at most SS_CAP keys are handled wholly in LDS by one fused
-// kernel (load, stable sort, features, decision, store); larger segments go
-// through the sample-sort levels and get their features from runs of equal
-// bins in their sorted output.  Features are permutation-invariant, so
-// computing them after sorting gives the same values as before.
+// Segments of at most SS_CAP keys are queued by size class and handled
+// wholly in LDS by one fused kernel per class (load, stable sort, features,
+// decision, store); larger segments go through the sample-sort levels and
+// get their features from runs of equal bins in their sorted output.
+// Features are permutation-invariant, so computing them after sorting gives
+// the same values as before.  Every kernel reads its work count from the
+// device, so the whole batch can be enqueued without a host round trip.
 #include "blocksort.hpp"
 #include "segmented.hpp"
 
 namespace ahs {
 
-// Decision engine of Sec. III-A on the device.  thr[B] = h_ratio * log2(B)
-// is tabulated by the host with the host's log2, so the radix test compares
-// exactly as the host decision engine does.
-__device__ __forceinline__ uint8_t seg_fsm(uint64_t n, uint64_t span, uint32_t nbins, double H, const SegConfig& c,
-                                           const double* __restrict__ thr) {
-  if (n <= c.n_small) return 4;                  // INSERTION
-  if (span <= c.k_count - 1) return 1;           // COUNTING
-  if (span >= c.k_radix && H < thr[nbins]) return 2;  // RADIX
-  return 3;                                      // QUICK
+// Decision engine of Sec. III-A on the device: n, then k = span + 1, then
+// the entropy test against h_ratio * log2(B).
+__device__ __forceinline__ uint8_t seg_fsm(uint64_t n, uint64_t span, uint32_t nbins, double H, const SegConfig& c) {
+  if (n <= c.n_small) return 4;                                             // INSERTION
+  if (span <= c.k_count - 1) return 1;                                      // COUNTING
+  if (span >= c.k_radix && H < c.h_ratio * log2((double)nbins)) return 2;  // RADIX
+  return 3;                                                                 // QUICK
 }
 
 // Mapped-key bounds of the non-NaN values: map(-inf) .. map(+inf).
@@ -37,98 +37,105 @@ __device__ __forceinline__ void shift_nbins(uint64_t span, uint32_t& shift, uint
 
 // ------------------------------------------------------------------ classify
 __global__ __launch_bounds__(256) void k_seg_classify(const uint64_t* __restrict__ offs, uint32_t nseg,
-                                                      uint64_t n_total, uint32_t* __restrict__ small_ids,
-                                                      SsSeg* __restrict__ large, SsSeg* __restrict__ large_copy,
+                                                      uint64_t n_total, uint32_t* __restrict__ queues, uint32_t qcap,
+                                                      SsSeg* __restrict__ large_ss, SsSeg* __restrict__ large,
                                                       uint32_t* __restrict__ large_ids,
                                                       SegCounters* __restrict__ ctr) {
   const uint32_t s = blockIdx.x * 256 + threadIdx.x;
-  if (s == 0 && offs[nseg] != n_total) atomicOr(&ctr->bad, 1u);
+  if (s == 0 && offs[nseg] != n_total) atomicOr(&ctr->bad, SEG_ERR_OFFSETS);
   if (s >= nseg) return;
   const uint64_t a = offs[s], b = offs[s + 1];
   if (b < a || b > n_total || b - a > 0xFFFFFFFFull) {
-    atomicOr(&ctr->bad, 2u);
+    atomicOr(&ctr->bad, SEG_ERR_OFFSETS);
     return;
   }
   const uint64_t size = b - a;
   if (size <= (uint64_t)SS_CAP) {
-    small_ids[atomicAdd(&ctr->nsmall, 1u)] = s;
+    int c = 0;
+    while (size > SEG_CLASS_CAP[c]) ++c;
+    queues[(size_t)c * qcap + atomicAdd(&ctr->nclass[c], 1u)] = s;
+    atomicAdd(&ctr->small_keys, (unsigned long long)size);
   } else {
     const uint32_t i = atomicAdd(&ctr->nlarge, 1u);
     SsSeg g;
     g.start = a;
     g.size = (uint32_t)size;
     g.first_tile = 0;
+    large_ss[i] = g;
     large[i] = g;
-    large_copy[i] = g;
     large_ids[i] = s;
     atomicAdd(&ctr->large_keys, (unsigned long long)size);
     atomicMax(&ctr->max_large, (uint32_t)size);
   }
 }
 
+__global__ void k_seg_gate(const SegCounters* __restrict__ ctr, SsCounters* __restrict__ rec0) {
+  if (threadIdx.x == 0) rec0->nsegs_next = ctr->bad ? 0u : ctr->nlarge;
+}
+
 // ------------------------------------------------------------------ small segments, fused
-template <int KK, bool PAY>
-__global__ __launch_bounds__(SS_THREADS) void k_seg_small(SegArgs a) {
+template <int KK, bool PAY, int CAP, int NT>
+__global__ __launch_bounds__(NT) void k_seg_small(SegArgs a, int cls) {
   using K = typename KeyTraits<KK>::K;
-  __shared__ BlockSortSmem<K, PAY> sm;
-  const uint32_t s = a.small_ids[blockIdx.x];
-  const uint64_t base = a.offs[s];
-  const uint32_t size = (uint32_t)(a.offs[s + 1] - base);
+  __shared__ BlockSortSmem<K, PAY, CAP, NT> sm;
+  const uint32_t count = a.ctr->bad ? 0u : a.ctr->nclass[cls];
+  const uint32_t* __restrict__ queue = a.queues + (size_t)cls * a.qcap;
   const int t = threadIdx.x;
-  const K* __restrict__ kin = (const K*)a.kin + base;
-  K* __restrict__ kout = (K*)a.kout + base;
-  lds_load_mapped<KK, PAY>(sm, kin, PAY ? a.vin + base : nullptr, size, true);
-  K mn = 0, mx = 0;
-  if (size > 0) lds_sort_loaded<K, PAY>(sm, size, mn, mx);
-  for (uint32_t j = t; j < size; j += SS_THREADS) {
-    K x = sm.keys[j];
-    if constexpr (KeyTraits<KK>::FLT) x = funmap(x);
-    kout[j] = x;
-    if constexpr (PAY) a.vout[base + j] = sm.vals[j];
-  }
-  // features from the sorted keys (exclude NaNs, which sit at both ends)
-  uint32_t nan = 0, lo = 0, hi = size;
-  if constexpr (KeyTraits<KK>::FLT) {
-    for (uint32_t j = t; j < size; j += SS_THREADS)
-      nan += (sm.keys[j] < NanBounds<K>::lo || sm.keys[j] > NanBounds<K>::hi) ? 1u : 0u;
-    nan = wave_sum(nan);
-    if (lane_id() == 0) sm.scan[t / WAVE] = nan;
-    __syncthreads();
-    nan = 0;
-    for (int i = 0; i < SS_THREADS / WAVE; ++i) nan += sm.scan[i];
-    __syncthreads();
-  }
-  DevFeatures f = {};
-  f.n = size;
-  f.nan_count = nan;
-  uint8_t chosen;
-  if (nan) {
-    chosen = SEG_STATUS_NAN;
-  } else {
-    if (size > 0) {
-      mn = sm.keys[lo];
-      mx = sm.keys[hi - 1];
+  for (uint32_t q = blockIdx.x; q < count; q += gridDim.x) {
+    __syncthreads();  // the previous segment's LDS contents are consumed
+    const uint32_t s = queue[q];
+    const uint64_t base = a.offs[s];
+    const uint32_t size = (uint32_t)(a.offs[s + 1] - base);
+    const K* __restrict__ kin = (const K*)a.kin + base;
+    K* __restrict__ kout = (K*)a.kout + base;
+    lds_load_mapped<KK, PAY>(sm, kin, PAY ? a.vin + base : nullptr, size, true);
+    K mn = 0, mx = 0;
+    if (size > 0) lds_sort_loaded(sm, size, mn, mx);
+    for (uint32_t j = t; j < size; j += NT) {
+      K x = sm.keys[j];
+      if constexpr (KeyTraits<KK>::FLT) x = funmap(x);
+      kout[j] = x;
+      if constexpr (PAY) a.vout[base + j] = sm.vals[j];
     }
-    f.min_key = mn;
-    f.max_key = mx;
-    f.span = (uint64_t)(mx - mn);
-    shift_nbins(f.span, f.shift, f.nbins);
-    f.exact = f.shift == 0;
-    uint64_t carry = 0;
-    double H = 0.0;
-    if (size > 0)
-      H = lds_run_entropy<K, PAY>(sm, size, 0, K(0), false, K(0), false, mn, f.shift, size, carry);
-    f.entropy_bits = H < 0.0 ? 0.0 : H;
-    f.entropy_ratio = f.nbins > 1 ? f.entropy_bits / log2((double)f.nbins) : 0.0;
-    chosen = a.requested ? (uint8_t)a.requested : seg_fsm(size, f.span, f.nbins, f.entropy_bits, a.cfg, a.thr);
-    if (size == 0) {
-      f.nbins = 0;
-      f.exact = 0;
+    // features from the sorted keys (NaNs sit at both ends of the mapped order)
+    uint32_t nan = 0;
+    if constexpr (KeyTraits<KK>::FLT) {
+      for (uint32_t j = t; j < size; j += NT)
+        nan += (sm.keys[j] < NanBounds<K>::lo || sm.keys[j] > NanBounds<K>::hi) ? 1u : 0u;
+      nan = wave_sum(nan);
+      if (lane_id() == 0) sm.scan[t / WAVE] = nan;
+      __syncthreads();
+      nan = 0;
+      for (int i = 0; i < NT / WAVE; ++i) nan += sm.scan[i];
+      __syncthreads();
     }
-  }
-  if (t == 0) {
-    if (a.chosen) a.chosen[s] = chosen;
-    if (a.feats) a.feats[s] = f;
+    DevFeatures f = {};
+    f.n = size;
+    f.nan_count = nan;
+    uint8_t chosen;
+    if (nan) {
+      chosen = SEG_STATUS_NAN;
+    } else {
+      f.min_key = mn;
+      f.max_key = mx;
+      f.span = (uint64_t)(mx - mn);
+      shift_nbins(f.span, f.shift, f.nbins);
+      f.exact = f.shift == 0;
+      uint64_t carry = 0;
+      double H = 0.0;
+      if (size > 0) H = lds_run_entropy(sm, size, 0, K(0), false, K(0), false, mn, f.shift, size, carry);
+      f.entropy_bits = H < 0.0 ? 0.0 : H;
+      f.entropy_ratio = f.nbins > 1 ? f.entropy_bits / log2((double)f.nbins) : 0.0;
+      chosen = a.requested ? (uint8_t)a.requested : seg_fsm(size, f.span, f.nbins, f.entropy_bits, a.cfg);
+      if (size == 0) {
+        f.nbins = 0;
+        f.exact = 0;
+      }
+    }
+    if (t == 0) {
+      if (a.chosen) a.chosen[s] = chosen;
+      if (a.feats) a.feats[s] = f;
+    }
   }
 }
 
@@ -137,89 +144,199 @@ template <int KK>
 __global__ __launch_bounds__(SS_THREADS) void k_seg_large(SegArgs a) {
   using K = typename KeyTraits<KK>::K;
   __shared__ BlockSortSmem<K, false> sm;
-  const SsSeg g = a.large[blockIdx.x];
-  const uint32_t s = a.large_ids[blockIdx.x];
-  const K* __restrict__ keys = (const K*)a.kout + g.start;
-  const uint32_t size = g.size;
-  auto mapped = [&](uint64_t j) {
-    K x = keys[j];
-    if constexpr (KeyTraits<KK>::FLT) x = fmap(x);
-    return x;
-  };
-  // NaNs occupy a prefix and a suffix of the sorted mapped order
-  uint32_t lo = 0, hi = size;
-  if constexpr (KeyTraits<KK>::FLT) {
-    uint32_t l = 0, h = size;  // first index with mapped >= lo bound
-    while (l < h) { const uint32_t m = (l + h) >> 1; if (mapped(m) < NanBounds<K>::lo) l = m + 1; else h = m; }
-    lo = l;
-    l = lo; h = size;  // first index with mapped > hi bound
-    while (l < h) { const uint32_t m = (l + h) >> 1; if (mapped(m) > NanBounds<K>::hi) h = m; else l = m + 1; }
-    hi = l;
-  }
-  DevFeatures f = {};
-  f.n = size;
-  f.nan_count = lo + (size - hi);
-  uint8_t chosen;
-  if (f.nan_count) {
-    chosen = SEG_STATUS_NAN;
-  } else {
-    const K mn = mapped(0), mx = mapped(size - 1);
-    f.min_key = mn;
-    f.max_key = mx;
-    f.span = (uint64_t)(mx - mn);
-    shift_nbins(f.span, f.shift, f.nbins);
-    f.exact = f.shift == 0;
-    double H = 0.0;
-    uint64_t carry = 0;
-    for (uint32_t c0 = 0; c0 < size; c0 += SS_CAP) {
-      const uint32_t cnt = size - c0 < (uint32_t)SS_CAP ? size - c0 : (uint32_t)SS_CAP;
-      for (uint32_t j = threadIdx.x; j < cnt; j += SS_THREADS) sm.keys[j] = mapped(c0 + j);
-      const K prev = c0 > 0 ? mapped(c0 - 1) : K(0);
-      const K next = c0 + cnt < size ? mapped(c0 + cnt) : K(0);
-      __syncthreads();
-      H += lds_run_entropy<K, false>(sm, cnt, c0, prev, c0 > 0, next, c0 + cnt < size, mn, f.shift, size, carry);
+  const uint32_t count = a.ctr->bad ? 0u : a.ctr->nlarge;
+  for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
+    __syncthreads();
+    const SsSeg g = a.large[i];
+    const uint32_t s = a.large_ids[i];
+    const K* __restrict__ keys = (const K*)a.kout + g.start;
+    const uint32_t size = g.size;
+    auto mapped = [&](uint64_t j) {
+      K x = keys[j];
+      if constexpr (KeyTraits<KK>::FLT) x = fmap(x);
+      return x;
+    };
+    // NaNs occupy a prefix and a suffix of the sorted mapped order
+    uint32_t lo = 0, hi = size;
+    if constexpr (KeyTraits<KK>::FLT) {
+      uint32_t l = 0, h = size;  // first index with mapped >= lo bound
+      while (l < h) {
+        const uint32_t m = (l + h) >> 1;
+        if (mapped(m) < NanBounds<K>::lo) l = m + 1; else h = m;
+      }
+      lo = l;
+      l = lo;
+      h = size;  // first index with mapped > hi bound
+      while (l < h) {
+        const uint32_t m = (l + h) >> 1;
+        if (mapped(m) > NanBounds<K>::hi) h = m; else l = m + 1;
+      }
+      hi = l;
     }
-    f.entropy_bits = H < 0.0 ? 0.0 : H;
-    f.entropy_ratio = f.nbins > 1 ? f.entropy_bits / log2((double)f.nbins) : 0.0;
-    chosen = a.requested ? (uint8_t)a.requested : seg_fsm(size, f.span, f.nbins, f.entropy_bits, a.cfg, a.thr);
+    DevFeatures f = {};
+    f.n = size;
+    f.nan_count = lo + (size - hi);
+    uint8_t chosen;
+    if (f.nan_count) {
+      chosen = SEG_STATUS_NAN;
+    } else {
+      const K mn = mapped(0), mx = mapped(size - 1);
+      f.min_key = mn;
+      f.max_key = mx;
+      f.span = (uint64_t)(mx - mn);
+      shift_nbins(f.span, f.shift, f.nbins);
+      f.exact = f.shift == 0;
+      double H = 0.0;
+      uint64_t carry = 0;
+      for (uint32_t c0 = 0; c0 < size; c0 += SS_CAP) {
+        const uint32_t cnt = size - c0 < (uint32_t)SS_CAP ? size - c0 : (uint32_t)SS_CAP;
+        for (uint32_t j = threadIdx.x; j < cnt; j += SS_THREADS) sm.keys[j] = mapped(c0 + j);
+        const K prev = c0 > 0 ? mapped(c0 - 1) : K(0);
+        const K next = c0 + cnt < size ? mapped(c0 + cnt) : K(0);
+        __syncthreads();
+        H += lds_run_entropy(sm, cnt, c0, prev, c0 > 0, next, c0 + cnt < size, mn, f.shift, size, carry);
+      }
+      f.entropy_bits = H < 0.0 ? 0.0 : H;
+      f.entropy_ratio = f.nbins > 1 ? f.entropy_bits / log2((double)f.nbins) : 0.0;
+      chosen = a.requested ? (uint8_t)a.requested : seg_fsm(size, f.span, f.nbins, f.entropy_bits, a.cfg);
+    }
+    if (threadIdx.x == 0) {
+      if (a.chosen) a.chosen[s] = chosen;
+      if (a.feats) a.feats[s] = f;
+    }
   }
-  if (threadIdx.x == 0) {
-    if (a.chosen) a.chosen[s] = chosen;
-    if (a.feats) a.feats[s] = f;
+}
+
+__global__ void k_seg_status(const SegCounters* __restrict__ ctr, const SsCounters* __restrict__ levels, int nlevels,
+                             uint32_t* __restrict__ status) {
+  if (threadIdx.x != 0) return;
+  uint32_t st = ctr->bad ? SEG_ERR_OFFSETS : 0u;
+  for (int l = 0; l < nlevels; ++l)
+    if (levels[l].overflow) st |= SEG_ERR_OVERFLOW;
+  if (!ctr->bad && ctr->nlarge > 0 && (nlevels == 0 || levels[nlevels - 1].nsegs_next > 0)) st |= SEG_ERR_LEVELS;
+  *status = st;
+}
+
+// SplitMix64 finaliser over a counter: synthetic keys for tuning runs only.
+template <int KK>
+__global__ __launch_bounds__(256) void k_tune_fill(typename KeyTraits<KK>::K* __restrict__ keys, uint64_t n,
+                                                   uint64_t seed) {
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    if constexpr (KK == KK_U32) {
+      keys[i] = (uint32_t)(z >> 32);
+    } else if constexpr (KK == KK_U64) {
+      keys[i] = z;
+    } else if constexpr (KK == KK_F32) {
+      const float x = (float)(z >> 40) * (1.0f / 16777216.0f) * 2000.0f - 1000.0f;
+      keys[i] = __float_as_uint(x);
+    } else {
+      const double x = (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2000.0 - 1000.0;
+      keys[i] = (uint64_t)__double_as_longlong(x);
+    }
   }
 }
 
 // ------------------------------------------------------------------ launchers
-hipError_t launch_seg_classify(const uint64_t* offs, uint32_t nseg, uint64_t n_total, uint32_t* small_ids, SsSeg* large,
-                               SsSeg* large_copy, uint32_t* large_ids, SegCounters* ctr, hipStream_t s) {
+hipError_t launch_seg_classify(const uint64_t* offs, uint32_t nseg, uint64_t n_total, uint32_t* queues, uint32_t qcap,
+                               SsSeg* large_ss, SsSeg* large, uint32_t* large_ids, SegCounters* ctr, hipStream_t s) {
   const uint32_t nb = (nseg + 256) / 256;
-  k_seg_classify<<<nb, 256, 0, s>>>(offs, nseg, n_total, small_ids, large, large_copy, large_ids, ctr);
+  k_seg_classify<<<nb, 256, 0, s>>>(offs, nseg, n_total, queues, qcap, large_ss, large, large_ids, ctr);
   return hipGetLastError();
 }
 
-hipError_t launch_seg_small(int kk, int with_vals, const SegArgs& a, uint32_t nsmall, hipStream_t s) {
-  if (nsmall == 0) return hipSuccess;
-  switch (kk * 2 + (with_vals ? 1 : 0)) {
-    case KK_U32 * 2: k_seg_small<KK_U32, false><<<nsmall, SS_THREADS, 0, s>>>(a); break;
-    case KK_U32 * 2 + 1: k_seg_small<KK_U32, true><<<nsmall, SS_THREADS, 0, s>>>(a); break;
-    case KK_U64 * 2: k_seg_small<KK_U64, false><<<nsmall, SS_THREADS, 0, s>>>(a); break;
-    case KK_U64 * 2 + 1: k_seg_small<KK_U64, true><<<nsmall, SS_THREADS, 0, s>>>(a); break;
-    case KK_F32 * 2: k_seg_small<KK_F32, false><<<nsmall, SS_THREADS, 0, s>>>(a); break;
-    case KK_F32 * 2 + 1: k_seg_small<KK_F32, true><<<nsmall, SS_THREADS, 0, s>>>(a); break;
-    case KK_F64 * 2: k_seg_small<KK_F64, false><<<nsmall, SS_THREADS, 0, s>>>(a); break;
-    case KK_F64 * 2 + 1: k_seg_small<KK_F64, true><<<nsmall, SS_THREADS, 0, s>>>(a); break;
+hipError_t launch_seg_gate(const SegCounters* ctr, SsCounters* rec0, hipStream_t s) {
+  k_seg_gate<<<1, 64, 0, s>>>(ctr, rec0);
+  return hipGetLastError();
+}
+
+template <int KK, bool PAY>
+static const void* small_fn(int variant) {
+  switch (variant) {
+    case 0: return reinterpret_cast<const void*>(&k_seg_small<KK, PAY, 1024, 256>);
+    case 1: return reinterpret_cast<const void*>(&k_seg_small<KK, PAY, 2048, 256>);
+    case 2: return reinterpret_cast<const void*>(&k_seg_small<KK, PAY, 4096, 256>);
+    default: return reinterpret_cast<const void*>(&k_seg_small<KK, PAY, 8192, 512>);
+  }
+}
+
+template <int KK, bool PAY>
+static hipError_t small_kk(const SegArgs& a, int cls, int variant, uint32_t grid, hipStream_t s) {
+  switch (variant) {
+    case 0: k_seg_small<KK, PAY, 1024, 256><<<grid, 256, 0, s>>>(a, cls); break;
+    case 1: k_seg_small<KK, PAY, 2048, 256><<<grid, 256, 0, s>>>(a, cls); break;
+    case 2: k_seg_small<KK, PAY, 4096, 256><<<grid, 256, 0, s>>>(a, cls); break;
+    case 3: k_seg_small<KK, PAY, 8192, 512><<<grid, 512, 0, s>>>(a, cls); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_seg_large(int kk, const SegArgs& a, uint32_t nlarge, hipStream_t s) {
-  if (nlarge == 0) return hipSuccess;
+hipError_t launch_seg_small(int kk, int with_vals, const SegArgs& a, int cls, int variant, uint32_t nblocks,
+                            hipStream_t s) {
+  if (nblocks == 0) return hipSuccess;
+  if (cls < 0 || cls >= SEG_NCLASS || variant < cls || variant >= SEG_NVARIANT) return hipErrorInvalidValue;
+  switch (kk * 2 + (with_vals ? 1 : 0)) {
+    case KK_U32 * 2: return small_kk<KK_U32, false>(a, cls, variant, nblocks, s);
+    case KK_U32 * 2 + 1: return small_kk<KK_U32, true>(a, cls, variant, nblocks, s);
+    case KK_U64 * 2: return small_kk<KK_U64, false>(a, cls, variant, nblocks, s);
+    case KK_U64 * 2 + 1: return small_kk<KK_U64, true>(a, cls, variant, nblocks, s);
+    case KK_F32 * 2: return small_kk<KK_F32, false>(a, cls, variant, nblocks, s);
+    case KK_F32 * 2 + 1: return small_kk<KK_F32, true>(a, cls, variant, nblocks, s);
+    case KK_F64 * 2: return small_kk<KK_F64, false>(a, cls, variant, nblocks, s);
+    case KK_F64 * 2 + 1: return small_kk<KK_F64, true>(a, cls, variant, nblocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+uint32_t seg_small_resident(int kk, int with_vals, int variant, uint32_t cu_count) {
+  const void* fn = nullptr;
+  switch (kk * 2 + (with_vals ? 1 : 0)) {
+    case KK_U32 * 2: fn = small_fn<KK_U32, false>(variant); break;
+    case KK_U32 * 2 + 1: fn = small_fn<KK_U32, true>(variant); break;
+    case KK_U64 * 2: fn = small_fn<KK_U64, false>(variant); break;
+    case KK_U64 * 2 + 1: fn = small_fn<KK_U64, true>(variant); break;
+    case KK_F32 * 2: fn = small_fn<KK_F32, false>(variant); break;
+    case KK_F32 * 2 + 1: fn = small_fn<KK_F32, true>(variant); break;
+    case KK_F64 * 2: fn = small_fn<KK_F64, false>(variant); break;
+    default: fn = small_fn<KK_F64, true>(variant); break;
+  }
+  int per_cu = 0;
+  const int threads = variant == 3 ? 512 : 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  return (uint32_t)per_cu * (cu_count ? cu_count : 1);
+}
+
+hipError_t launch_seg_large(int kk, const SegArgs& a, uint32_t nblocks, hipStream_t s) {
+  if (nblocks == 0) return hipSuccess;
   switch (kk) {
-    case KK_U32: k_seg_large<KK_U32><<<nlarge, SS_THREADS, 0, s>>>(a); break;
-    case KK_U64: k_seg_large<KK_U64><<<nlarge, SS_THREADS, 0, s>>>(a); break;
-    case KK_F32: k_seg_large<KK_F32><<<nlarge, SS_THREADS, 0, s>>>(a); break;
-    case KK_F64: k_seg_large<KK_F64><<<nlarge, SS_THREADS, 0, s>>>(a); break;
+    case KK_U32: k_seg_large<KK_U32><<<nblocks, SS_THREADS, 0, s>>>(a); break;
+    case KK_U64: k_seg_large<KK_U64><<<nblocks, SS_THREADS, 0, s>>>(a); break;
+    case KK_F32: k_seg_large<KK_F32><<<nblocks, SS_THREADS, 0, s>>>(a); break;
+    case KK_F64: k_seg_large<KK_F64><<<nblocks, SS_THREADS, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_status(const SegCounters* ctr, const SsCounters* levels, int nlevels, uint32_t* status,
+                             hipStream_t s) {
+  k_seg_status<<<1, 64, 0, s>>>(ctr, levels, nlevels, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_tune_fill(int kk, void* keys, uint64_t n, uint64_t seed, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint64_t nb = (n + 255) / 256;
+  const uint32_t grid = (uint32_t)(nb < 8192 ? nb : 8192);
+  switch (kk) {
+    case KK_U32: k_tune_fill<KK_U32><<<grid, 256, 0, s>>>((uint32_t*)keys, n, seed); break;
+    case KK_U64: k_tune_fill<KK_U64><<<grid, 256, 0, s>>>((uint64_t*)keys, n, seed); break;
+    case KK_F32: k_tune_fill<KK_F32><<<grid, 256, 0, s>>>((uint32_t*)keys, n, seed); break;
+    case KK_F64: k_tune_fill<KK_F64><<<grid, 256, 0, s>>>((uint64_t*)keys, n, seed); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -19,13 +19,6 @@ static bool partial_overlap(const void* a, const void* b, size_t bytes) {
   return x < y + bytes && y < x + bytes;
 }
 
-#define AHS_TRY(expr)                    \
-  do {                                   \
-    ahs_status st__ = (expr);            \
-    if (st__ != AHS_OK) return st__;     \
-  } while (0)
-
-#define AHS_HIP(j, call, what) AHS_TRY((j).ctx->check((call), (what)))
 
 // Enqueues min/max, reads the feature header back (one sync).
 static ahs_status step_minmax(SortJob& j) {

@@ -64,21 +64,30 @@ def near_threshold(rf):
     return abs(rf.entropy_bits - thr) <= H_RTOL * thr
 
 
-def run_segments(keys, offs, vals=None, strategy=ahs.AUTO, preset=0, in_place=False):
-    """Sorts all segments in one call and checks every segment against the
-    oracle.  Returns the host array of decisions."""
+def run_segments(keys, offs, vals=None, strategy=ahs.AUTO, preset=0, in_place=False, mode="blocking", hint=0):
+    """Sorts all segments in one call (blocking, enqueue-only or a captured
+    graph) and checks every segment against the oracle.  Returns the host
+    array of decisions."""
     nseg = len(offs) - 1
-    say(f"segmented nseg={nseg} n={keys.size} dtype={keys.dtype} payload={vals is not None} "
+    say(f"segmented mode={mode} nseg={nseg} n={keys.size} dtype={keys.dtype} payload={vals is not None} "
         f"strategy={strategy} inplace={in_place} max_seg={int(np.max(np.diff(offs.astype(np.int64)), initial=0))}")
     k = to_dev(keys)
     v = to_dev(vals) if vals is not None else None
     o = to_dev(offs)
     cfg = ahs.ahs_config_init(preset)
-    if in_place:
-        ko, vo, chosen, feats = ahs.ahs_sort_segmented(k, o, v, strategy, cfg, out=k, out_values=v,
-                                                       want_features=True)
+    outs = dict(out=k, out_values=v) if in_place else {}
+    if mode == "blocking":
+        ko, vo, chosen, feats = ahs.ahs_sort_segmented(k, o, v, strategy, cfg, want_features=True, **outs)
+    elif mode == "async":
+        ko, vo, chosen, feats, status = ahs.ahs_sort_segmented_async(k, o, v, strategy, cfg, max_seg_hint=hint,
+                                                                     want_features=True, **outs)
+        assert int(status.item()) == 0
     else:
-        ko, vo, chosen, feats = ahs.ahs_sort_segmented(k, o, v, strategy, cfg, want_features=True)
+        g = ahs.SegmentedGraph(k, o, v, strategy, cfg, max_seg_hint=hint, want_features=True, **outs)
+        g.launch()
+        torch.cuda.synchronize()
+        assert int(g.status.item()) == 0
+        ko, vo, chosen, feats = g.out, g.out_values, g.chosen, g.feats
     torch.cuda.synchronize()
     ko = ko.cpu().numpy()
     vo = vo.cpu().numpy() if vals is not None else None
@@ -231,3 +240,120 @@ def test_segmented_errors():
     # zero segments is a no-op
     out, _, chosen, _ = ahs.ahs_sort_segmented(k[:0], to_dev(np.array([0], np.uint64)))
     assert out.numel() == 0 and chosen.numel() == 0
+
+
+# ------------------------------------------------------------------ enqueue-only form, graphs, autotuner
+@pytest.mark.parametrize("hint", [0, 1 << 15])
+def test_segmented_async_mixed(hint):
+    keys, offs, _ = gen.segments(nseg=300, seed=41, sizes=mixed_sizes(300, 41, 1 << 15))
+    run_segments(keys, offs, np.arange(keys.size, dtype=np.uint32), mode="async", hint=hint)
+
+
+def test_segmented_async_multilevel_and_wide():
+    sizes = [(1 << 21) + 3, 9000, 0, 7, 300_000, 8193, 65_536, 5000]
+    keys, offs, _ = gen.segments(nseg=len(sizes), seed=42, sizes=np.array(sizes))
+    run_segments(keys, offs, mode="async")
+    n = int(offs[-1])
+    wide = gen.wide_keys("u64zipf4096", n=n)
+    run_segments(wide, offs, np.arange(n, dtype=np.uint32), mode="async", hint=(1 << 21) + 3)
+    f = gen.wide_keys("f32normal", n=n)
+    f[5] = np.nan
+    run_segments(f, offs, np.arange(n, dtype=np.uint32), mode="async", in_place=True)
+
+
+def test_segmented_async_invalid_offsets_write_nothing():
+    k = to_dev(np.arange(100, dtype=np.uint32)[::-1].copy())
+    out = torch.full((100,), 7, dtype=torch.int32, device=DEV).view(torch.uint32)
+    o = to_dev(np.array([0, 60, 50, 100], np.uint64))
+    _, _, _, _, status = ahs.ahs_sort_segmented_async(k, o, out=out)
+    assert int(status.item()) & ahs.SEG_ERR_OFFSETS
+    assert (out.view(torch.int32) == 7).all()
+
+
+def test_segmented_async_hint_too_small_is_reported():
+    """A segment above the size hint with no level launched for it is
+    reported in the status word (its output is not sorted)."""
+    sizes = [100, 20_000, 50]
+    keys, offs, _ = gen.segments(nseg=3, seed=43, sizes=np.array(sizes))
+    k = to_dev(keys)
+    ko, _, _, _, status = ahs.ahs_sort_segmented_async(k, to_dev(offs), max_seg_hint=100)
+    assert int(status.item()) == ahs.SEG_ERR_LEVELS
+    # the small segments are still sorted
+    ko = ko.cpu().numpy()
+    assert np.array_equal(ko[:100], np.sort(keys[:100]))
+
+
+def test_segmented_graph_replays():
+    """One capture, several replays with the program's own eager work and
+    synchronisations in between; every replay is checked against the eager
+    (blocking) result for the inputs it saw."""
+    sizes = mixed_sizes(120, 44, 1 << 15)
+    sizes[-1] = 70_000
+    offs = offsets_of(sizes)
+    n = int(offs[-1])
+    k = torch.empty(n, dtype=torch.uint32, device=DEV)
+    o = to_dev(offs)
+    g = ahs.SegmentedGraph(k, o, max_seg_hint=70_000, want_features=True)
+    for rep in range(3):
+        keys, _, _ = gen.segments(nseg=len(sizes), seed=50 + rep, sizes=sizes)
+        k.copy_(to_dev(keys))
+        torch.cuda.synchronize()
+        say(f"graph replay {rep}")
+        g.launch()
+        torch.cuda.synchronize()
+        assert int(g.status.item()) == 0
+        eo, _, ech, ef = ahs.ahs_sort_segmented(k, o, want_features=True)
+        torch.cuda.synchronize()
+        assert torch.equal(g.out, eo), rep
+        assert torch.equal(g.chosen, ech), rep
+        assert torch.equal(g.feats, ef), rep
+        # and against the oracle on a few segments
+        gk = g.out.cpu().numpy()
+        for s in (0, 9, len(sizes) - 1):
+            a, b = int(offs[s]), int(offs[s + 1])
+            assert np.array_equal(gk[a:b], np.sort(keys[a:b]))
+        g.out.view(torch.int32).fill_(0)  # eager work between replays
+
+
+def test_segmented_graph_matches_oracle():
+    keys, offs, _ = gen.segments(nseg=200, seed=45, sizes=mixed_sizes(200, 45, 1 << 15))
+    run_segments(keys, offs, np.arange(keys.size, dtype=np.uint32), mode="graph")
+
+
+@pytest.mark.parametrize("dt", [ahs.U32, ahs.F64])
+@pytest.mark.parametrize("pay", [False, True])
+def test_autotune_choices_valid(dt, pay):
+    caps, ms = ahs.ahs_segmented_autotune(dt, pay)
+    say(f"autotune dtype={dt} payload={pay}: {caps} {ms}")
+    for c, cap in enumerate(caps):
+        assert cap in (1024, 2048, 4096, 8192) and cap >= (1024 << c)
+        assert ms[c] > 0
+    assert ahs.ahs_segmented_get_variants(dt, pay) == caps
+
+
+def test_every_variant_gives_identical_results():
+    keys, offs, _ = gen.segments(nseg=200, seed=46, sizes=mixed_sizes(200, 46, 1 << 13))
+    vals = np.arange(keys.size, dtype=np.uint32)
+    k, o, v = to_dev(keys), to_dev(offs), to_dev(vals)
+    saved = ahs.ahs_segmented_get_variants(ahs.U32, True)
+    results = []
+    try:
+        for caps in ([1024, 2048, 4096, 8192], [8192] * 4, [2048, 2048, 8192, 8192], [4096, 4096, 4096, 8192]):
+            ahs.ahs_segmented_set_variants(ahs.U32, caps, True)
+            ko, vo, ch, f = ahs.ahs_sort_segmented(k, o, v, want_features=True)
+            torch.cuda.synchronize()
+            results.append((ko.clone(), vo.clone(), ch.clone(), f.clone()))
+    finally:
+        ahs.ahs_segmented_set_variants(ahs.U32, saved, True)
+    ref = ahs.feature_records(results[0][3])
+    for r in results[1:]:
+        for x, y in zip(results[0][:3], r[:3]):
+            assert torch.equal(x, y)
+        # features: integer fields equal; entropy sums differ only in the
+        # order the workgroup adds its terms
+        for fa, fb in zip(ref, ahs.feature_records(r[3])):
+            assert (fa.n, fa.min_key, fa.max_key, fa.span, fa.nan_count, fa.shift, fa.nbins, fa.exact) == \
+                (fb.n, fb.min_key, fb.max_key, fb.span, fb.nan_count, fb.shift, fb.nbins, fb.exact)
+            assert abs(fa.entropy_bits - fb.entropy_bits) <= 1e-12 * max(1.0, fa.entropy_bits)
+    with pytest.raises(ahs.AhsError):
+        ahs.ahs_segmented_set_variants(ahs.U32, [1024, 1024, 4096, 8192], True)
