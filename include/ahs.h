@@ -242,6 +242,72 @@ ahs_status ahs_segmented_autotune(ahs_context* ctx, ahs_dtype dtype, int with_pa
 ahs_status ahs_segmented_get_variants(ahs_context* ctx, ahs_dtype dtype, int with_payload, int* h_caps);
 ahs_status ahs_segmented_set_variants(ahs_context* ctx, ahs_dtype dtype, int with_payload, const int* h_caps);
 
+/* Serving loop.  Sort requests of different sizes and key types arrive
+ * over time; the server keeps their buffers on the device inside one arena
+ * of hbm_budget_bytes (allocated by ahs_server_create), admits a batch only
+ * when its buffers (inputs, outputs, payloads, offsets and the batched
+ * sort's workspace) fit in the free part of the arena, and runs batches on
+ * `slots` streams at once.  Batching is continuous: whenever a slot is
+ * free, the oldest pending request and the later pending requests of the
+ * same key type and payload flag (in arrival order, up to max_batch_keys
+ * keys and max_batch_requests requests; the oldest is always taken) form a
+ * batch, sorted by the enqueue-only batched sort.  Each request's result is
+ * identical to ahs_sort(AUTO) of that request alone; its reported strategy
+ * is its own FSM decision.  A request that cannot fit even in an empty arena
+ * completes with AHS_E_OOM.  Latency = completion (the batch's completion
+ * event, on the server clock) - arrival (given, or the submit time).
+ * One host thread drives a server; the calls are not thread-safe.
+ *
+ * ahs_server_submit: the input (and payload) buffers are the caller's and
+ * must stay unmodified until the request completes; the server records an
+ * event on src_stream (the stream that produced the input) and orders its
+ * copy after it.  arrival_ms < 0 means now (ahs_server_now_ms clock).
+ * ahs_server_poll: advances the loop, returns up to `max` finished requests
+ * (each once), waiting up to wait_ms for at least one while work remains.
+ * Results point into the arena (d_keys_out, d_vals_out) and stay valid until
+ * ahs_server_release(id); a batch's memory returns to the arena when all its
+ * requests are released, so unreleased results hold back admission. */
+typedef struct ahs_server ahs_server;
+typedef struct {
+  uint64_t hbm_budget_bytes;     /* arena size: the admission limit */
+  uint64_t max_batch_keys;
+  uint32_t max_batch_requests;   /* 1..65535 */
+  uint32_t slots;                /* batches in flight at once, 1..16 */
+  uint32_t autotune;             /* run ahs_segmented_autotune for every key type at creation */
+  uint32_t reserved;
+  ahs_config cfg;                /* decision thresholds; use_model must be 0 */
+} ahs_server_config;
+typedef struct {
+  uint64_t id;
+  int32_t status;                /* AHS_OK, AHS_E_OOM, or AHS_E_DEVICE */
+  int32_t chosen;                /* the request's strategy code (0xFD: holds NaN keys) */
+  uint64_t n;
+  ahs_dtype dtype;
+  int32_t reserved;
+  const void* d_keys_out;
+  const uint32_t* d_vals_out;    /* null without payload */
+  double arrival_ms, done_ms;
+} ahs_server_result;
+typedef struct {
+  uint64_t submitted, completed, failed, pending, running_batches, batches;
+  uint64_t keys_completed;
+  double mean_batch_requests;
+  double p50_ms, p99_ms, max_ms, mean_ms;   /* latency of completed requests (nearest rank) */
+  double first_arrival_ms, last_done_ms;
+  double gkeys_per_s;                        /* keys completed / (last completion - first arrival) */
+  uint64_t arena_used_bytes, arena_peak_bytes;
+} ahs_server_statistics;
+void ahs_server_config_init(ahs_server_config* cfg);
+ahs_status ahs_server_create(int device, const ahs_server_config* cfg, ahs_server** out);
+double ahs_server_now_ms(ahs_server* server);
+ahs_status ahs_server_submit(ahs_server* server, ahs_dtype dtype, uint64_t n, const void* d_keys,
+                             const uint32_t* d_vals, void* src_stream, double arrival_ms, uint64_t* out_id);
+ahs_status ahs_server_poll(ahs_server* server, ahs_server_result* out, uint32_t max, uint32_t* count,
+                           double wait_ms);
+ahs_status ahs_server_release(ahs_server* server, uint64_t id);
+ahs_status ahs_server_stats(ahs_server* server, ahs_server_statistics* out);
+void ahs_server_destroy(ahs_server* server);
+
 /* Learned predictor (Sec. III-H, Listing 5): gradient-boosted trees over
  * (n, k, H) in the project's text format
  *   ahs-gbt 1 / num_class 3 / base_score s0 s1 s2 / num_trees T /

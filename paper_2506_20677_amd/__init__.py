@@ -58,6 +58,30 @@ class Config(C.Structure):
                 ("k_count_cap", C.c_uint64)]
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_batch_keys", C.c_uint64),
+                ("max_batch_requests", C.c_uint32), ("slots", C.c_uint32), ("autotune", C.c_uint32),
+                ("reserved", C.c_uint32), ("cfg", Config)]
+
+
+class ServerResult(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("status", C.c_int32), ("chosen", C.c_int32), ("n", C.c_uint64),
+                ("dtype", C.c_int32), ("reserved", C.c_int32), ("d_keys_out", C.c_void_p),
+                ("d_vals_out", C.c_void_p), ("arrival_ms", C.c_double), ("done_ms", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("failed", C.c_uint64),
+                ("pending", C.c_uint64), ("running_batches", C.c_uint64), ("batches", C.c_uint64),
+                ("keys_completed", C.c_uint64), ("mean_batch_requests", C.c_double),
+                ("p50_ms", C.c_double), ("p99_ms", C.c_double), ("max_ms", C.c_double), ("mean_ms", C.c_double),
+                ("first_arrival_ms", C.c_double), ("last_done_ms", C.c_double), ("gkeys_per_s", C.c_double),
+                ("arena_used_bytes", C.c_uint64), ("arena_peak_bytes", C.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 _lock = threading.Lock()
 
@@ -98,6 +122,14 @@ def lib():
             "ahs_segmented_autotune": (i32, [vp, i32, i32, vp, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
             "ahs_segmented_get_variants": (i32, [vp, i32, i32, C.POINTER(C.c_int)]),
             "ahs_segmented_set_variants": (i32, [vp, i32, i32, C.POINTER(C.c_int)]),
+            "ahs_server_config_init": (None, [C.POINTER(ServerConfig)]),
+            "ahs_server_create": (i32, [i32, C.POINTER(ServerConfig), C.POINTER(vp)]),
+            "ahs_server_now_ms": (C.c_double, [vp]),
+            "ahs_server_submit": (i32, [vp, i32, u64, vp, vp, vp, C.c_double, C.POINTER(C.c_uint64)]),
+            "ahs_server_poll": (i32, [vp, C.POINTER(ServerResult), u32, C.POINTER(C.c_uint32), C.c_double]),
+            "ahs_server_release": (i32, [vp, u64]),
+            "ahs_server_stats": (i32, [vp, C.POINTER(ServerStats)]),
+            "ahs_server_destroy": (None, [vp]),
             "ahs_model_load": (i32, [C.c_char_p, C.POINTER(vp)]),
             "ahs_model_free": (None, [vp]),
             "ahs_model_predict": (i32, [vp, C.POINTER(FeatureVector), C.POINTER(C.c_int)]),
@@ -452,6 +484,120 @@ def ahs_segmented_set_variants(dtype: int, caps, with_payload: bool = False, ctx
     st = lib().ahs_segmented_set_variants(ctx.handle, dtype, 1 if with_payload else 0, arr)
     if st != OK:
         _raise(st, ctx)
+
+
+class Server:
+    """The serving loop (continuous batching under an HBM budget).  Results
+    are device tensors viewing the server's arena, valid until release()."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int | None = None, max_batch_keys: int | None = None,
+                 max_batch_requests: int | None = None, slots: int | None = None, autotune: bool = False,
+                 cfg: Config | None = None):
+        c = ServerConfig()
+        lib().ahs_server_config_init(C.byref(c))
+        if hbm_budget_bytes is not None:
+            c.hbm_budget_bytes = hbm_budget_bytes
+        if max_batch_keys is not None:
+            c.max_batch_keys = max_batch_keys
+        if max_batch_requests is not None:
+            c.max_batch_requests = max_batch_requests
+        if slots is not None:
+            c.slots = slots
+        c.autotune = 1 if autotune else 0
+        if cfg is not None:
+            c.cfg = cfg
+        h = C.c_void_p()
+        st = lib().ahs_server_create(device, C.byref(c), C.byref(h))
+        if st != OK:
+            _raise(st)
+        self.handle = h
+        self.device = device
+        self._inputs = {}  # id -> tensors kept alive until completion
+
+    def now_ms(self) -> float:
+        return lib().ahs_server_now_ms(self.handle)
+
+    def submit(self, keys: torch.Tensor, values: torch.Tensor | None = None, dtype: int | None = None,
+               arrival_ms: float = -1.0, stream=None) -> int:
+        code = dtype_code(keys, dtype)
+        _check_keys(keys, code)
+        if values is not None and (values.numel() != keys.numel() or values.element_size() != 4
+                                   or not values.is_contiguous()):
+            raise ValueError("values must be a contiguous device tensor of n 32-bit elements")
+        rid = C.c_uint64()
+        st = lib().ahs_server_submit(self.handle, code, keys.numel(), C.c_void_p(keys.data_ptr()),
+                                     C.c_void_p(values.data_ptr()) if values is not None else None,
+                                     _stream_handle(stream), arrival_ms, C.byref(rid))
+        if st != OK:
+            _raise(st)
+        self._inputs[rid.value] = (keys, values)
+        return rid.value
+
+    def poll(self, max_results: int = 256, wait_ms: float = 0.0) -> list:
+        """Finished requests as dicts: id, status, chosen, n, dtype, keys and
+        values (device tensors viewing the arena), arrival_ms, done_ms."""
+        arr = (ServerResult * max_results)()
+        cnt = C.c_uint32()
+        st = lib().ahs_server_poll(self.handle, arr, max_results, C.byref(cnt), wait_ms)
+        if st != OK:
+            _raise(st)
+        out = []
+        for i in range(cnt.value):
+            r = arr[i]
+            keys = vals = None
+            if r.status == OK:
+                keys = _device_view(r.d_keys_out, r.n, _KEY_TORCH[r.dtype], self.device)
+                if r.dtype == U32:
+                    keys = keys.view(torch.uint32)
+                elif r.dtype == U64:
+                    keys = keys.view(torch.uint64)
+                if r.d_vals_out:
+                    vals = _device_view(r.d_vals_out, r.n, torch.int32, self.device).view(torch.uint32)
+            self._inputs.pop(r.id, None)
+            out.append({"id": r.id, "status": r.status, "chosen": r.chosen, "n": r.n, "dtype": r.dtype,
+                        "keys": keys, "values": vals, "arrival_ms": r.arrival_ms, "done_ms": r.done_ms})
+        return out
+
+    def release(self, rid: int):
+        st = lib().ahs_server_release(self.handle, rid)
+        if st != OK:
+            _raise(st)
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        st = lib().ahs_server_stats(self.handle, C.byref(s))
+        if st != OK:
+            _raise(st)
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.ahs_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+_KEY_TORCH = {U32: torch.int32, U64: torch.int64, F32: torch.float32, F64: torch.float64}
+
+
+class _DevBuf:
+    """Minimal __cuda_array_interface__ holder for memory owned by the library."""
+
+    def __init__(self, ptr, n, typestr, device):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": typestr, "data": (ptr, False), "version": 3,
+                                         "strides": None, "stream": None}
+        self.device = device
+
+
+def _device_view(ptr: int, n: int, tdtype, device: int) -> torch.Tensor:
+    """A torch tensor aliasing n elements at a device address the library owns."""
+    typestr = {torch.int32: "<i4", torch.int64: "<i8", torch.float32: "<f4", torch.float64: "<f8"}[tdtype]
+    if n == 0:
+        return torch.empty(0, dtype=tdtype, device=f"cuda:{device}")
+    with torch.cuda.device(device):
+        return torch.as_tensor(_DevBuf(ptr, n, typestr, device), device=f"cuda:{device}")
 
 
 def feature_records(feats: torch.Tensor) -> list:

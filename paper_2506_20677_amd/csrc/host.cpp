@@ -22,11 +22,11 @@ static_assert(sizeof(ahs_feature_vector) == sizeof(DevFeatures), "feature vector
 // ------------------------------------------------------------------ context
 ahs_context::~ahs_context() {
   for (auto& r : pending) {
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
   }
-  for (auto e : event_pool) hipEventDestroy(e);
-  if (pinned) hipHostFree(pinned);
+  for (auto e : event_pool) (void)hipEventDestroy(e);
+  if (pinned) (void)hipHostFree(pinned);
 }
 
 ahs_status ahs_context::fail(ahs_status s, const char* fmt, ...) {
@@ -51,7 +51,7 @@ hipEvent_t ahs_context::take_event() {
     return e;
   }
   hipEvent_t e = nullptr;
-  hipEventCreate(&e);
+  (void)hipEventCreate(&e);
   return e;
 }
 
@@ -62,20 +62,20 @@ void ahs_context::prof_begin(const char* name, hipStream_t s, double bytes) {
   r.bytes = bytes;
   r.a = take_event();
   r.b = take_event();
-  hipEventRecord(r.a, s);
+  (void)hipEventRecord(r.a, s);
   pending.push_back(r);
 }
 
 void ahs_context::prof_end(hipStream_t s) {
   if (!profiling || capturing || pending.empty()) return;
-  hipEventRecord(pending.back().b, s);
+  (void)hipEventRecord(pending.back().b, s);
 }
 
 void ahs_context::prof_collect() {
   for (auto& r : pending) {
-    hipEventSynchronize(r.b);
+    (void)hipEventSynchronize(r.b);
     float ms = 0.f;
-    hipEventElapsedTime(&ms, r.a, r.b);
+    (void)hipEventElapsedTime(&ms, r.a, r.b);
     auto& t = totals[r.name];
     t.launches += 1;
     t.ms += ms;
