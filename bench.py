@@ -12,6 +12,15 @@ Prints one JSON line: whole-job Gkeys/s, the dominant kernel's roofline
 (algorithmic bytes per launch over its average launch time, both measured
 with HIP events on the launch stream), the CPU oracle on a bounded sample,
 and per-array AUTO-vs-forced-strategy timings with %HBM of each path.
+
+Two further sections, reported beside the headline (not in `value`):
+* batched: 65,536 uint32 segments, sizes log-uniform on [16, 2^20] (about
+  6.2e9 keys), distributions mixed per segment; the autotuned, graph-captured
+  batched sort against a host loop of per-array AHS AUTO calls.
+* serving: Poisson arrivals at 2,000 requests/s, sizes log-uniform on
+  [2^10, 2^24], key types u32/u64/f32, half with payload, 48 GB admission
+  budget; the serving loop against one-at-a-time AHS AUTO on one stream, in
+  real time (latency p50/p99) and as a burst (throughput).
 """
 import argparse
 import json
@@ -71,6 +80,189 @@ def measured_traffic(kernel, tag):
     return k["fetch_bytes_per_launch"] + (k["write_bytes_per_launch"] or 0)
 
 
+def percentile(xs, q):
+    """Nearest-rank percentile."""
+    import math
+    v = sorted(xs)
+    if not v:
+        return None
+    return v[max(1, min(len(v), math.ceil(q / 100.0 * len(v)))) - 1]
+
+
+def batched_section(args, ahs, gen, torch, np):
+    """65,536 segments in one batched call (autotuned, graph-captured) against
+    a host loop of per-array AUTO sorts of the same segments."""
+    dev = torch.device("cuda:0")
+    t = time.time()
+    keys_h, offs_h, kinds = gen.segments(nseg=args.seg_count, seed=8)
+    n = keys_h.size
+    log(f"[bench] batched workload: {args.seg_count} segments, {n} keys, generated in {time.time() - t:.1f}s")
+    keys = torch.from_numpy(keys_h).to(dev)
+    offs = torch.from_numpy(offs_h.view(np.int64)).to(dev)
+    sizes = np.diff(offs_h.astype(np.int64))
+    del keys_h
+    torch.cuda.synchronize()
+    ctx = ahs.default_context(0)
+    caps, tune_ms = ahs.ahs_segmented_autotune(ahs.U32, False, ctx)
+    log(f"[bench] autotuned size-class variants {caps}")
+    # blocking call (one host read per sample-sort level)
+    out_b, _, chosen_b, _ = ahs.ahs_sort_segmented(keys, offs, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.seg_reps):
+        ahs.ahs_sort_segmented(keys, offs, out=out_b, ctx=ctx)
+    torch.cuda.synchronize()
+    blocking_s = (time.perf_counter() - t0) / args.seg_reps
+    # graph-captured enqueue-only call
+    g = ahs.SegmentedGraph(keys, offs, ctx=ctx, max_seg_hint=int(sizes.max()))
+    g.launch()
+    torch.cuda.synchronize()
+    status = int(g.status.item())
+    t0 = time.perf_counter()
+    for _ in range(args.seg_reps):
+        g.launch()
+    torch.cuda.synchronize()
+    graph_s = (time.perf_counter() - t0) / args.seg_reps
+    same_graph = bool(torch.equal(g.out.view(torch.int32), out_b.view(torch.int32)))
+    same_chosen = bool(torch.equal(g.chosen, chosen_b))
+    del g
+    torch.cuda.empty_cache()
+    # host loop of plain per-array calls
+    out_l = torch.empty_like(keys)
+    ws = ctx.workspace(ahs.ahs_workspace_bytes(int(sizes.max()), ahs.U32, False, ahs.AUTO))
+    bounds = offs_h.astype(np.int64).tolist()
+    loop_chosen = np.empty(args.seg_count, np.uint8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.seg_count):
+        a, b = bounds[i], bounds[i + 1]
+        _, _, ch, _ = ahs.ahs_sort(keys[a:b], out=out_l[a:b], ctx=ctx)
+        loop_chosen[i] = ch
+    torch.cuda.synchronize()
+    loop_s = time.perf_counter() - t0
+    same_loop = bool(torch.equal(out_l.view(torch.int32), out_b.view(torch.int32)))
+    agree = float(np.mean(loop_chosen == chosen_b.cpu().numpy()))
+    del out_l, ws
+    kinds_count = {k: int(np.sum(kinds == i)) for i, k in enumerate(gen.SEG_KINDS)}
+    res = {
+        "workload": f"{args.seg_count} uint32 segments, sizes log-uniform on [16, 2^20] (seed 8), "
+                    f"{n} keys; per-segment kinds {kinds_count}",
+        "keys": n, "autotuned_caps": caps, "autotune_kernel_ms": [round(x, 4) for x in tune_ms],
+        "graph_ms": round(graph_s * 1e3, 3), "graph_gkeys_s": round(n / graph_s / 1e9, 3),
+        "blocking_ms": round(blocking_s * 1e3, 3), "blocking_gkeys_s": round(n / blocking_s / 1e9, 3),
+        "loop_ms": round(loop_s * 1e3, 3), "loop_gkeys_s": round(n / loop_s / 1e9, 3),
+        "speedup_graph_vs_loop": round(loop_s / graph_s, 2), "graph_status": status,
+        "identical_outputs": same_graph and same_loop, "decisions_equal_graph_blocking": same_chosen,
+        "decisions_agree_with_loop": round(agree, 6),
+    }
+    log(f"[bench] batched {json.dumps(res)}")
+    del keys, offs, out_b
+    torch.cuda.empty_cache()
+    return res
+
+
+def serving_section(args, ahs, gen, torch, np):
+    """The request trace through the serving loop and through one-at-a-time
+    plain AUTO sorts, in real time and as a burst."""
+    dev = torch.device("cuda:0")
+    tr = gen.request_trace(duration_s=args.serve_seconds)
+    m = len(tr["arrival_s"])
+    pool_n = 1 << 26
+    pools = {}
+    for k in gen.POOL_KINDS:
+        pools[k] = torch.from_numpy(gen.request_pool(k, n=pool_n)).to(dev)
+    pay_pool = torch.arange(pool_n, dtype=torch.int32, device=dev).view(torch.uint32)
+    torch.cuda.synchronize()
+    reqs = []
+    for i in range(m):
+        n = int(tr["size"][i])
+        kind = gen.request_pool_kind(int(tr["dtype"][i]), int(tr["dist"][i]))
+        off = int(tr["offset"][i]) % (pool_n - n + 1)
+        reqs.append((float(tr["arrival_s"][i]) * 1e3, kind, off, n, bool(tr["payload"][i])))
+    total_keys = sum(r[3] for r in reqs)
+    log(f"[bench] serving trace: {m} requests over {args.serve_seconds}s, {total_keys} keys")
+
+    def view(r):
+        _, kind, off, n, pay = r
+        return pools[kind][off:off + n], (pay_pool[off:off + n] if pay else None)
+
+    def served(burst):
+        srv = ahs.Server(hbm_budget_bytes=int(args.serve_budget_gb * 1e9), slots=4, autotune=True)
+        start = srv.now_ms() + 20.0
+        i, outstanding, done, checked = 0, 0, 0, 0
+        while i < m or outstanding:
+            now = srv.now_ms()
+            while i < m and (burst or start + reqs[i][0] <= now):
+                k, v = view(reqs[i])
+                srv.submit(k, v, arrival_ms=start if burst else start + reqs[i][0])
+                i += 1
+                outstanding += 1
+            for r in srv.poll(wait_ms=0.0 if i < m else 50.0):
+                if r["status"] != ahs.OK:
+                    raise RuntimeError(f"request {r['id']} failed with status {r['status']}")
+                if done % 997 == 0 and r["n"] > 1:  # spot check on the device
+                    x = r["keys"]
+                    if x.dtype == torch.uint32:
+                        x = x.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+                    elif x.dtype == torch.uint64:
+                        x = x.view(torch.int64) ^ (-(2 ** 63))  # unsigned order as signed
+                    assert bool((x[1:] >= x[:-1]).all().item()), "unsorted result"
+                    checked += 1
+                srv.release(r["id"])
+                outstanding -= 1
+                done += 1
+        st = srv.stats()
+        srv.close()
+        return {"p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3), "max_ms": round(st["max_ms"], 3),
+                "gkeys_s": round(st["gkeys_per_s"], 3), "batches": st["batches"],
+                "mean_batch_requests": round(st["mean_batch_requests"], 2),
+                "arena_peak_GB": round(st["arena_peak_bytes"] / 1e9, 3), "spot_checked": checked}
+
+    def plain(burst):
+        ctx = ahs.default_context(0)
+        ctx.workspace(ahs.ahs_workspace_bytes(1 << 24, ahs.U64, True, ahs.AUTO))
+        out_k = torch.empty(1 << 24, dtype=torch.int64, device=dev)
+        out_v = torch.empty(1 << 24, dtype=torch.int32, device=dev).view(torch.uint32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter() * 1e3 + 20.0
+        lat, last = [], 0.0
+        for r in reqs:
+            a = t0 if burst else t0 + r[0]
+            while time.perf_counter() * 1e3 < a:
+                pass
+            k, v = view(r)
+            o = out_k.view(k.dtype)[:k.numel()] if k.element_size() == 8 else \
+                out_k.view(torch.int32)[:k.numel()].view(k.dtype)
+            ahs.ahs_sort(k, v, out=o, out_values=out_v[:k.numel()] if v is not None else None, ctx=ctx)
+            torch.cuda.synchronize()
+            last = time.perf_counter() * 1e3
+            lat.append(last - a)
+        del out_k, out_v
+        return {"p50_ms": round(percentile(lat, 50), 3), "p99_ms": round(percentile(lat, 99), 3),
+                "max_ms": round(max(lat), 3), "gkeys_s": round(total_keys / ((last - t0) * 1e-3) / 1e9, 3)}
+
+    res = {"workload": f"Poisson arrivals 2000/s for {args.serve_seconds}s ({m} requests, {total_keys} keys), "
+                       "sizes log-uniform on [2^10, 2^24], u32/u64/f32 (uniform or Zipf(1.0) over 4,096 values; "
+                       f"f32 Normal), half with payload; budget {args.serve_budget_gb} GB, 4 slots",
+           "offered_gkeys_s": round(total_keys / args.serve_seconds / 1e9, 3)}
+    modes = args.serve_modes.split(",")
+    for mode, burst in (("realtime", False), ("burst", True)):
+        for kind, fn in (("served", served), ("plain", plain)):
+            if kind not in modes:
+                continue
+            t = time.time()
+            res[f"{kind}_{mode}"] = fn(burst)
+            log(f"[bench] {kind} {mode} in {time.time() - t:.1f}s: {res[f'{kind}_{mode}']}")
+    if "served" in modes and "plain" in modes:
+        res["p99_served_over_plain_realtime"] = round(
+            res["served_realtime"]["p99_ms"] / res["plain_realtime"]["p99_ms"], 3)
+        res["throughput_served_over_plain_burst"] = round(
+            res["served_burst"]["gkeys_s"] / res["plain_burst"]["gkeys_s"], 3)
+    del pools, pay_pool
+    torch.cuda.empty_cache()
+    return res
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +278,16 @@ def parse():
     ap.add_argument("--only", default=None, help="comma list of sweep cases to run")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain elementwise copy of 2^log2n 32-bit words first (counter calibration)")
+    ap.add_argument("--headline", action=argparse.BooleanOptionalAction, default=True,
+                    help="the strategy sweep (the reported value); --no-headline runs only the other sections")
+    ap.add_argument("--batched", action=argparse.BooleanOptionalAction, default=True)
+    ap.add_argument("--seg-count", type=int, default=65536, help="segments in the batched workload")
+    ap.add_argument("--seg-reps", type=int, default=3, help="timed graph replays of the batched sort")
+    ap.add_argument("--serve", action=argparse.BooleanOptionalAction, default=True)
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="seconds of the Poisson request trace replayed in real time")
+    ap.add_argument("--serve-budget-gb", type=float, default=48.0)
+    ap.add_argument("--serve-modes", default="served,plain", help="which serving runs: served, plain or both")
     return ap.parse_args()
 
 
@@ -105,6 +307,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if not args.headline:
+        side = {"batched": batched_section(args, ahs, gen, torch, np) if args.batched else None,
+                "serving": serving_section(args, ahs, gen, torch, np) if args.serve else None}
+        print(json.dumps({"metric": METRIC, "value": None, "note": "sections only (--no-headline)", **side}),
+              flush=True)
+        return
     n = 1 << args.log2n
     cases = list(gen.SWEEP_CASES) if not args.only else args.only.split(",")
 
@@ -242,6 +450,12 @@ def main():
                          f"single-threaded C oracle, {tot_t:.1f} s total", **host_info()}
         log(f"[bench] cpu baseline {cpu}")
 
+    # ------------------------------------------------------------ batched and serving sections
+    del dkeys, out, host
+    torch.cuda.empty_cache()
+    batched = batched_section(args, ahs, gen, torch, np) if args.batched else None
+    serving = serving_section(args, ahs, gen, torch, np) if args.serve else None
+
     res = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
@@ -249,6 +463,7 @@ def main():
         "config": {"workload": f"strategy sweep: {len(cases)} arrays x 2^{args.log2n} uint32 ({', '.join(cases)}), "
                                "AHS AUTO per array", "n_per_array": n, "arrays": cases, "auto_choices": chosen},
         "roofline": roofline, "cpu_baseline": cpu, "step_kernels": step_kernels, "per_case": per_case,
+        "batched": batched, "serving": serving,
     }
     print(json.dumps(res), flush=True)
 

@@ -50,6 +50,8 @@ def lib():
         L.gen_exponential.argtypes = [u64, u64, u64, C.c_double, vp]
         L.gen_unit.argtypes = [u64, u64, u64, vp]
         L.gen_apply_swaps.argtypes = [vp, u64, C.c_uint32, u64, u64, u64]
+        L.gen_segments_u32.argtypes = [u64, C.c_uint32, vp, vp, vp, vp]
+        L.gen_segments_u32.restype = C.c_int
         _lib = L
     return _lib
 
@@ -197,30 +199,46 @@ def segment_sizes(nseg, seed=8, lo_exp=4, span_exp=16, cap=1 << 20, lo=16):
 def segments(nseg=65536, seed=8, sizes=None):
     """Concatenated u32 segments and their u64 offsets[nseg + 1]; each segment's
     distribution is drawn from SEG_KINDS (stream 1) and its keys from a
-    stream of its own."""
+    stream of its own (1000 + segment index); see gen_segments_u32."""
     if sizes is None:
         sizes = segment_sizes(nseg, seed)
+    sizes = np.ascontiguousarray(sizes, dtype=np.int64)
+    nseg = sizes.size
     kinds = (index(seed, 1, nseg, len(SEG_KINDS))).astype(np.int64)
     offs = np.zeros(nseg + 1, np.uint64)
     np.cumsum(sizes, out=offs[1:])
     keys = np.empty(int(offs[-1]), np.uint32)
-    for i in range(nseg):
-        n = int(sizes[i])
-        st = 1000 + i
-        kind = SEG_KINDS[kinds[i]]
-        if kind == "u256":
-            v = u32(seed, st, n, 255)
-        elif kind == "u32":
-            v = u32(seed, st, n)
-        elif kind == "zipf64":
-            vals = distinct(seed * 7919 + i, 1, 64, 32)
-            v = vals[zipf_index(seed * 7919 + i, 2, n, 1.1, 64)]
-        elif kind == "sorted":
-            v = np.sort(u32(seed, st, n))
-        else:
-            v = np.sort(u32(seed, st, n))[::-1]
-        keys[int(offs[i]): int(offs[i + 1])] = v
+    if lib().gen_segments_u32(seed, nseg, _p(sizes), _p(kinds), _p(offs), _p(keys)) != 0:
+        raise MemoryError("segment generator failed")
     return keys, offs, kinds
+
+
+POOL_KINDS = ("u32uniform", "u32zipf4096", "u64uniform", "u64zipf4096", "f32normal")
+
+
+def request_pool(kind, n=1 << 26, seed=10):
+    """Device-resident key pools the serving workload draws requests from:
+    u32/u64 uniform over the full range, u32/u64 with 4,096 distinct values
+    drawn with Zipf(1.0) ranks, f32 Normal(0, 1e3) with duplicates and
+    signed zeros (the wide-key recipe)."""
+    k = POOL_KINDS.index(kind)
+    if kind == "u32uniform":
+        return u32(seed + k, 0, n)
+    if kind == "u32zipf4096":
+        return zipf_keys(seed + k, n, 4096, 1.0, 32).astype(np.uint32)
+    if kind == "u64uniform":
+        return u64(seed + k, 0, n)
+    if kind == "u64zipf4096":
+        return zipf_keys(seed + k, n, 4096, 1.0, 64)
+    return _normal_recipe(seed + k, n, np.float32)
+
+
+def request_pool_kind(dtype_code, dist):
+    """Pool of a request with key type 0 u32 / 1 u64 / 2 f32 and distribution
+    0 uniform / 1 Zipf (f32 requests always use the Normal pool)."""
+    if dtype_code == 2:
+        return "f32normal"
+    return ("u32" if dtype_code == 0 else "u64") + ("uniform" if dist == 0 else "zipf4096")
 
 
 def request_trace(duration_s=60.0, rate=2000.0, seed=9, lo_exp=10, span_exp=14, max_requests=None):

@@ -156,3 +156,59 @@ void gen_apply_swaps(void* data, uint64_t n, uint32_t elem_size, uint64_t seed, 
     memcpy(d + q * elem_size, tmp, elem_size);
   }
 }
+
+static int cmp_u32(const void* a, const void* b) {
+  const uint32_t x = *(const uint32_t*)a, y = *(const uint32_t*)b;
+  return (x > y) - (x < y);
+}
+
+/* Concatenated u32 segments, one OpenMP task per segment.  Segment i has
+ * sizes[i] keys at offs[i] and kind kinds[i]:
+ *   0 uniform on [0, 255]   (high 32 bits & 255, stream 1000 + i)
+ *   1 uniform 32-bit        (stream 1000 + i)
+ *   2 64 distinct 32-bit values (seed * 7919 + i, stream 1) drawn with
+ *     Zipf(1.1) ranks (same seed, stream 2)
+ *   3 uniform 32-bit, ascending (libc qsort)
+ *   4 uniform 32-bit, descending
+ * Returns 0, or -1 when a Zipf table could not be allocated. */
+int gen_segments_u32(uint64_t seed, uint32_t nseg, const int64_t* sizes, const int64_t* kinds,
+                     const uint64_t* offs, uint32_t* out) {
+  int64_t i;
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : bad)
+  for (i = 0; i < (int64_t)nseg; i++) {
+    uint32_t* dst = out + offs[i];
+    const uint64_t n = (uint64_t)sizes[i];
+    const uint64_t st = 1000u + (uint64_t)i;
+    uint64_t j;
+    switch (kinds[i]) {
+      case 0:
+        gen_u32(seed, st, n, 255u, dst);
+        break;
+      case 1:
+        gen_u32(seed, st, n, 0xFFFFFFFFu, dst);
+        break;
+      case 2: {
+        uint64_t vals[64];
+        uint32_t* idx = (uint32_t*)malloc((n ? n : 1) * sizeof(uint32_t));
+        if (!idx) { bad |= 1; break; }
+        gen_distinct(seed * 7919u + (uint64_t)i, 1, 64, 32, vals);
+        if (gen_zipf_index(seed * 7919u + (uint64_t)i, 2, n, 1.1, 64, idx) != 0) bad |= 1;
+        for (j = 0; j < n; j++) dst[j] = (uint32_t)vals[idx[j]];
+        free(idx);
+        break;
+      }
+      default:
+        gen_u32(seed, st, n, 0xFFFFFFFFu, dst);
+        qsort(dst, n, sizeof(uint32_t), cmp_u32);
+        if (kinds[i] == 4)
+          for (j = 0; j < n / 2; j++) {
+            const uint32_t t = dst[j];
+            dst[j] = dst[n - 1 - j];
+            dst[n - 1 - j] = t;
+          }
+        break;
+    }
+  }
+  return bad ? -1 : 0;
+}

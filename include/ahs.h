@@ -274,7 +274,7 @@ typedef struct {
   uint32_t max_batch_requests;   /* 1..65535 */
   uint32_t slots;                /* batches in flight at once, 1..16 */
   uint32_t autotune;             /* run ahs_segmented_autotune for every key type at creation */
-  uint32_t reserved;
+  uint32_t lazy_dispatch;        /* 1: submit only queues; batches are formed and launched by poll */
   ahs_config cfg;                /* decision thresholds; use_model must be 0 */
 } ahs_server_config;
 typedef struct {

@@ -61,7 +61,7 @@ class Config(C.Structure):
 class ServerConfig(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_batch_keys", C.c_uint64),
                 ("max_batch_requests", C.c_uint32), ("slots", C.c_uint32), ("autotune", C.c_uint32),
-                ("reserved", C.c_uint32), ("cfg", Config)]
+                ("lazy_dispatch", C.c_uint32), ("cfg", Config)]
 
 
 class ServerResult(C.Structure):
@@ -492,7 +492,7 @@ class Server:
 
     def __init__(self, device: int = 0, hbm_budget_bytes: int | None = None, max_batch_keys: int | None = None,
                  max_batch_requests: int | None = None, slots: int | None = None, autotune: bool = False,
-                 cfg: Config | None = None):
+                 lazy_dispatch: bool = False, cfg: Config | None = None):
         c = ServerConfig()
         lib().ahs_server_config_init(C.byref(c))
         if hbm_budget_bytes is not None:
@@ -504,6 +504,7 @@ class Server:
         if slots is not None:
             c.slots = slots
         c.autotune = 1 if autotune else 0
+        c.lazy_dispatch = 1 if lazy_dispatch else 0
         if cfg is not None:
             c.cfg = cfg
         h = C.c_void_p()

@@ -33,15 +33,6 @@ __device__ __forceinline__ uint64_t ss_mix(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-// Segment holding tile `tile` (segments' first_tile ascend).
-__device__ __forceinline__ uint32_t ss_seg_of_tile(const SsSeg* __restrict__ segs, uint32_t nsegs, uint32_t tile) {
-  uint32_t lo = 0, hi = nsegs;  // largest s with first_tile <= tile
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (segs[mid].first_tile <= tile) lo = mid; else hi = mid;
-  }
-  return lo;
-}
 
 // ------------------------------------------------------------------ init
 // Level 0: one segment (or, for n <= SS_CAP, one block-sort item) covering

@@ -35,6 +35,16 @@ struct SsCounters {   // per level, written by the device, read by the host
   unsigned long long item_keys, seg_keys_next;
 };
 
+// Segment holding tile `tile` (segments' first_tile ascend).
+__device__ __forceinline__ uint32_t ss_seg_of_tile(const SsSeg* __restrict__ segs, uint32_t nsegs, uint32_t tile) {
+  uint32_t lo = 0, hi = nsegs;  // largest s with first_tile <= tile
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (segs[mid].first_tile <= tile) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 // Level sizes: the host passes them (host-driven levels), or a kernel reads
 // them from the previous level's counter record `in` (device-driven levels,
 // enqueue-only), clamped to the table capacities.

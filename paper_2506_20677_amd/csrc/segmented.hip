@@ -69,8 +69,13 @@ __global__ __launch_bounds__(256) void k_seg_classify(const uint64_t* __restrict
   }
 }
 
-__global__ void k_seg_gate(const SegCounters* __restrict__ ctr, SsCounters* __restrict__ rec0) {
-  if (threadIdx.x == 0) rec0->nsegs_next = ctr->bad ? 0u : ctr->nlarge;
+__global__ void k_seg_gate(const SegCounters* __restrict__ ctr, SsCounters* __restrict__ rec0,
+                           SsCounters* __restrict__ rec_chunks) {
+  if (threadIdx.x == 0) {
+    const uint32_t nl = ctr->bad ? 0u : ctr->nlarge;
+    rec0->nsegs_next = nl;
+    rec_chunks->nsegs_next = nl;
+  }
 }
 
 // ------------------------------------------------------------------ small segments, fused
@@ -140,70 +145,206 @@ __global__ __launch_bounds__(NT) void k_seg_small(SegArgs a, int cls) {
 }
 
 // ------------------------------------------------------------------ large segments: features after sorting
+// NaN bounds of each sorted large segment: NaNs occupy a prefix and a suffix
+// of the mapped order.  One thread per segment.
 template <int KK>
-__global__ __launch_bounds__(SS_THREADS) void k_seg_large(SegArgs a) {
+__global__ __launch_bounds__(64) void k_seg_bounds(SegArgs a) {
   using K = typename KeyTraits<KK>::K;
-  __shared__ BlockSortSmem<K, false> sm;
   const uint32_t count = a.ctr->bad ? 0u : a.ctr->nlarge;
-  for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
-    __syncthreads();
+  for (uint32_t i = blockIdx.x * 64 + threadIdx.x; i < count; i += gridDim.x * 64) {
     const SsSeg g = a.large[i];
-    const uint32_t s = a.large_ids[i];
-    const K* __restrict__ keys = (const K*)a.kout + g.start;
+    uint32_t lo = 0, hi = g.size;
+    if constexpr (KeyTraits<KK>::FLT) {
+      const K* __restrict__ keys = (const K*)a.kout + g.start;
+      uint32_t l = 0, h = g.size;  // first index with mapped >= map(-inf)
+      while (l < h) {
+        const uint32_t m = (l + h) >> 1;
+        if (fmap(keys[m]) < NanBounds<K>::lo) l = m + 1; else h = m;
+      }
+      lo = l;
+      h = g.size;  // first index with mapped > map(+inf)
+      while (l < h) {
+        const uint32_t m = (l + h) >> 1;
+        if (fmap(keys[m]) > NanBounds<K>::hi) h = m; else l = m + 1;
+      }
+      hi = l;
+    }
+    a.bounds[2 * i] = lo;
+    a.bounds[2 * i + 1] = hi;
+  }
+}
+
+// Exclusive max over the threads of a workgroup (-1 identity).
+template <int NT>
+__device__ __forceinline__ int block_excl_max(int v, int* smem) {
+  constexpr int NW = NT / WAVE;
+  const int w = threadIdx.x / WAVE, l = lane_id();
+  int inc = v;
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const int o = __shfl_up(inc, d, WAVE);
+    if (l >= d) inc = o > inc ? o : inc;
+  }
+  int ex = __shfl_up(inc, 1, WAVE);
+  if (l == 0) ex = -1;
+  if (l == WAVE - 1) smem[w] = inc;
+  __syncthreads();
+  int before = -1;
+  for (int i = 0; i < w; ++i) before = smem[i] > before ? smem[i] : before;
+  __syncthreads();
+  return ex > before ? ex : before;
+}
+
+// Per chunk of a sorted large segment without NaNs: the entropy terms
+// -(c/n) log2(c/n) of the runs of equal bins that END in the chunk.  A run
+// that began before the chunk gets its start from a 64-way galloping search
+// by one wave (bins ascend along the sorted segment).
+template <int KK>
+__global__ __launch_bounds__(SEG_CH_THREADS) void k_seg_chunk(SegArgs a) {
+  using K = typename KeyTraits<KK>::K;
+  constexpr int NT = SEG_CH_THREADS, CPT = SEG_CH / NT;
+  __shared__ K s_k[SEG_CH + 2];  // s_k[j + 1] = key at chunk position j; halo keys at both ends
+  __shared__ int s_max[NT / WAVE];
+  __shared__ double s_red[NT / WAVE];
+  __shared__ uint32_t s_carry;
+  const int t = threadIdx.x;
+  uint32_t nch = a.chunks->ntiles_next;
+  nch = nch < a.chunk_cap ? nch : a.chunk_cap;
+  const uint32_t nl = a.chunks->nsegs_next;
+  for (uint32_t c = blockIdx.x; c < nch; c += gridDim.x) {
+    __syncthreads();  // the previous chunk's LDS contents are consumed
+    const uint32_t li = ss_seg_of_tile(a.large, nl, c);
+    const SsSeg g = a.large[li];
     const uint32_t size = g.size;
-    auto mapped = [&](uint64_t j) {
+    if (a.bounds[2 * li] != 0 || a.bounds[2 * li + 1] != size) {  // holds NaNs: no features
+      if (t == 0) a.partial[c] = 0.0;
+      continue;
+    }
+    const K* __restrict__ keys = (const K*)a.kout + g.start;
+    auto mapped = [&](uint32_t j) {
       K x = keys[j];
       if constexpr (KeyTraits<KK>::FLT) x = fmap(x);
       return x;
     };
-    // NaNs occupy a prefix and a suffix of the sorted mapped order
-    uint32_t lo = 0, hi = size;
-    if constexpr (KeyTraits<KK>::FLT) {
-      uint32_t l = 0, h = size;  // first index with mapped >= lo bound
-      while (l < h) {
-        const uint32_t m = (l + h) >> 1;
-        if (mapped(m) < NanBounds<K>::lo) l = m + 1; else h = m;
+    const K kmin = mapped(0);
+    uint32_t shift, nbins;
+    shift_nbins((uint64_t)(mapped(size - 1) - kmin), shift, nbins);
+    auto binof = [&](K x) { return (uint64_t)((x - kmin) >> shift); };
+    const uint32_t c0 = (c - g.first_tile) * SEG_CH;
+    const uint32_t cnt = size - c0 < SEG_CH ? size - c0 : SEG_CH;
+    for (uint32_t j = t; j < cnt; j += NT) s_k[j + 1] = mapped(c0 + j);
+    if (t == 0) s_k[0] = c0 > 0 ? mapped(c0 - 1) : K(0);
+    if (t == 1) s_k[cnt + 1] = c0 + cnt < size ? mapped(c0 + cnt) : K(0);
+    __syncthreads();
+    const bool carry_needed = c0 > 0 && binof(s_k[0]) == binof(s_k[1]);
+    if (carry_needed && t < WAVE) {
+      // smallest position p <= c0 with bin(p) == bin(c0)
+      const uint64_t target = binof(s_k[1]);
+      int64_t R = c0;  // bin(R) == target
+      int64_t step = 1, L = 0;
+      for (;;) {
+        const int64_t pos = R - step * (int64_t)(lane_id() + 1);
+        const bool less = pos < L || binof(mapped((uint32_t)pos)) < target;
+        const uint64_t m = __ballot(less);
+        if (m == 0) {
+          R -= step * WAVE;
+          step *= WAVE;
+          continue;
+        }
+        const int l = __builtin_ctzll(m);
+        const int64_t same = R - step * l, below = R - step * (l + 1);
+        if (step == 1) {
+          R = same;
+          break;
+        }
+        L = below + 1 > L ? below + 1 : L;
+        R = same;
+        step = (step + WAVE - 1) / WAVE;
       }
-      lo = l;
-      l = lo;
-      h = size;  // first index with mapped > hi bound
-      while (l < h) {
-        const uint32_t m = (l + h) >> 1;
-        if (mapped(m) > NanBounds<K>::hi) h = m; else l = m + 1;
-      }
-      hi = l;
+      if (t == 0) s_carry = (uint32_t)R;
     }
+    __syncthreads();
+    const uint32_t carry = carry_needed ? s_carry : c0;
+    // run starts in my positions
+    const uint32_t j0 = (uint32_t)t * CPT;
+    int last = -1;
+    for (int q = 0; q < CPT; ++q) {
+      const uint32_t j = j0 + q;
+      if (j >= cnt) break;
+      const bool st = (c0 + j == 0) || binof(s_k[j]) != binof(s_k[j + 1]);
+      if (st) last = (int)j;
+    }
+    int cur = block_excl_max<NT>(last, s_max);
+    const double inv_n = 1.0 / (double)size;
+    double acc = 0.0;
+    for (int q = 0; q < CPT; ++q) {
+      const uint32_t j = j0 + q;
+      if (j >= cnt) break;
+      if ((c0 + j == 0) || binof(s_k[j]) != binof(s_k[j + 1])) cur = (int)j;
+      const bool end = (c0 + j + 1 == size) || binof(s_k[j + 2]) != binof(s_k[j + 1]);
+      if (end) {
+        const uint32_t start = cur >= 0 ? c0 + (uint32_t)cur : carry;
+        const double p = (double)(c0 + j + 1 - start) * inv_n;
+        acc -= p * log2(p);
+      }
+    }
+    acc = wave_sum(acc);
+    if (lane_id() == 0) s_red[t / WAVE] = acc;
+    __syncthreads();
+    if (t == 0) {
+      double sum = 0.0;
+      for (int i = 0; i < NT / WAVE; ++i) sum += s_red[i];
+      a.partial[c] = sum;
+    }
+  }
+}
+
+// One workgroup per large segment: features from its ends and its chunks'
+// entropy terms (summed in a fixed order), then the decision.
+template <int KK>
+__global__ __launch_bounds__(256) void k_seg_large_final(SegArgs a) {
+  using K = typename KeyTraits<KK>::K;
+  __shared__ double s_red[256 / WAVE];
+  const uint32_t count = a.ctr->bad ? 0u : a.ctr->nlarge;
+  const int t = threadIdx.x;
+  for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
+    const SsSeg g = a.large[i];
+    const uint32_t s = a.large_ids[i];
+    const uint32_t lo = a.bounds[2 * i], hi = a.bounds[2 * i + 1];
+    const uint32_t nchunk = (g.size + SEG_CH - 1) / SEG_CH;
+    double acc = 0.0;
+    for (uint32_t k = t; k < nchunk; k += 256) acc += a.partial[g.first_tile + k];
+    acc = wave_sum(acc);
+    __syncthreads();
+    if (lane_id() == 0) s_red[t / WAVE] = acc;
+    __syncthreads();
+    if (t != 0) continue;
+    double H = 0.0;
+    for (int w = 0; w < 256 / WAVE; ++w) H += s_red[w];
     DevFeatures f = {};
-    f.n = size;
-    f.nan_count = lo + (size - hi);
+    f.n = g.size;
+    f.nan_count = lo + (g.size - hi);
     uint8_t chosen;
     if (f.nan_count) {
       chosen = SEG_STATUS_NAN;
     } else {
-      const K mn = mapped(0), mx = mapped(size - 1);
+      const K* __restrict__ keys = (const K*)a.kout + g.start;
+      K mn = keys[0], mx = keys[g.size - 1];
+      if constexpr (KeyTraits<KK>::FLT) {
+        mn = fmap(mn);
+        mx = fmap(mx);
+      }
       f.min_key = mn;
       f.max_key = mx;
       f.span = (uint64_t)(mx - mn);
       shift_nbins(f.span, f.shift, f.nbins);
       f.exact = f.shift == 0;
-      double H = 0.0;
-      uint64_t carry = 0;
-      for (uint32_t c0 = 0; c0 < size; c0 += SS_CAP) {
-        const uint32_t cnt = size - c0 < (uint32_t)SS_CAP ? size - c0 : (uint32_t)SS_CAP;
-        for (uint32_t j = threadIdx.x; j < cnt; j += SS_THREADS) sm.keys[j] = mapped(c0 + j);
-        const K prev = c0 > 0 ? mapped(c0 - 1) : K(0);
-        const K next = c0 + cnt < size ? mapped(c0 + cnt) : K(0);
-        __syncthreads();
-        H += lds_run_entropy(sm, cnt, c0, prev, c0 > 0, next, c0 + cnt < size, mn, f.shift, size, carry);
-      }
       f.entropy_bits = H < 0.0 ? 0.0 : H;
       f.entropy_ratio = f.nbins > 1 ? f.entropy_bits / log2((double)f.nbins) : 0.0;
-      chosen = a.requested ? (uint8_t)a.requested : seg_fsm(size, f.span, f.nbins, f.entropy_bits, a.cfg);
+      chosen = a.requested ? (uint8_t)a.requested : seg_fsm(g.size, f.span, f.nbins, f.entropy_bits, a.cfg);
     }
-    if (threadIdx.x == 0) {
-      if (a.chosen) a.chosen[s] = chosen;
-      if (a.feats) a.feats[s] = f;
-    }
+    if (a.chosen) a.chosen[s] = chosen;
+    if (a.feats) a.feats[s] = f;
   }
 }
 
@@ -248,8 +389,8 @@ hipError_t launch_seg_classify(const uint64_t* offs, uint32_t nseg, uint64_t n_t
   return hipGetLastError();
 }
 
-hipError_t launch_seg_gate(const SegCounters* ctr, SsCounters* rec0, hipStream_t s) {
-  k_seg_gate<<<1, 64, 0, s>>>(ctr, rec0);
+hipError_t launch_seg_gate(const SegCounters* ctr, SsCounters* rec0, SsCounters* rec_chunks, hipStream_t s) {
+  k_seg_gate<<<1, 64, 0, s>>>(ctr, rec0, rec_chunks);
   return hipGetLastError();
 }
 
@@ -310,16 +451,44 @@ uint32_t seg_small_resident(int kk, int with_vals, int variant, uint32_t cu_coun
   return (uint32_t)per_cu * (cu_count ? cu_count : 1);
 }
 
-hipError_t launch_seg_large(int kk, const SegArgs& a, uint32_t nblocks, hipStream_t s) {
-  if (nblocks == 0) return hipSuccess;
+hipError_t launch_seg_large(int kk, const SegArgs& a, uint32_t bound_blocks, uint32_t chunk_blocks,
+                            uint32_t final_blocks, hipStream_t s) {
+  if (bound_blocks == 0 || chunk_blocks == 0 || final_blocks == 0) return hipSuccess;
   switch (kk) {
-    case KK_U32: k_seg_large<KK_U32><<<nblocks, SS_THREADS, 0, s>>>(a); break;
-    case KK_U64: k_seg_large<KK_U64><<<nblocks, SS_THREADS, 0, s>>>(a); break;
-    case KK_F32: k_seg_large<KK_F32><<<nblocks, SS_THREADS, 0, s>>>(a); break;
-    case KK_F64: k_seg_large<KK_F64><<<nblocks, SS_THREADS, 0, s>>>(a); break;
+    case KK_U32:
+      k_seg_bounds<KK_U32><<<bound_blocks, 64, 0, s>>>(a);
+      k_seg_chunk<KK_U32><<<chunk_blocks, SEG_CH_THREADS, 0, s>>>(a);
+      k_seg_large_final<KK_U32><<<final_blocks, 256, 0, s>>>(a);
+      break;
+    case KK_U64:
+      k_seg_bounds<KK_U64><<<bound_blocks, 64, 0, s>>>(a);
+      k_seg_chunk<KK_U64><<<chunk_blocks, SEG_CH_THREADS, 0, s>>>(a);
+      k_seg_large_final<KK_U64><<<final_blocks, 256, 0, s>>>(a);
+      break;
+    case KK_F32:
+      k_seg_bounds<KK_F32><<<bound_blocks, 64, 0, s>>>(a);
+      k_seg_chunk<KK_F32><<<chunk_blocks, SEG_CH_THREADS, 0, s>>>(a);
+      k_seg_large_final<KK_F32><<<final_blocks, 256, 0, s>>>(a);
+      break;
+    case KK_F64:
+      k_seg_bounds<KK_F64><<<bound_blocks, 64, 0, s>>>(a);
+      k_seg_chunk<KK_F64><<<chunk_blocks, SEG_CH_THREADS, 0, s>>>(a);
+      k_seg_large_final<KK_F64><<<final_blocks, 256, 0, s>>>(a);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+uint32_t seg_chunk_resident(int kk, uint32_t cu_count) {
+  const void* fn = kk == KK_U32 ? reinterpret_cast<const void*>(&k_seg_chunk<KK_U32>)
+                 : kk == KK_U64 ? reinterpret_cast<const void*>(&k_seg_chunk<KK_U64>)
+                 : kk == KK_F32 ? reinterpret_cast<const void*>(&k_seg_chunk<KK_F32>)
+                                : reinterpret_cast<const void*>(&k_seg_chunk<KK_F64>);
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, SEG_CH_THREADS, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  return (uint32_t)per_cu * (cu_count ? cu_count : 1);
 }
 
 hipError_t launch_seg_status(const SegCounters* ctr, const SsCounters* levels, int nlevels, uint32_t* status,

@@ -34,6 +34,11 @@ struct SegCounters {
   unsigned long long large_keys, small_keys;
 };
 
+// Features of large segments are taken from their sorted output in chunks
+// of SEG_CH keys spread over the whole grid.
+constexpr uint32_t SEG_CH = 8192;
+constexpr int SEG_CH_THREADS = 256;
+
 struct SegArgs {
   const void* kin;
   void* kout;
@@ -45,6 +50,10 @@ struct SegArgs {
   const SsSeg* large;       // [nlarge] large segments (sample-sort level 0)
   const uint32_t* large_ids;
   const SegCounters* ctr;
+  const SsCounters* chunks;  // nsegs_next = large segments, ntiles_next = their chunks (first chunk in large[].first_tile)
+  uint32_t chunk_cap;
+  uint32_t* bounds;          // [2 * nlarge]: first and end index of the non-NaN keys of each sorted large segment
+  double* partial;           // [chunk_cap] entropy terms of the runs that end in each chunk
   SegConfig cfg;
   uint32_t requested;       // 0 = AUTO, else the forced strategy reported for every segment
   uint8_t* chosen;          // [nseg] or null
@@ -55,14 +64,18 @@ struct SegArgs {
 // to a copy the feature kernel reads after the levels (large).
 hipError_t launch_seg_classify(const uint64_t* offs, uint32_t nseg, uint64_t n_total, uint32_t* queues, uint32_t qcap,
                                SsSeg* large_ss, SsSeg* large, uint32_t* large_ids, SegCounters* ctr, hipStream_t s);
-// Level-0 record of the sample sort: the large-segment count, or zero when
-// the offsets were invalid.
-hipError_t launch_seg_gate(const SegCounters* ctr, SsCounters* rec0, hipStream_t s);
+// Level-0 record of the sample sort and the chunk record: the large-segment
+// count, or zero when the offsets were invalid.
+hipError_t launch_seg_gate(const SegCounters* ctr, SsCounters* rec0, SsCounters* rec_chunks, hipStream_t s);
 // Class `cls` through variant `variant` (capacity SEG_CLASS_CAP[variant] >=
 // SEG_CLASS_CAP[cls]); the kernel reads the queue length from ctr.
 hipError_t launch_seg_small(int kk, int with_vals, const SegArgs& a, int cls, int variant, uint32_t nblocks,
                             hipStream_t s);
-hipError_t launch_seg_large(int kk, const SegArgs& a, uint32_t nblocks, hipStream_t s);
+// Features of the large segments after sorting: NaN bounds, per-chunk run
+// entropy, then one workgroup per segment folds its chunks in order.
+hipError_t launch_seg_large(int kk, const SegArgs& a, uint32_t bound_blocks, uint32_t chunk_blocks,
+                            uint32_t final_blocks, hipStream_t s);
+uint32_t seg_chunk_resident(int kk, uint32_t cu_count);
 hipError_t launch_seg_status(const SegCounters* ctr, const SsCounters* levels, int nlevels, uint32_t* status,
                              hipStream_t s);
 uint32_t seg_small_resident(int kk, int with_vals, int variant, uint32_t cu_count);

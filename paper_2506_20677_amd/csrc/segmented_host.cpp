@@ -14,10 +14,11 @@ namespace ahs {
 namespace {
 
 struct SegLayout {
-  size_t queues = 0, large = 0, large_ids = 0, segctr = 0, status = 0, total = 0;
+  size_t queues = 0, large = 0, large_ids = 0, bounds = 0, partial = 0, segctr = 0, status = 0, total = 0;
+  uint64_t chunk_cap = 0;
 };
 
-SegLayout seg_layout(size_t base, uint32_t nseg) {
+SegLayout seg_layout(size_t base, uint64_t n_total, uint32_t nseg) {
   SegLayout L;
   size_t o = base;
   auto take = [&](size_t bytes) {
@@ -28,7 +29,10 @@ SegLayout seg_layout(size_t base, uint32_t nseg) {
   L.queues = take(4 * (size_t)SEG_NCLASS * ((size_t)nseg + 1));
   L.large = take(sizeof(SsSeg) * ((size_t)nseg + 1));
   L.large_ids = take(4 * ((size_t)nseg + 1));
-  L.segctr = take(sizeof(SegCounters) + sizeof(SsCounters));
+  L.bounds = take(8 * ((size_t)nseg + 1));
+  L.chunk_cap = n_total / SEG_CH + (uint64_t)nseg + 1;
+  L.partial = take(sizeof(double) * L.chunk_cap);
+  L.segctr = take(sizeof(SegCounters) + 2 * sizeof(SsCounters));
   L.status = take(256);
   L.total = o;
   return L;
@@ -44,7 +48,8 @@ struct SegCall {
   SegLayout G;
   SegArgs a;
   SegCounters* sctr;
-  SsCounters* rec0;
+  SsCounters* rec0;        // level 0 of the sample sort
+  SsCounters* rec_chunks;  // chunks of the large segments
   uint32_t nseg;
   int pay;
 };
@@ -84,13 +89,14 @@ ahs_status seg_setup(SegCall& C, ahs_context* ctx, const void* d_keys_in, void* 
   j.s = (hipStream_t)stream;
   j.L = plan_layout(n_total, kb, d_vals_in ? 1 : 0, true);
   memset(&j.f, 0, sizeof j.f);
-  C.G = seg_layout(j.L.total, nseg);
+  C.G = seg_layout(j.L.total, n_total, nseg);
   if (ws_bytes < C.G.total) return ctx->fail(AHS_E_WORKSPACE, "workspace %zu < %zu", ws_bytes, C.G.total);
   AHS_HIP(j, hipSetDevice(ctx->device), "set device");
   C.S = ss_layout(n_total, kb);
   C.T = ss_tables(j, C.S);
   C.sctr = at<SegCounters>(d_ws, C.G.segctr);
   C.rec0 = reinterpret_cast<SsCounters*>(C.sctr + 1);
+  C.rec_chunks = C.rec0 + 1;
   C.nseg = nseg;
   C.pay = d_vals_in != nullptr;
   SegArgs& a = C.a;
@@ -104,6 +110,10 @@ ahs_status seg_setup(SegCall& C, ahs_context* ctx, const void* d_keys_in, void* 
   a.large = at<SsSeg>(d_ws, C.G.large);
   a.large_ids = at<uint32_t>(d_ws, C.G.large_ids);
   a.ctr = C.sctr;
+  a.chunks = C.rec_chunks;
+  a.chunk_cap = (uint32_t)std::min<uint64_t>(C.G.chunk_cap, 0xFFFFFFFFull);
+  a.bounds = at<uint32_t>(d_ws, C.G.bounds);
+  a.partial = at<double>(d_ws, C.G.partial);
   a.cfg.n_small = c.n_small;
   a.cfg.k_count = c.k_count;
   a.cfg.k_radix = c.k_radix;
@@ -119,8 +129,8 @@ ahs_status seg_setup(SegCall& C, ahs_context* ctx, const void* d_keys_in, void* 
 ahs_status seg_classify(SegCall& C, uint64_t n_total) {
   SortJob& j = C.j;
   AHS_HIP(j,
-          launch_fill_u32(reinterpret_cast<uint32_t*>(C.sctr), (sizeof(SegCounters) + sizeof(SsCounters)) / 4, 0u,
-                          j.s),
+          launch_fill_u32(reinterpret_cast<uint32_t*>(C.sctr), (sizeof(SegCounters) + 2 * sizeof(SsCounters)) / 4,
+                          0u, j.s),
           "fill");
   {
     ProfScope p(j.ctx, "seg_classify", j.s);
@@ -129,9 +139,10 @@ ahs_status seg_classify(SegCall& C, uint64_t n_total) {
                                 const_cast<SsSeg*>(C.a.large), const_cast<uint32_t*>(C.a.large_ids), C.sctr, j.s),
             "classify");
   }
-  AHS_HIP(j, launch_seg_gate(C.sctr, C.rec0, j.s), "gate");
+  AHS_HIP(j, launch_seg_gate(C.sctr, C.rec0, C.rec_chunks, j.s), "gate");
   AHS_HIP(j, launch_ss_tiles(C.T.segs[0], C.rec0, (uint32_t)ss_tile(j.key_bytes), (uint32_t)C.S.seg_cap, j.s),
           "tiles");
+  AHS_HIP(j, launch_ss_tiles(const_cast<SsSeg*>(C.a.large), C.rec_chunks, SEG_CH, C.nseg + 1, j.s), "chunks");
   return AHS_OK;
 }
 
@@ -163,7 +174,11 @@ ahs_status seg_enqueue_async(SegCall& C, uint64_t n_total, uint64_t max_seg_hint
     AHS_TRY(ss_levels_device(j, C.S, C.T, C.rec0, levels, max_seg));
     ProfScope p(j.ctx, "seg_large_features", j.s);
     const uint32_t cu = j.ctx->cu_count ? j.ctx->cu_count : 256;
-    AHS_HIP(j, launch_seg_large(j.kk, C.a, std::min<uint32_t>(C.nseg, 2 * cu), j.s), "large-segment features");
+    const uint32_t lmax = (uint32_t)std::min<uint64_t>(C.nseg, n_total / (SS_CAP + 1) + 1);
+    AHS_HIP(j,
+            launch_seg_large(j.kk, C.a, (lmax + 63) / 64, seg_chunk_resident(j.kk, cu),
+                             std::min<uint32_t>(lmax, 2 * cu), j.s),
+            "large-segment features");
   }
   AHS_HIP(j, launch_seg_status(C.sctr, C.T.ctr, levels, d_status, j.s), "status");
   return AHS_OK;
@@ -177,7 +192,7 @@ using namespace ahs;
 extern "C" size_t ahs_segmented_workspace_bytes(uint64_t n_total, uint32_t nseg, ahs_dtype dtype, int with_payload) {
   if ((int)dtype < 0 || (int)dtype > 3) return 0;
   const Layout L = plan_layout(n_total, key_bytes_of(dtype), with_payload ? 1 : 0, true);
-  return seg_layout(L.total, nseg).total;
+  return seg_layout(L.total, n_total, nseg).total;
 }
 
 extern "C" ahs_status ahs_sort_segmented(ahs_context* ctx, const void* d_keys_in, void* d_keys_out,
@@ -205,7 +220,12 @@ extern "C" ahs_status ahs_sort_segmented(ahs_context* ctx, const void* d_keys_in
   if (sc.nlarge) {
     AHS_TRY(ss_levels_host(j, C.S, C.T, sc.nlarge, rc.ntiles_next, sc.large_keys, sc.max_large));
     ProfScope p(ctx, "seg_large_features", j.s, (double)j.key_bytes * (double)sc.large_keys);
-    AHS_HIP(j, launch_seg_large(j.kk, C.a, sc.nlarge, j.s), "large-segment features");
+    const uint64_t chunks = sc.large_keys / SEG_CH + sc.nlarge;
+    const uint32_t res = seg_chunk_resident(j.kk, ctx->cu_count);
+    AHS_HIP(j,
+            launch_seg_large(j.kk, C.a, (sc.nlarge + 63) / 64, (uint32_t)std::min<uint64_t>(chunks, res), sc.nlarge,
+                             j.s),
+            "large-segment features");
   }
   return AHS_OK;
 }

@@ -318,7 +318,7 @@ extern "C" ahs_status ahs_server_submit(ahs_server* S, ahs_dtype dtype, uint64_t
     r.ready = e;
   }
   *out_id = id;
-  return progress(S);
+  return S->cfg.lazy_dispatch ? AHS_OK : progress(S);
 }
 
 extern "C" ahs_status ahs_server_poll(ahs_server* S, ahs_server_result* out, uint32_t max, uint32_t* count,

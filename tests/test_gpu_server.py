@@ -105,7 +105,8 @@ def run_mix(server, reqs):
 
 def test_server_mix_matches_oracle_and_batches():
     reqs = make_requests(60, seed=61)
-    s = ahs.Server(hbm_budget_bytes=2 << 30, slots=3)
+    # lazy dispatch: all 60 requests are pending when the first poll forms batches
+    s = ahs.Server(hbm_budget_bytes=2 << 30, slots=3, lazy_dispatch=True)
     say("server mix of 60 requests")
     run_mix(s, reqs)
     st = s.stats()
