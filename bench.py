@@ -328,12 +328,18 @@ def main():
     ctx = ahs.default_context(0)
     ws_bytes = ahs.ahs_workspace_bytes(n, ahs.U32, False, ahs.AUTO)
     ctx.workspace(ws_bytes)
+    # AUTO = the FSM plus the gradient-boosted selector trained on MI355X
+    # measurements (the paper's two decision mechanisms)
+    model = ahs.default_model()
+    ctx.set_model(model)
+    cfg_auto = ahs.ahs_config_init(ahs.PRESET_GPU, use_model=1)
+    cfg_fsm = ahs.ahs_config_init(ahs.PRESET_GPU)
     torch.cuda.synchronize()
 
     def step():
         chosen = {}
         for c in cases:
-            _, _, ch, _ = ahs.ahs_sort(dkeys[c], strategy=ahs.AUTO, out=out, ctx=ctx)
+            _, _, ch, _ = ahs.ahs_sort(dkeys[c], strategy=ahs.AUTO, cfg=cfg_auto, out=out, ctx=ctx)
             chosen[c] = ahs.STRATEGY_NAMES[ch]
         return chosen
 
@@ -387,8 +393,9 @@ def main():
         for c in cases:
             row = {"case": c, "auto_choice": chosen[c]}
             ref = None
-            for sname, s in (("auto", ahs.AUTO), ("counting", ahs.COUNTING), ("radix", ahs.RADIX),
-                             ("quick", ahs.QUICK)):
+            for sname, s, cfg in (("auto", ahs.AUTO, cfg_auto), ("auto_fsm", ahs.AUTO, cfg_fsm),
+                                  ("counting", ahs.COUNTING, cfg_fsm), ("radix", ahs.RADIX, cfg_fsm),
+                                  ("quick", ahs.QUICK, cfg_fsm)):
                 times = []
                 path_bytes = None
                 try:
@@ -397,7 +404,7 @@ def main():
                         ahs.ahs_profile_reset(ctx)
                         torch.cuda.synchronize()
                         a = time.perf_counter()
-                        _, _, ch, _ = ahs.ahs_sort(dkeys[c], strategy=s, out=out, ctx=ctx)
+                        _, _, ch, _ = ahs.ahs_sort(dkeys[c], strategy=s, cfg=cfg, out=out, ctx=ctx)
                         torch.cuda.synchronize()
                         times.append(time.perf_counter() - a)
                         p = ahs.ahs_profile_dump(ctx)
@@ -419,6 +426,7 @@ def main():
                     agree = bool(torch.equal(ref, o))
                 med = statistics.median(times)
                 row[sname] = {"ms": round(med * 1e3, 4), "Gkeys_s": round(n / med / 1e9, 2),
+                              "chosen": ahs.STRATEGY_NAMES[ch],
                               "path_GB": round(path_bytes / 1e9, 3),
                               "hbm_frac_path": round(path_bytes / med / 1e9 / HBM_PEAK_GBS, 4),
                               "agrees": agree, "kernels": {k: [v[0], round(v[1], 4)] for k, v in p.items()}}
@@ -426,6 +434,8 @@ def main():
                        default=None)
             if best and "ms" in row.get("auto", {}):
                 row["auto_over_best"] = round(row["auto"]["ms"] / best, 4)
+            if best and "ms" in row.get("auto_fsm", {}):
+                row["auto_fsm_over_best"] = round(row["auto_fsm"]["ms"] / best, 4)
             per_case.append(row)
             log(f"[bench] case {c}: " + json.dumps(row))
             del ref
@@ -437,17 +447,20 @@ def main():
 
         m = min(n, 1 << args.cpu_sample_log2)
         tot_t, tot_k = 0.0, 0
+        omodel = oracle.Model(ahs.SELECTOR_MODEL)
+        ocfg = oracle.config(0, use_model=1)
         for c in cases:
             sample = np.ascontiguousarray(host[c][:m])
             a = time.perf_counter()
-            st, _, _, _, _ = oracle.sort(sample, None, oracle.AUTO)
+            st, _, _, _, _ = oracle.sort(sample, None, oracle.AUTO, ocfg, omodel)
             tot_t += time.perf_counter() - a
             tot_k += m
             if st != 0:
                 log(f"[bench] oracle status {st} on {c}")
         cpu = {"value": round(tot_k / tot_t / 1e9, 6), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
-               "sample": f"first 2^{int(np.log2(m))} keys of each of the {len(cases)} arrays, AHS AUTO, "
-                         f"single-threaded C oracle, {tot_t:.1f} s total", **host_info()}
+               "sample": f"first 2^{int(np.log2(m))} keys of each of the {len(cases)} arrays, AHS AUTO "
+                         f"(FSM + the same selector model), single-threaded C oracle, {tot_t:.1f} s total",
+               **host_info()}
         log(f"[bench] cpu baseline {cpu}")
 
     # ------------------------------------------------------------ batched and serving sections
@@ -461,7 +474,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"strategy sweep: {len(cases)} arrays x 2^{args.log2n} uint32 ({', '.join(cases)}), "
-                               "AHS AUTO per array", "n_per_array": n, "arrays": cases, "auto_choices": chosen},
+                               "AHS AUTO per array (FSM + selector trained on MI355X measurements)",
+                   "n_per_array": n, "arrays": cases, "auto_choices": chosen},
         "roofline": roofline, "cpu_baseline": cpu, "step_kernels": step_kernels, "per_case": per_case,
         "batched": batched, "serving": serving,
     }

@@ -180,6 +180,14 @@ class Model:
             self.handle = None
 
 
+SELECTOR_MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "models", "mi355x_selector.gbt")
+
+
+def default_model() -> "Model":
+    """The selector trained on MI355X measurements (models/mi355x_selector.gbt)."""
+    return ahs_model_load(SELECTOR_MODEL)
+
+
 def ahs_model_load(path: str) -> Model:
     return Model(path)
 

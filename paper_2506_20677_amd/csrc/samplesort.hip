@@ -255,7 +255,7 @@ __global__ __launch_bounds__(SS_TILES_THREADS) void k_ss_tiles(SsSeg* __restrict
 // in order from an atomic counter until none is left (one tile each when
 // the grid has one workgroup per tile); a workgroup only ever waits on
 // tiles taken earlier by running workgroups, so any grid size is safe.
-template <int KK, bool PAY, int IPT, typename ST>
+template <int KK, bool PAY, int IPT, typename ST, bool PERSIST>
 __global__ __launch_bounds__(SS_THREADS) void k_ss_scatter(SsScatterArgs a) {
   using K = typename KeyTraits<KK>::K;
   constexpr int TILE = SS_THREADS * IPT;
@@ -275,7 +275,8 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_scatter(SsScatterArgs a) {
 
   const int t = threadIdx.x, w = t / WAVE, lane = lane_id();
   const uint32_t ntiles = a.lv.tiles_n(), nsegs = a.lv.segs_n();
-  for (;;) {
+  for (int iter = 0;; ++iter) {
+    if (!PERSIST && iter > 0) break;  // one tile per workgroup: no loop to keep registers live across
     __syncthreads();  // the previous tile's LDS contents have been consumed
     for (int i = t; i < NW * SS_NB; i += SS_THREADS) {
       (&s_slot[0][0])[i].mask = 0ull;
@@ -357,46 +358,55 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_scatter(SsScatterArgs a) {
 }
 
 // ------------------------------------------------------------------ block sort
-// Workgroups stride over the items.  COPY items move (and unmap) keys.
-// SORT items (at most SS_CAP keys) are loaded into LDS and sorted by
-// lds_sort_loaded.
+// COPY items move (and unmap) keys.  SORT items (at most SS_CAP keys) are
+// loaded into LDS and sorted by lds_sort_loaded.
 template <int KK, bool PAY>
-__global__ __launch_bounds__(SS_THREADS) void k_ss_block(SsBlockArgs a) {
+__device__ __forceinline__ void ss_block_item(const SsBlockArgs& a, BlockSortSmem<typename KeyTraits<KK>::K, PAY>& sm,
+                                              uint32_t item) {
+  using K = typename KeyTraits<KK>::K;
+  const int t = threadIdx.x;
+  K* __restrict__ dst = (K*)a.kout;
+  const SsItem it = a.items[item];
+  const uint32_t buf = (it.flags >> 8) & 0xFFu;
+  const K* __restrict__ src = (const K*)(buf == SS_BUF_IN ? a.kin : (buf == SS_BUF_OUT ? a.kout : a.ktmp));
+  const uint32_t* __restrict__ vsrc = buf == SS_BUF_IN ? a.vin : (buf == SS_BUF_OUT ? a.vout : a.vtmp);
+  const bool raw = buf == SS_BUF_IN;
+  const uint64_t base = it.start;
+  const uint32_t size = it.size;
+  if (it.flags & SS_ITEM_COPY) {
+    for (uint32_t j = t; j < size; j += SS_THREADS) {
+      K x = src[base + j];
+      if constexpr (KeyTraits<KK>::FLT) x = raw ? x : funmap(x);
+      dst[base + j] = x;
+      if constexpr (PAY) a.vout[base + j] = vsrc[base + j];
+    }
+    return;
+  }
+  lds_load_mapped<KK, PAY>(sm, src + base, PAY ? vsrc + base : nullptr, size, raw);
+  K mn, mx;
+  lds_sort_loaded(sm, size, mn, mx);
+  for (uint32_t j = t; j < size; j += SS_THREADS) {
+    K x = sm.keys[j];
+    if constexpr (KeyTraits<KK>::FLT) x = funmap(x);
+    dst[base + j] = x;
+    if constexpr (PAY) a.vout[base + j] = sm.vals[j];
+  }
+}
+
+// One item per workgroup (host-driven levels), or workgroups striding over
+// the items whose count the device holds (device-driven levels).
+template <int KK, bool PAY, bool PERSIST>
+__global__ __launch_bounds__(SS_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_ss_block(SsBlockArgs a) {
   using K = typename KeyTraits<KK>::K;
   __shared__ BlockSortSmem<K, PAY> sm;
-  const int t = threadIdx.x;
-  uint32_t nitems = a.nitems;
-  if (a.lvl) {
-    nitems = a.lvl->nitems;
+  if constexpr (!PERSIST) {
+    if (blockIdx.x < a.nitems) ss_block_item<KK, PAY>(a, sm, blockIdx.x);
+  } else {
+    uint32_t nitems = a.lvl ? a.lvl->nitems : a.nitems;
     nitems = nitems < a.item_cap ? nitems : a.item_cap;
-  }
-  K* __restrict__ dst = (K*)a.kout;
-  for (uint32_t item = blockIdx.x; item < nitems; item += gridDim.x) {
-    __syncthreads();  // the previous item's LDS contents have been stored
-    const SsItem it = a.items[item];
-    const uint32_t buf = (it.flags >> 8) & 0xFFu;
-    const K* __restrict__ src = (const K*)(buf == SS_BUF_IN ? a.kin : (buf == SS_BUF_OUT ? a.kout : a.ktmp));
-    const uint32_t* __restrict__ vsrc = buf == SS_BUF_IN ? a.vin : (buf == SS_BUF_OUT ? a.vout : a.vtmp);
-    const bool raw = buf == SS_BUF_IN;
-    const uint64_t base = it.start;
-    const uint32_t size = it.size;
-    if (it.flags & SS_ITEM_COPY) {
-      for (uint32_t j = t; j < size; j += SS_THREADS) {
-        K x = src[base + j];
-        if constexpr (KeyTraits<KK>::FLT) x = raw ? x : funmap(x);
-        dst[base + j] = x;
-        if constexpr (PAY) a.vout[base + j] = vsrc[base + j];
-      }
-      continue;
-    }
-    lds_load_mapped<KK, PAY>(sm, src + base, PAY ? vsrc + base : nullptr, size, raw);
-    K mn, mx;
-    lds_sort_loaded(sm, size, mn, mx);
-    for (uint32_t j = t; j < size; j += SS_THREADS) {
-      K x = sm.keys[j];
-      if constexpr (KeyTraits<KK>::FLT) x = funmap(x);
-      dst[base + j] = x;
-      if constexpr (PAY) a.vout[base + j] = sm.vals[j];
+    for (uint32_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+      __syncthreads();  // the previous item's LDS contents have been stored
+      ss_block_item<KK, PAY>(a, sm, item);
     }
   }
 }
@@ -461,50 +471,60 @@ hipError_t launch_ss_tiles(SsSeg* segs, SsCounters* ctr, uint32_t tile_keys, uin
 template <int KK, bool PAY, typename ST>
 static const void* scatter_fn() {
   constexpr int IPT = sizeof(typename KeyTraits<KK>::K) == 4 ? 16 : 8;
-  return reinterpret_cast<const void*>(&k_ss_scatter<KK, PAY, IPT, ST>);
+  return reinterpret_cast<const void*>(&k_ss_scatter<KK, PAY, IPT, ST, true>);
 }
 
-template <int KK, bool PAY>
+template <int KK, bool PAY, bool PERSIST>
 static hipError_t scatter_kk(const SsScatterArgs& a, uint32_t grid, hipStream_t s) {
   constexpr int IPT = sizeof(typename KeyTraits<KK>::K) == 4 ? 16 : 8;
   if (a.max_seg < STATUS32_MAX_N)
-    k_ss_scatter<KK, PAY, IPT, uint32_t><<<grid, SS_THREADS, 0, s>>>(a);
+    k_ss_scatter<KK, PAY, IPT, uint32_t, PERSIST><<<grid, SS_THREADS, 0, s>>>(a);
   else
-    k_ss_scatter<KK, PAY, IPT, uint64_t><<<grid, SS_THREADS, 0, s>>>(a);
+    k_ss_scatter<KK, PAY, IPT, uint64_t, PERSIST><<<grid, SS_THREADS, 0, s>>>(a);
   return hipGetLastError();
+}
+
+template <bool PERSIST>
+static hipError_t scatter_any(int kk, int with_vals, const SsScatterArgs& a, uint32_t grid, hipStream_t s) {
+  switch (kk * 2 + (with_vals ? 1 : 0)) {
+    case KK_U32 * 2: return scatter_kk<KK_U32, false, PERSIST>(a, grid, s);
+    case KK_U32 * 2 + 1: return scatter_kk<KK_U32, true, PERSIST>(a, grid, s);
+    case KK_U64 * 2: return scatter_kk<KK_U64, false, PERSIST>(a, grid, s);
+    case KK_U64 * 2 + 1: return scatter_kk<KK_U64, true, PERSIST>(a, grid, s);
+    case KK_F32 * 2: return scatter_kk<KK_F32, false, PERSIST>(a, grid, s);
+    case KK_F32 * 2 + 1: return scatter_kk<KK_F32, true, PERSIST>(a, grid, s);
+    case KK_F64 * 2: return scatter_kk<KK_F64, false, PERSIST>(a, grid, s);
+    case KK_F64 * 2 + 1: return scatter_kk<KK_F64, true, PERSIST>(a, grid, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_ss_scatter(int kk, int with_vals, const SsScatterArgs& a, uint32_t nblocks, hipStream_t s) {
-  const uint32_t grid = nblocks ? nblocks : a.lv.ntiles;
-  if (grid == 0) return hipSuccess;
-  switch (kk * 2 + (with_vals ? 1 : 0)) {
-    case KK_U32 * 2: return scatter_kk<KK_U32, false>(a, grid, s);
-    case KK_U32 * 2 + 1: return scatter_kk<KK_U32, true>(a, grid, s);
-    case KK_U64 * 2: return scatter_kk<KK_U64, false>(a, grid, s);
-    case KK_U64 * 2 + 1: return scatter_kk<KK_U64, true>(a, grid, s);
-    case KK_F32 * 2: return scatter_kk<KK_F32, false>(a, grid, s);
-    case KK_F32 * 2 + 1: return scatter_kk<KK_F32, true>(a, grid, s);
-    case KK_F64 * 2: return scatter_kk<KK_F64, false>(a, grid, s);
-    case KK_F64 * 2 + 1: return scatter_kk<KK_F64, true>(a, grid, s);
-    default: return hipErrorInvalidValue;
-  }
+  if (nblocks) return scatter_any<true>(kk, with_vals, a, nblocks, s);
+  if (a.lv.ntiles == 0) return hipSuccess;
+  return scatter_any<false>(kk, with_vals, a, a.lv.ntiles, s);
 }
 
-hipError_t launch_ss_block(int kk, int with_vals, const SsBlockArgs& a, uint32_t nblocks, hipStream_t s) {
-  const uint32_t grid = nblocks ? nblocks : a.nitems;
-  if (grid == 0) return hipSuccess;
+template <bool PERSIST>
+static hipError_t block_any(int kk, int with_vals, const SsBlockArgs& a, uint32_t grid, hipStream_t s) {
   switch (kk * 2 + (with_vals ? 1 : 0)) {
-    case KK_U32 * 2: k_ss_block<KK_U32, false><<<grid, SS_THREADS, 0, s>>>(a); break;
-    case KK_U32 * 2 + 1: k_ss_block<KK_U32, true><<<grid, SS_THREADS, 0, s>>>(a); break;
-    case KK_U64 * 2: k_ss_block<KK_U64, false><<<grid, SS_THREADS, 0, s>>>(a); break;
-    case KK_U64 * 2 + 1: k_ss_block<KK_U64, true><<<grid, SS_THREADS, 0, s>>>(a); break;
-    case KK_F32 * 2: k_ss_block<KK_F32, false><<<grid, SS_THREADS, 0, s>>>(a); break;
-    case KK_F32 * 2 + 1: k_ss_block<KK_F32, true><<<grid, SS_THREADS, 0, s>>>(a); break;
-    case KK_F64 * 2: k_ss_block<KK_F64, false><<<grid, SS_THREADS, 0, s>>>(a); break;
-    case KK_F64 * 2 + 1: k_ss_block<KK_F64, true><<<grid, SS_THREADS, 0, s>>>(a); break;
+    case KK_U32 * 2: k_ss_block<KK_U32, false, PERSIST><<<grid, SS_THREADS, 0, s>>>(a); break;
+    case KK_U32 * 2 + 1: k_ss_block<KK_U32, true, PERSIST><<<grid, SS_THREADS, 0, s>>>(a); break;
+    case KK_U64 * 2: k_ss_block<KK_U64, false, PERSIST><<<grid, SS_THREADS, 0, s>>>(a); break;
+    case KK_U64 * 2 + 1: k_ss_block<KK_U64, true, PERSIST><<<grid, SS_THREADS, 0, s>>>(a); break;
+    case KK_F32 * 2: k_ss_block<KK_F32, false, PERSIST><<<grid, SS_THREADS, 0, s>>>(a); break;
+    case KK_F32 * 2 + 1: k_ss_block<KK_F32, true, PERSIST><<<grid, SS_THREADS, 0, s>>>(a); break;
+    case KK_F64 * 2: k_ss_block<KK_F64, false, PERSIST><<<grid, SS_THREADS, 0, s>>>(a); break;
+    case KK_F64 * 2 + 1: k_ss_block<KK_F64, true, PERSIST><<<grid, SS_THREADS, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_ss_block(int kk, int with_vals, const SsBlockArgs& a, uint32_t nblocks, hipStream_t s) {
+  if (nblocks) return block_any<true>(kk, with_vals, a, nblocks, s);
+  if (a.nitems == 0) return hipSuccess;
+  return block_any<false>(kk, with_vals, a, a.nitems, s);
 }
 
 static uint32_t resident(const void* fn, int threads, uint32_t cu_count) {
@@ -532,14 +552,14 @@ uint32_t ss_scatter_resident(int kk, int with_vals, uint64_t max_seg, uint32_t c
 uint32_t ss_block_resident(int kk, int with_vals, uint32_t cu_count) {
   const void* fn = nullptr;
   switch (kk * 2 + (with_vals ? 1 : 0)) {
-    case KK_U32 * 2: fn = reinterpret_cast<const void*>(&k_ss_block<KK_U32, false>); break;
-    case KK_U32 * 2 + 1: fn = reinterpret_cast<const void*>(&k_ss_block<KK_U32, true>); break;
-    case KK_U64 * 2: fn = reinterpret_cast<const void*>(&k_ss_block<KK_U64, false>); break;
-    case KK_U64 * 2 + 1: fn = reinterpret_cast<const void*>(&k_ss_block<KK_U64, true>); break;
-    case KK_F32 * 2: fn = reinterpret_cast<const void*>(&k_ss_block<KK_F32, false>); break;
-    case KK_F32 * 2 + 1: fn = reinterpret_cast<const void*>(&k_ss_block<KK_F32, true>); break;
-    case KK_F64 * 2: fn = reinterpret_cast<const void*>(&k_ss_block<KK_F64, false>); break;
-    default: fn = reinterpret_cast<const void*>(&k_ss_block<KK_F64, true>); break;
+    case KK_U32 * 2: fn = reinterpret_cast<const void*>(&k_ss_block<KK_U32, false, true>); break;
+    case KK_U32 * 2 + 1: fn = reinterpret_cast<const void*>(&k_ss_block<KK_U32, true, true>); break;
+    case KK_U64 * 2: fn = reinterpret_cast<const void*>(&k_ss_block<KK_U64, false, true>); break;
+    case KK_U64 * 2 + 1: fn = reinterpret_cast<const void*>(&k_ss_block<KK_U64, true, true>); break;
+    case KK_F32 * 2: fn = reinterpret_cast<const void*>(&k_ss_block<KK_F32, false, true>); break;
+    case KK_F32 * 2 + 1: fn = reinterpret_cast<const void*>(&k_ss_block<KK_F32, true, true>); break;
+    case KK_F64 * 2: fn = reinterpret_cast<const void*>(&k_ss_block<KK_F64, false, true>); break;
+    default: fn = reinterpret_cast<const void*>(&k_ss_block<KK_F64, true, true>); break;
   }
   return resident(fn, SS_THREADS, cu_count);
 }

@@ -328,7 +328,11 @@ extern "C" ahs_status ahs_sort(ahs_context* ctx, const void* d_keys_in, void* d_
   std::vector<uint32_t> dcounts;
   bool have_dcounts = false;
   if (requested == AHS_AUTO) {
-    const bool radix_possible = n > c.n_small && j.f.span > c.k_count - 1 && j.f.span >= c.k_radix;
+    // digit counts ride along with the feature histogram whenever radix can
+    // be the outcome: the FSM's radix test, or any span the model may send
+    // to radix
+    const bool radix_possible =
+        n > c.n_small && j.f.span > c.k_count - 1 && (j.f.span >= c.k_radix || model_decides);
     const bool need_h = want_feats || model_decides || radix_possible;
     if (need_h) {
       const int ndig = radix_possible ? radix_digits(j.f.span) : 0;

@@ -1,0 +1,131 @@
+#!/usr/bin/env python3
+"""Measures, on the GPU this runs on, which forced strategy (COUNTING, RADIX,
+QUICK) sorts each of a grid of synthetic workloads fastest, and writes one
+CSV row per workload: its features (n, span, nbins, entropy) and the three
+wall times of ahs_sort with that strategy forced (inputs resident on the
+device, the host round trips each path needs included).  These are the
+labels the selector model of Sec. III-H is trained on (train_gbt.py).
+
+Workloads: u32 keys uniform over k values (k from 16 to 2^32), 64..65,536
+distinct values drawn with Zipf ranks, sorted and reversed uniform keys;
+u64 keys uniform over 2^64 / 2^32 / 2^16 values and Zipf over 4,096 values;
+f32 and f64 Normal(0, 1e3); n from 2^10 to 2^28.  Keys are drawn on the
+device from a seeded torch generator (the labels are measurements, not
+parity data).
+"""
+import argparse
+import csv
+import os
+import statistics
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import torch  # noqa: E402
+
+import paper_2506_20677_amd as ahs  # noqa: E402
+
+
+def workloads(max_log2n):
+    out = []
+    for lg in range(10, max_log2n + 1, 2):
+        for k in (16, 256, 1024, 4096, 65536, 1 << 20, 1 << 24, 1 << 32):
+            out.append(("u32", lg, "uniform", k))
+        for m, s in ((64, 1.1), (256, 1.1), (4096, 1.1), (65536, 1.1), (256, 1.5)):
+            out.append(("u32", lg, f"zipf{s}", m))
+        out.append(("u32", lg, "sorted", 1 << 32))
+        out.append(("u32", lg, "reverse", 1 << 32))
+        if lg <= max_log2n - 2:
+            for k in (1 << 16, 1 << 32, 1 << 64):
+                out.append(("u64", lg, "uniform", k))
+            out.append(("u64", lg, "zipf1.0", 4096))
+            out.append(("f32", lg, "normal", 0))
+            out.append(("f64", lg, "normal", 0))
+    return out
+
+
+def make_keys(dtype, lg, dist, param, g, dev):
+    n = 1 << lg
+    if dist in ("uniform", "sorted", "reverse"):
+        if param >= 1 << 63:
+            x = torch.randint(-(1 << 63), (1 << 63) - 1, (n,), generator=g, device=dev, dtype=torch.int64)
+        else:
+            x = torch.randint(0, param, (n,), generator=g, device=dev, dtype=torch.int64)
+        if dist != "uniform":
+            x = torch.sort(x, descending=(dist == "reverse")).values
+    elif dist.startswith("zipf"):
+        s = float(dist[4:])
+        vals = torch.randint(0, 1 << 32 if dtype == "u32" else (1 << 62), (param,), generator=g, device=dev,
+                             dtype=torch.int64)
+        w = torch.arange(1, param + 1, device=dev, dtype=torch.float64) ** (-s)
+        cdf = torch.cumsum(w, 0)
+        cdf /= cdf[-1].clone()
+        u = torch.rand(n, generator=g, device=dev, dtype=torch.float64)
+        x = vals[torch.searchsorted(cdf, u).clamp_(max=param - 1)]
+    else:  # normal
+        fdt = torch.float32 if dtype == "f32" else torch.float64
+        return (torch.randn(n, generator=g, device=dev, dtype=torch.float64) * 1e3).to(fdt)
+    if dtype == "u32":
+        # low 32 bits as two's complement int32, viewed unsigned
+        x = x.bitwise_and(0xFFFFFFFF)
+        x = torch.where(x >= (1 << 31), x - (1 << 32), x)
+        return x.to(torch.int32).view(torch.uint32)
+    return x.view(torch.uint64)
+
+
+def time_sort(keys, out, strategy, ctx, reps):
+    ts = []
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ahs.ahs_sort(keys, strategy=strategy, out=out, ctx=ctx)
+        torch.cuda.synchronize()
+        if r:
+            ts.append(time.perf_counter() - t)
+    return statistics.median(ts)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=os.path.join(HERE, "mi355x_labels.csv"))
+    ap.add_argument("--max-log2n", type=int, default=28)
+    ap.add_argument("--reps", type=int, default=3)
+    args = ap.parse_args()
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(2506)
+    ctx = ahs.default_context(0)
+    ctx.workspace(ahs.ahs_workspace_bytes(1 << args.max_log2n, ahs.U64, False, ahs.AUTO))
+    cfg = ahs.ahs_config_init(ahs.PRESET_GPU)
+    rows = []
+    wl = workloads(args.max_log2n)
+    for i, (dtype, lg, dist, param) in enumerate(wl):
+        keys = make_keys(dtype, lg, dist, param, g, dev)
+        out = torch.empty_like(keys)
+        f = ahs.ahs_features(keys, ctx=ctx)
+        fsm = ahs.ahs_select(f, cfg)
+        t = {}
+        for name, s in (("counting", ahs.COUNTING), ("radix", ahs.RADIX), ("quick", ahs.QUICK)):
+            if s == ahs.COUNTING and f.span >= 65536:
+                t[name] = float("inf")
+                continue
+            t[name] = time_sort(keys, out, s, ctx, args.reps)
+        best = min(t, key=t.get)
+        rows.append({"dtype": dtype, "n": f.n, "dist": dist, "param": param, "span": f.span, "nbins": f.nbins,
+                     "entropy_bits": repr(f.entropy_bits), "t_counting": t["counting"], "t_radix": t["radix"],
+                     "t_quick": t["quick"], "best": best, "fsm": ahs.STRATEGY_NAMES[fsm]})
+        print(f"[labels] {i + 1}/{len(wl)} {dtype} 2^{lg} {dist} {param}: best {best} "
+              f"({', '.join(f'{k} {v * 1e3:.3f}' for k, v in t.items())} ms), fsm {ahs.STRATEGY_NAMES[fsm]}",
+              flush=True)
+        del keys, out
+    with open(args.out, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=list(rows[0]))
+        w.writeheader()
+        w.writerows(rows)
+    print(f"[labels] wrote {len(rows)} rows to {args.out}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,105 @@
+#!/usr/bin/env python3
+"""Fits the strategy selector of Sec. III-H (gradient-boosted trees over the
+features (n, k = span + 1, H)) to labels measured on the target GPU by
+collect_labels.py, and writes it in the library's text format (the format
+ahs_model_load and the oracle's ref_model_load parse).
+
+The class of a workload is its fastest forced strategy (COUNTING, RADIX,
+QUICK); each workload is weighted by how much a wrong choice would cost
+(log of the slowest feasible time over the fastest).  Training uses
+scikit-learn's GradientBoostingClassifier (multinomial deviance); the export
+keeps its arithmetic: class score = initial raw score + learning rate x the
+leaf values of the class's trees, and the largest score wins.  scikit-learn
+sends x <= t to the left child, the library x < t, so thresholds are moved
+to the next double above.  The written model is then re-evaluated with the
+library's own evaluator (ahs_model_predict, a host function), which must
+reproduce scikit-learn's class on every training row.
+"""
+import argparse
+import csv
+import math
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CLASSES = ("counting", "radix", "quick")
+
+
+def load(path):
+    rows = list(csv.DictReader(open(path)))
+    X, y, w, times = [], [], [], []
+    for r in rows:
+        t = [float(r["t_counting"]), float(r["t_radix"]), float(r["t_quick"])]
+        X.append([float(r["n"]), float(r["span"]) + 1.0, float(r["entropy_bits"])])
+        y.append(CLASSES.index(r["best"]))
+        finite = [v for v in t if math.isfinite(v)]
+        w.append(0.1 + math.log(max(finite) / min(finite)))
+        times.append(t)
+    return rows, np.array(X), np.array(y), np.array(w), np.array(times)
+
+
+def export(clf, path):
+    lr = clf.learning_rate
+    base = clf._raw_predict_init(np.zeros((1, 3)))[0]
+    lines = ["ahs-gbt 1", "num_class 3", "base_score " + " ".join(repr(float(b)) for b in base)]
+    trees = []
+    for stage in clf.estimators_:
+        for cls, est in enumerate(stage):
+            t = est.tree_
+            nodes = []
+            for i in range(t.node_count):
+                if t.children_left[i] == -1:
+                    nodes.append(f"{i} leaf {float(t.value[i][0][0]) * lr!r}")
+                else:
+                    thr = float(np.nextafter(t.threshold[i], np.inf))
+                    nodes.append(f"{i} split {int(t.feature[i])} {thr!r} {int(t.children_left[i])} "
+                                 f"{int(t.children_right[i])}")
+            trees.append((cls, nodes))
+    lines.append(f"num_trees {len(trees)}")
+    for cls, nodes in trees:
+        lines.append(f"tree {cls} {len(nodes)}")
+        lines.extend(nodes)
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--labels", default=os.path.join(HERE, "mi355x_labels.csv"))
+    ap.add_argument("--out", default=os.path.join(HERE, "mi355x_selector.gbt"))
+    ap.add_argument("--trees", type=int, default=10)
+    ap.add_argument("--depth", type=int, default=2)
+    args = ap.parse_args()
+    from sklearn.ensemble import GradientBoostingClassifier
+
+    rows, X, y, w, times = load(args.labels)
+    clf = GradientBoostingClassifier(n_estimators=args.trees, max_depth=args.depth, learning_rate=0.3,
+                                     random_state=0)
+    clf.fit(X, y, sample_weight=w)
+    pred = clf.predict(X)
+    export(clf, args.out)
+
+    # the written file, evaluated by the library, must agree with scikit-learn
+    sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+    import paper_2506_20677_amd as ahs
+    m = ahs.ahs_model_load(args.out)
+    mism = 0
+    regret = []
+    for i in range(len(X)):
+        f = ahs.FeatureVector(n=int(X[i, 0]), span=int(rows[i]["span"]), entropy_bits=float(X[i, 2]))
+        c = ahs.ahs_model_predict(m, f) - ahs.COUNTING
+        mism += int(c != pred[i])
+        t = times[i]
+        regret.append(t[c] / np.nanmin(t) if math.isfinite(t[c]) else float("inf"))
+    acc = float(np.mean(pred == y))
+    print(f"trained {len(clf.estimators_) * 3} trees on {len(X)} rows: accuracy {acc:.3f}, "
+          f"mean time over best {np.mean([r for r in regret if math.isfinite(r)]):.4f}, "
+          f"worst {max(regret):.3f}, library/scikit-learn disagreements {mism}")
+    if mism:
+        raise SystemExit("exported model does not reproduce the fitted classifier")
+
+
+if __name__ == "__main__":
+    main()

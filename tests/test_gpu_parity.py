@@ -359,6 +359,36 @@ def test_auto_general_path():
     assert run_pair(keys, np.arange(keys.size, dtype=np.uint32)) == ahs.QUICK
 
 
+SELECTOR_CASES = [("sweep", c, 1 << 20) for c in gen.SWEEP_CASES] + \
+    [("wide", c, 1 << 19) for c in gen.WIDE_CASES] + [("pr1", "pr1", 1_000_000), ("sweep", "uniform32", 3000)]
+
+
+@pytest.mark.parametrize("family,case,n", SELECTOR_CASES, ids=[f"{c[1]}-{c[2]}" for c in SELECTOR_CASES])
+def test_auto_with_selector_model(family, case, n):
+    """AUTO with the shipped selector model: the library's decision equals the
+    oracle's (same model file, same features up to the entropy tolerance) and
+    the output is the oracle's."""
+    keys = gen.pr1() if family == "pr1" else (gen.strategy_sweep(case, n=n) if family == "sweep"
+                                              else gen.wide_keys(case, n=n))
+    vals = np.arange(keys.size, dtype=np.uint32)
+    ctx = ahs.default_context(0)
+    ctx.set_model(ahs.default_model())
+    try:
+        cfg = ahs.ahs_config_init(0, use_model=1)
+        say(f"selector {case} n={keys.size}")
+        ko, vo, chosen, f = ahs.ahs_sort(to_dev(keys), to_dev(vals), ahs.AUTO, cfg, want_features=True, ctx=ctx)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_model(None)
+    om = O.Model(ahs.SELECTOR_MODEL)
+    st, rk, rv, rchosen, rf = O.sort(keys, vals, O.AUTO, O.config(0, use_model=1), om)
+    assert st == O.OK
+    assert np.array_equal(bits(ko.cpu().numpy()), bits(rk))
+    assert np.array_equal(vo.cpu().numpy(), rv)
+    check_features(f, rf)
+    assert chosen == rchosen, (chosen, rchosen, rf.as_dict())
+
+
 @pytest.mark.parametrize("kind,log2n", [("u32", 25), ("u64", 24), ("f32", 24)])
 def test_quick_multilevel(kind, log2n):
     """Large enough that level 0 leaves buckets above the block-sort
