@@ -158,7 +158,7 @@ __global__ __launch_bounds__(MINMAX_THREADS) void k_minmax(const typename KeyTra
 
 // One workgroup folds the partials and derives span, shift and nbins.
 __global__ __launch_bounds__(256) void k_minmax_final(const MinMaxPartial* __restrict__ part, int nparts,
-                                                      uint64_t n, DevFeatures* __restrict__ df) {
+                                                      uint64_t n, DevFeatures* __restrict__ df, FeaturePlanCfg pc) {
   uint64_t mn = ~0ull, mx = 0, nan = 0;
   for (int i = threadIdx.x; i < nparts; i += 256) {
     mn = part[i].mn < mn ? part[i].mn : mn;
@@ -189,12 +189,25 @@ __global__ __launch_bounds__(256) void k_minmax_final(const MinMaxPartial* __res
     f.shift = bl > 16 ? (uint32_t)(bl - 16) : 0u;
     f.nbins = (uint32_t)(f.span >> f.shift) + 1u;
     f.exact = f.shift == 0 ? 1u : 0u;
+    if (pc.enabled) {
+      // what the AUTO decision will need: the exact histogram when counting
+      // may follow (it doubles as the counting histogram), the entropy and
+      // fused digit counts when radix may follow, the entropy for the model
+      const bool small_n = n <= pc.n_small;
+      const bool counting = !small_n && f.span <= pc.kcount_minus1 && f.span <= 65535u;
+      const bool radix = !small_n && f.span > pc.kcount_minus1 && (f.span >= pc.k_radix || pc.model);
+      const bool need = n > 0 && nan == 0 && (pc.want_hist || counting || radix || (pc.model && !small_n));
+      const int ndig = radix ? (bl + 7) / 8 > 1 ? (bl + 7) / 8 : 1 : 0;
+      uint32_t plan = PLAN_ON | (need ? 0u : PLAN_SKIP) | ((uint32_t)ndig << 4);
+      if (f.nbins > (uint32_t)HIST_SMALL_MAX_BINS || ndig > 0) plan |= PLAN_LARGE;
+      f.reserved = plan;
+    }
     *df = f;
   }
 }
 
 hipError_t launch_minmax(int kk, const void* keys, uint64_t n, MinMaxPartial* partials, int nblocks,
-                         DevFeatures* df, hipStream_t s) {
+                         DevFeatures* df, hipStream_t s, const FeaturePlanCfg* plan_cfg) {
   switch (kk) {
     case KK_U32: k_minmax<KK_U32><<<nblocks, MINMAX_THREADS, 0, s>>>((const uint32_t*)keys, n, partials); break;
     case KK_U64: k_minmax<KK_U64><<<nblocks, MINMAX_THREADS, 0, s>>>((const uint64_t*)keys, n, partials); break;
@@ -204,7 +217,9 @@ hipError_t launch_minmax(int kk, const void* keys, uint64_t n, MinMaxPartial* pa
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_minmax_final<<<1, 256, 0, s>>>(partials, nblocks, n, df);
+  FeaturePlanCfg pc = {};
+  if (plan_cfg) pc = *plan_cfg;
+  k_minmax_final<<<1, 256, 0, s>>>(partials, nblocks, n, df, pc);
   return hipGetLastError();
 }
 
@@ -215,9 +230,16 @@ template <int KK>
 __global__ __launch_bounds__(HIST_SMALL_THREADS) void k_hist_small(const typename KeyTraits<KK>::K* __restrict__ keys,
                                                                    uint64_t n, typename KeyTraits<KK>::K kmin,
                                                                    uint32_t shift, uint32_t nbins,
-                                                                   uint32_t* __restrict__ partials) {
+                                                                   uint32_t* __restrict__ partials,
+                                                                   const DevFeatures* __restrict__ plan) {
   using K = typename KeyTraits<KK>::K;
   __shared__ uint32_t h[HIST_SMALL_MAX_BINS];
+  if (plan) {
+    if (plan->reserved & (PLAN_SKIP | PLAN_LARGE)) return;
+    kmin = (K)plan->min_key;
+    shift = plan->shift;
+    nbins = plan->nbins;
+  }
   for (uint32_t b = threadIdx.x; b < nbins; b += HIST_SMALL_THREADS) h[b] = 0;
   __syncthreads();
   const uint64_t tid = (uint64_t)blockIdx.x * HIST_SMALL_THREADS + threadIdx.x;
@@ -234,13 +256,13 @@ __global__ __launch_bounds__(HIST_SMALL_THREADS) void k_hist_small(const typenam
 }
 
 hipError_t launch_hist_small(int kk, const void* keys, uint64_t n, uint64_t kmin, uint32_t shift,
-                             uint32_t nbins, uint32_t* partials, int nblocks, hipStream_t s) {
-  if (nbins > (uint32_t)HIST_SMALL_MAX_BINS) return hipErrorInvalidValue;
+                             uint32_t nbins, uint32_t* partials, int nblocks, hipStream_t s, const DevFeatures* plan) {
+  if (!plan && nbins > (uint32_t)HIST_SMALL_MAX_BINS) return hipErrorInvalidValue;
   switch (kk) {
-    case KK_U32: k_hist_small<KK_U32><<<nblocks, HIST_SMALL_THREADS, 0, s>>>((const uint32_t*)keys, n, (uint32_t)kmin, shift, nbins, partials); break;
-    case KK_U64: k_hist_small<KK_U64><<<nblocks, HIST_SMALL_THREADS, 0, s>>>((const uint64_t*)keys, n, kmin, shift, nbins, partials); break;
-    case KK_F32: k_hist_small<KK_F32><<<nblocks, HIST_SMALL_THREADS, 0, s>>>((const uint32_t*)keys, n, (uint32_t)kmin, shift, nbins, partials); break;
-    case KK_F64: k_hist_small<KK_F64><<<nblocks, HIST_SMALL_THREADS, 0, s>>>((const uint64_t*)keys, n, kmin, shift, nbins, partials); break;
+    case KK_U32: k_hist_small<KK_U32><<<nblocks, HIST_SMALL_THREADS, 0, s>>>((const uint32_t*)keys, n, (uint32_t)kmin, shift, nbins, partials, plan); break;
+    case KK_U64: k_hist_small<KK_U64><<<nblocks, HIST_SMALL_THREADS, 0, s>>>((const uint64_t*)keys, n, kmin, shift, nbins, partials, plan); break;
+    case KK_F32: k_hist_small<KK_F32><<<nblocks, HIST_SMALL_THREADS, 0, s>>>((const uint32_t*)keys, n, (uint32_t)kmin, shift, nbins, partials, plan); break;
+    case KK_F64: k_hist_small<KK_F64><<<nblocks, HIST_SMALL_THREADS, 0, s>>>((const uint64_t*)keys, n, kmin, shift, nbins, partials, plan); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -263,11 +285,19 @@ __global__ __launch_bounds__(HIST_LARGE_THREADS) void k_hist_large(const typenam
                                                                    uint64_t n, typename KeyTraits<KK>::K kmin,
                                                                    uint32_t shift, uint32_t* __restrict__ partials,
                                                                    uint32_t* __restrict__ corr, int ndig,
-                                                                   uint32_t* __restrict__ digit_partials) {
+                                                                   uint32_t* __restrict__ digit_partials,
+                                                                   const DevFeatures* __restrict__ plan) {
   using K = typename KeyTraits<KK>::K;
   constexpr int V = 16 / sizeof(K);  // keys per 16-byte load
   __shared__ uint32_t h[HIST_LARGE_WORDS];
   __shared__ uint32_t dh[DIG ? 8 * 256 : 1];
+  if (plan) {
+    const uint32_t p = plan->reserved;
+    if ((p & PLAN_SKIP) || !(p & PLAN_LARGE)) return;
+    kmin = (K)plan->min_key;
+    shift = plan->shift;
+    ndig = DIG ? plan_digits(p) : 0;
+  }
   for (int i = threadIdx.x; i < HIST_LARGE_WORDS; i += HIST_LARGE_THREADS) h[i] = 0;
   if constexpr (DIG)
     for (int i = threadIdx.x; i < 8 * 256; i += HIST_LARGE_THREADS) dh[i] = 0;
@@ -357,24 +387,25 @@ __global__ __launch_bounds__(HIST_LARGE_THREADS) void k_hist_large(const typenam
 
 template <int KK>
 static hipError_t hist_large_kk(const void* keys, uint64_t n, uint64_t kmin, uint32_t shift, uint32_t* partials,
-                                uint32_t* corr, int nblocks, int ndig, uint32_t* dparts, hipStream_t s) {
+                                uint32_t* corr, int nblocks, int ndig, uint32_t* dparts, hipStream_t s,
+                                const DevFeatures* plan) {
   using K = typename KeyTraits<KK>::K;
-  if (ndig > 0)
-    k_hist_large<KK, true><<<nblocks, HIST_LARGE_THREADS, 0, s>>>((const K*)keys, n, (K)kmin, shift, partials, corr, ndig, dparts);
+  if (ndig > 0 || plan)  // with a plan the digit count is read on the device
+    k_hist_large<KK, true><<<nblocks, HIST_LARGE_THREADS, 0, s>>>((const K*)keys, n, (K)kmin, shift, partials, corr, ndig, dparts, plan);
   else
-    k_hist_large<KK, false><<<nblocks, HIST_LARGE_THREADS, 0, s>>>((const K*)keys, n, (K)kmin, shift, partials, corr, 0, nullptr);
+    k_hist_large<KK, false><<<nblocks, HIST_LARGE_THREADS, 0, s>>>((const K*)keys, n, (K)kmin, shift, partials, corr, 0, nullptr, nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_hist_large(int kk, const void* keys, uint64_t n, uint64_t kmin, uint32_t shift,
                              uint32_t* partials, uint32_t* corr, int nblocks, int ndig,
-                             uint32_t* digit_partials, hipStream_t s) {
+                             uint32_t* digit_partials, hipStream_t s, const DevFeatures* plan) {
   if (ndig < 0 || ndig > 8) return hipErrorInvalidValue;
   switch (kk) {
-    case KK_U32: return hist_large_kk<KK_U32>(keys, n, kmin, shift, partials, corr, nblocks, ndig, digit_partials, s);
-    case KK_U64: return hist_large_kk<KK_U64>(keys, n, kmin, shift, partials, corr, nblocks, ndig, digit_partials, s);
-    case KK_F32: return hist_large_kk<KK_F32>(keys, n, kmin, shift, partials, corr, nblocks, ndig, digit_partials, s);
-    case KK_F64: return hist_large_kk<KK_F64>(keys, n, kmin, shift, partials, corr, nblocks, ndig, digit_partials, s);
+    case KK_U32: return hist_large_kk<KK_U32>(keys, n, kmin, shift, partials, corr, nblocks, ndig, digit_partials, s, plan);
+    case KK_U64: return hist_large_kk<KK_U64>(keys, n, kmin, shift, partials, corr, nblocks, ndig, digit_partials, s, plan);
+    case KK_F32: return hist_large_kk<KK_F32>(keys, n, kmin, shift, partials, corr, nblocks, ndig, digit_partials, s, plan);
+    case KK_F64: return hist_large_kk<KK_F64>(keys, n, kmin, shift, partials, corr, nblocks, ndig, digit_partials, s, plan);
     default: return hipErrorInvalidValue;
   }
 }
@@ -392,9 +423,21 @@ __global__ __launch_bounds__(HRED_THREADS) void k_hist_reduce(const uint32_t* __
                                                               uint32_t nbins, int large,
                                                               const uint32_t* __restrict__ corr,
                                                               uint32_t* __restrict__ hist_out, uint64_t n,
-                                                              double* __restrict__ hpart) {
+                                                              double* __restrict__ hpart,
+                                                              const DevFeatures* __restrict__ plan,
+                                                              int ngroups_large) {
   __shared__ uint32_t s0[HRED_SLICES][HRED_ITEMS], s1[HRED_SLICES][HRED_ITEMS];
   const int it = threadIdx.x % HRED_ITEMS, sl = threadIdx.x / HRED_ITEMS;
+  if (plan) {
+    const uint32_t p = plan->reserved;
+    if (p & PLAN_SKIP) {
+      if (threadIdx.x == 0) hpart[blockIdx.x] = 0.0;
+      return;
+    }
+    large = (p & PLAN_LARGE) ? 1 : 0;
+    nbins = plan->nbins;
+    if (large) ngroups = ngroups_large;
+  }
   const uint32_t item = blockIdx.x * HRED_ITEMS + it;
   const uint32_t nitems = large ? (nbins + 1u) / 2u : nbins;
   uint32_t c0 = 0, c1 = 0;
@@ -446,11 +489,14 @@ __global__ __launch_bounds__(HRED_THREADS) void k_hist_reduce(const uint32_t* __
 
 hipError_t launch_hist_reduce(const uint32_t* partials, int ngroups, uint32_t nbins, int large,
                               const uint32_t* corr, uint32_t* hist_out, uint64_t n, double* hpart,
-                              int* nparts_out, hipStream_t s) {
+                              int* nparts_out, hipStream_t s, const DevFeatures* plan, int ngroups_large) {
   const uint32_t items = large ? (nbins + 1u) / 2u : nbins;
-  const int nb = (int)((items + HRED_ITEMS - 1) / HRED_ITEMS);
+  // with a plan the bins are known on the device only: cover the largest
+  // histogram; blocks past the last bin contribute a zero partial
+  const int nb = plan ? HRED_MAX_BLOCKS : (int)((items + HRED_ITEMS - 1) / HRED_ITEMS);
   *nparts_out = nb;
-  k_hist_reduce<<<nb, HRED_THREADS, 0, s>>>(partials, ngroups, nbins, large, corr, hist_out, n, hpart);
+  k_hist_reduce<<<nb, HRED_THREADS, 0, s>>>(partials, ngroups, nbins, large, corr, hist_out, n, hpart, plan,
+                                            ngroups_large);
   return hipGetLastError();
 }
 
@@ -521,8 +567,14 @@ hipError_t launch_digit_hist(int kk, const void* keys, uint64_t n, uint64_t kmin
 // One thread per (pass, digit): sums the block partials; then each pass's
 // 256 counts are exclusively scanned by one wave group.
 __global__ __launch_bounds__(256) void k_digit_reduce(const uint32_t* __restrict__ parts, int nblocks, int ndig,
-                                                      uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets) {
+                                                      uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets,
+                                                      const DevFeatures* __restrict__ plan) {
   const int p = blockIdx.x, d = threadIdx.x;
+  if (plan) {
+    if (plan->reserved & PLAN_SKIP) return;
+    ndig = plan_digits(plan->reserved);
+  }
+  if (p >= ndig) return;
   uint32_t c = 0;
   for (int b = 0; b < nblocks; ++b) c += parts[((size_t)b * ndig + p) * 256 + d];
   __shared__ uint32_t sm[8];
@@ -533,8 +585,8 @@ __global__ __launch_bounds__(256) void k_digit_reduce(const uint32_t* __restrict
 }
 
 hipError_t launch_digit_reduce(const uint32_t* digit_partials, int nblocks, int ndig, uint32_t* counts,
-                               uint32_t* offsets, hipStream_t s) {
-  k_digit_reduce<<<ndig, 256, 0, s>>>(digit_partials, nblocks, ndig, counts, offsets);
+                               uint32_t* offsets, hipStream_t s, const DevFeatures* plan) {
+  k_digit_reduce<<<plan ? 8 : ndig, 256, 0, s>>>(digit_partials, nblocks, ndig, counts, offsets, plan);
   return hipGetLastError();
 }
 

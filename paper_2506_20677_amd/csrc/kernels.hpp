@@ -49,16 +49,35 @@ constexpr uint64_t STATUS32_MAX_N = 1ull << 30;
 inline size_t status_word_bytes(uint64_t n) { return n < STATUS32_MAX_N ? 4 : 8; }
 
 // ---------------------------------------------------------------- features
+// Histogram plan for the AUTO feature step without a host round trip: the
+// min/max kernel derives it from the span and the thresholds and leaves it
+// in DevFeatures::reserved; the histogram, reduce and digit kernels given a
+// `plan` pointer read their sizes from the device and skip what the plan
+// does not need.
+constexpr uint32_t PLAN_ON = 1u << 31;
+constexpr uint32_t PLAN_LARGE = 1u;  // the 65,536-bin packed histogram (else the exact small one)
+constexpr uint32_t PLAN_SKIP = 2u;   // no histogram needed
+inline __host__ __device__ int plan_digits(uint32_t plan) { return (int)((plan >> 4) & 15u); }
+struct FeaturePlanCfg {
+  uint64_t kcount_minus1, k_radix, n_small;
+  uint32_t enabled, model, want_hist, pad;
+};
+constexpr int HRED_MAX_BLOCKS = 1024;  // reduce blocks covering 65,536 bins
+
 hipError_t launch_minmax(int kk, const void* keys, uint64_t n, MinMaxPartial* partials, int nblocks,
-                         DevFeatures* df, hipStream_t s);
+                         DevFeatures* df, hipStream_t s, const FeaturePlanCfg* plan_cfg = nullptr);
 hipError_t launch_hist_small(int kk, const void* keys, uint64_t n, uint64_t kmin, uint32_t shift,
-                             uint32_t nbins, uint32_t* partials, int nblocks, hipStream_t s);
+                             uint32_t nbins, uint32_t* partials, int nblocks, hipStream_t s,
+                             const DevFeatures* plan = nullptr);
 hipError_t launch_hist_large(int kk, const void* keys, uint64_t n, uint64_t kmin, uint32_t shift,
                              uint32_t* partials, uint32_t* corr, int nblocks, int ndig,
-                             uint32_t* digit_partials, hipStream_t s);
+                             uint32_t* digit_partials, hipStream_t s, const DevFeatures* plan = nullptr);
+// With a plan: ngroups is the small histogram's block count and
+// ngroups_large the large one's; the grid covers 65,536 bins.
 hipError_t launch_hist_reduce(const uint32_t* partials, int ngroups, uint32_t nbins, int large,
                               const uint32_t* corr, uint32_t* hist_out, uint64_t n, double* hpart,
-                              int* nparts_out, hipStream_t s);
+                              int* nparts_out, hipStream_t s, const DevFeatures* plan = nullptr,
+                              int ngroups_large = 0);
 hipError_t launch_entropy_final(const double* hpart, int nparts, DevFeatures* df, hipStream_t s);
 
 // ---------------------------------------------------------------- counting
@@ -72,7 +91,8 @@ hipError_t launch_digit_hist(int kk, const void* keys, uint64_t n, uint64_t kmin
 // Sums per-block digit counts into counts[ndig][256] and their exclusive
 // scans into offsets[ndig][256].
 hipError_t launch_digit_reduce(const uint32_t* digit_partials, int nblocks, int ndig,
-                               uint32_t* counts, uint32_t* offsets, hipStream_t s);
+                               uint32_t* counts, uint32_t* offsets, hipStream_t s,
+                               const DevFeatures* plan = nullptr);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t count, uint64_t value, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t s);
 

@@ -74,6 +74,69 @@ static ahs_status step_hist(SortJob& j, uint32_t* hist_out, int ndig_fused) {
   return AHS_OK;
 }
 
+// AUTO feature step with one host round trip: min/max, then both histogram
+// kernels (the device plan keeps the one the span needs and skips the rest),
+// the reduce with the entropy, the fused digit counts; then one read of the
+// feature vector and the digit counts.  Returns the plan word.
+static ahs_status step_features_auto(SortJob& j, const ahs_config& c, bool model, bool want_hist,
+                                     std::vector<uint32_t>* dcounts, uint32_t* plan_out) {
+  DevFeatures* df = at<DevFeatures>(j.ws, j.L.df);
+  FeaturePlanCfg pc = {};
+  pc.enabled = 1;
+  pc.kcount_minus1 = c.k_count - 1;
+  pc.k_radix = c.k_radix;
+  pc.n_small = c.n_small;
+  pc.model = model ? 1u : 0u;
+  pc.want_hist = want_hist ? 1u : 0u;
+  {
+    ProfScope p(j.ctx, "minmax", j.s, (double)j.key_bytes * j.n);
+    AHS_HIP(j,
+            launch_minmax(j.kk, j.kin, j.n, at<MinMaxPartial>(j.ws, j.L.mm), minmax_blocks(j.n), df, j.s, &pc),
+            "minmax launch");
+  }
+  uint32_t* parts = at<uint32_t>(j.ws, j.L.hist_parts);
+  uint32_t* corr = at<uint32_t>(j.ws, j.L.corr);
+  const int gs = hist_small_blocks(j.n), gl = hist_large_blocks(j.n);
+  AHS_HIP(j, launch_fill_u32(corr, 65536, 0u, j.s), "fill");
+  {
+    ProfScope p(j.ctx, "feature_hist", j.s, (double)j.key_bytes * j.n);
+    AHS_HIP(j, launch_hist_small(j.kk, j.kin, j.n, 0, 0, 0, parts, gs, j.s, df), "histogram launch");
+    AHS_HIP(j, launch_hist_large(j.kk, j.kin, j.n, 0, 0, parts, corr, gl, 0, at<uint32_t>(j.ws, j.L.dparts), j.s, df),
+            "histogram launch");
+  }
+  {
+    ProfScope p(j.ctx, "hist_reduce", j.s);
+    int nparts = 0;
+    AHS_HIP(j,
+            launch_hist_reduce(parts, gs, 0, 0, corr, at<uint32_t>(j.ws, j.L.hist), j.n, at<double>(j.ws, j.L.hpart),
+                               &nparts, j.s, df, gl),
+            "histogram reduce");
+    AHS_HIP(j, launch_entropy_final(at<double>(j.ws, j.L.hpart), nparts, df, j.s), "entropy");
+  }
+  {
+    ProfScope p(j.ctx, "digit_reduce", j.s);
+    AHS_HIP(j,
+            launch_digit_reduce(at<uint32_t>(j.ws, j.L.dparts), gl, 0, at<uint32_t>(j.ws, j.L.dcounts),
+                                at<uint32_t>(j.ws, j.L.doffs), j.s, df),
+            "digit reduce");
+  }
+  char* pin = static_cast<char*>(j.ctx->pinned);
+  AHS_HIP(j, hipMemcpyAsync(pin, df, sizeof(DevFeatures), hipMemcpyDeviceToHost, j.s), "copy features");
+  AHS_HIP(j, hipMemcpyAsync(pin + 256, at<uint32_t>(j.ws, j.L.dcounts), 4 * 8 * 256, hipMemcpyDeviceToHost, j.s),
+          "copy digit counts");
+  AHS_HIP(j, hipStreamSynchronize(j.s), "synchronize");
+  memcpy(&j.f, pin, sizeof(DevFeatures));
+  const uint32_t plan = j.f.reserved;
+  j.f.reserved = 0;
+  const int ndig = plan_digits(plan);
+  if (ndig > 0) {
+    dcounts->resize(256 * (size_t)ndig);
+    memcpy(dcounts->data(), pin + 256, 4 * 256 * (size_t)ndig);
+  }
+  *plan_out = plan;
+  return AHS_OK;
+}
+
 // Reads back the feature vector and, if ndig > 0, the digit counts.
 static ahs_status read_features(SortJob& j, int ndig, std::vector<uint32_t>* counts) {
   char* pin = static_cast<char*>(j.ctx->pinned);
@@ -307,8 +370,14 @@ extern "C" ahs_status ahs_sort(ahs_context* ctx, const void* d_keys_in, void* d_
   const bool model_decides = requested == AHS_AUTO && c.use_model && n >= c.ml_min_n;
   if (model_decides && !ctx->model) return ctx->fail(AHS_E_NO_MODEL, "use_model set but no model attached");
   const bool need_minmax = flt || requested != AHS_QUICK || want_feats;
-  if (need_minmax) {
+  uint32_t plan = 0;
+  std::vector<uint32_t> dcounts;
+  if (requested == AHS_AUTO) {
+    AHS_TRY(step_features_auto(j, c, model_decides, want_feats, &dcounts, &plan));
+  } else if (need_minmax) {
     AHS_TRY(step_minmax(j));
+  }
+  if (need_minmax || requested == AHS_AUTO) {
     if (j.f.nan_count) {
       if (h_feats) {
         *h_feats = ahs_feature_vector{};
@@ -325,22 +394,13 @@ extern "C" ahs_status ahs_sort(ahs_context* ctx, const void* d_keys_in, void* d_
   // the model, or when the caller asks for the features.
   ahs_strategy s = requested;
   bool hist_ready = false;
-  std::vector<uint32_t> dcounts;
   bool have_dcounts = false;
   if (requested == AHS_AUTO) {
-    // digit counts ride along with the feature histogram whenever radix can
-    // be the outcome: the FSM's radix test, or any span the model may send
-    // to radix
-    const bool radix_possible =
-        n > c.n_small && j.f.span > c.k_count - 1 && (j.f.span >= c.k_radix || model_decides);
-    const bool need_h = want_feats || model_decides || radix_possible;
-    if (need_h) {
-      const int ndig = radix_possible ? radix_digits(j.f.span) : 0;
-      AHS_TRY(step_hist(j, at<uint32_t>(j.ws, j.L.hist), ndig));
-      AHS_TRY(read_features(j, ndig, &dcounts));
-      hist_ready = true;
-      have_dcounts = ndig > 0;
-    }
+    // the plan fused digit counts into the feature histogram whenever radix
+    // can be the outcome (the FSM's radix test, or any span the model may
+    // send to radix) and skipped the histogram where nothing needs it
+    hist_ready = (plan & PLAN_SKIP) == 0;
+    have_dcounts = plan_digits(plan) > 0;
     ahs_feature_vector fv;
     memcpy(&fv, &j.f, sizeof fv);
     AHS_TRY(ahs_select(&fv, &c, ctx->model, &s));
