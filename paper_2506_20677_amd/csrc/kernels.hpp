@@ -27,6 +27,12 @@ struct MinMaxPartial {
   uint64_t pad;
 };
 
+// A dispatch counts work-items in 32 bits: grid x block must stay below
+// 2^32.  Kernels whose work can exceed this take a grid stride, and the host
+// caps their grids at MAX_GRID_BLOCKS.
+constexpr uint32_t MAX_GRID_BLOCKS = 1u << 22;
+inline bool grid_fits(uint64_t blocks, uint32_t threads) { return blocks * (uint64_t)threads < (1ull << 32); }
+
 // Launch-geometry constants used by both the host planner and the kernels.
 constexpr int HIST_SMALL_MAX_BINS = 8192;      // u32 LDS bins
 constexpr int HIST_LARGE_WORDS = 32768;        // 65,536 packed u16 bins

@@ -420,6 +420,7 @@ hipError_t launch_ss_init(SsSeg* segs, SsItem* items, uint64_t n, hipStream_t s)
 hipError_t launch_ss_sample(int kk, const void* src, int map_in, const SsSeg* segs, const SsLevelIn& lv, void* spl,
                             uint32_t* counts, uint64_t seed, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
+  if ((uint32_t)nblocks > MAX_GRID_BLOCKS) nblocks = (int)MAX_GRID_BLOCKS;  // the kernel strides over segments
   switch (kk) {
     case KK_U32: k_ss_sample<KK_U32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, lv, (uint32_t*)spl, counts, seed); break;
     case KK_U64: k_ss_sample<KK_U64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, lv, (uint64_t*)spl, counts, seed); break;
@@ -458,6 +459,7 @@ hipError_t launch_ss_plan(const SsSeg* segs, const SsLevelIn& lv, const uint32_t
                           uint32_t dst_buf, int copy_in_place, SsSeg* next, SsItem* items, SsCounters* ctr,
                           uint32_t item_cap, uint32_t seg_cap, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
+  if ((uint32_t)nblocks > MAX_GRID_BLOCKS) nblocks = (int)MAX_GRID_BLOCKS;  // the kernel strides over segments
   k_ss_plan<<<nblocks, SS_NB, 0, s>>>(segs, lv, counts, offs, dst_buf, copy_in_place, next, items, ctr, item_cap,
                                       seg_cap);
   return hipGetLastError();
@@ -500,8 +502,13 @@ static hipError_t scatter_any(int kk, int with_vals, const SsScatterArgs& a, uin
 }
 
 hipError_t launch_ss_scatter(int kk, int with_vals, const SsScatterArgs& a, uint32_t nblocks, hipStream_t s) {
-  if (nblocks) return scatter_any<true>(kk, with_vals, a, nblocks, s);
+  if (nblocks) {
+    if (!grid_fits(nblocks, SS_THREADS)) return hipErrorInvalidConfiguration;
+    return scatter_any<true>(kk, with_vals, a, nblocks, s);
+  }
   if (a.lv.ntiles == 0) return hipSuccess;
+  if (a.lv.ntiles > MAX_GRID_BLOCKS)  // one workgroup per tile would overflow the dispatch
+    return scatter_any<true>(kk, with_vals, a, MAX_GRID_BLOCKS, s);
   return scatter_any<false>(kk, with_vals, a, a.lv.ntiles, s);
 }
 
@@ -522,8 +529,17 @@ static hipError_t block_any(int kk, int with_vals, const SsBlockArgs& a, uint32_
 }
 
 hipError_t launch_ss_block(int kk, int with_vals, const SsBlockArgs& a, uint32_t nblocks, hipStream_t s) {
-  if (nblocks) return block_any<true>(kk, with_vals, a, nblocks, s);
+  if (nblocks) {
+    if (!grid_fits(nblocks, SS_THREADS)) return hipErrorInvalidConfiguration;
+    return block_any<true>(kk, with_vals, a, nblocks, s);
+  }
   if (a.nitems == 0) return hipSuccess;
+  if (a.nitems > MAX_GRID_BLOCKS) {  // one workgroup per item would overflow the dispatch
+    SsBlockArgs b = a;
+    b.lvl = nullptr;
+    b.item_cap = a.nitems;
+    return block_any<true>(kk, with_vals, b, MAX_GRID_BLOCKS, s);
+  }
   return block_any<false>(kk, with_vals, a, a.nitems, s);
 }
 

@@ -384,7 +384,7 @@ __global__ __launch_bounds__(256) void k_tune_fill(typename KeyTraits<KK>::K* __
 // ------------------------------------------------------------------ launchers
 hipError_t launch_seg_classify(const uint64_t* offs, uint32_t nseg, uint64_t n_total, uint32_t* queues, uint32_t qcap,
                                SsSeg* large_ss, SsSeg* large, uint32_t* large_ids, SegCounters* ctr, hipStream_t s) {
-  const uint32_t nb = (nseg + 256) / 256;
+  const uint32_t nb = (uint32_t)(((uint64_t)nseg + 256) / 256);  // nseg < 2^32: at most 2^24 workgroups of 256
   k_seg_classify<<<nb, 256, 0, s>>>(offs, nseg, n_total, queues, qcap, large_ss, large, large_ids, ctr);
   return hipGetLastError();
 }
@@ -419,6 +419,7 @@ static hipError_t small_kk(const SegArgs& a, int cls, int variant, uint32_t grid
 hipError_t launch_seg_small(int kk, int with_vals, const SegArgs& a, int cls, int variant, uint32_t nblocks,
                             hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
+  if (nblocks > MAX_GRID_BLOCKS) nblocks = MAX_GRID_BLOCKS;  // the kernel strides over its queue
   if (cls < 0 || cls >= SEG_NCLASS || variant < cls || variant >= SEG_NVARIANT) return hipErrorInvalidValue;
   switch (kk * 2 + (with_vals ? 1 : 0)) {
     case KK_U32 * 2: return small_kk<KK_U32, false>(a, cls, variant, nblocks, s);
@@ -454,6 +455,10 @@ uint32_t seg_small_resident(int kk, int with_vals, int variant, uint32_t cu_coun
 hipError_t launch_seg_large(int kk, const SegArgs& a, uint32_t bound_blocks, uint32_t chunk_blocks,
                             uint32_t final_blocks, hipStream_t s) {
   if (bound_blocks == 0 || chunk_blocks == 0 || final_blocks == 0) return hipSuccess;
+  // every kernel here strides over its work
+  bound_blocks = bound_blocks < MAX_GRID_BLOCKS ? bound_blocks : MAX_GRID_BLOCKS;
+  chunk_blocks = chunk_blocks < MAX_GRID_BLOCKS ? chunk_blocks : MAX_GRID_BLOCKS;
+  final_blocks = final_blocks < MAX_GRID_BLOCKS ? final_blocks : MAX_GRID_BLOCKS;
   switch (kk) {
     case KK_U32:
       k_seg_bounds<KK_U32><<<bound_blocks, 64, 0, s>>>(a);

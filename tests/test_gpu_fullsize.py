@@ -161,3 +161,11 @@ def test_batched_full_size_graph():
         f = feats[s]
         assert (f.n, f.min_key, f.max_key, f.span, f.nbins) == (rf.n, rf.min_key, rf.max_key, rf.span, rf.nbins)
     say(f"full-size batch: {len(pick)} sampled segments match the oracle")
+    # the blocking form on the same batch: its host-driven levels finish more
+    # buckets in one level than one workgroup per bucket can address in a
+    # single dispatch (regression: the launch wrapped and left buckets unsorted)
+    ob, _, cb, fb = ahs.ahs_sort_segmented(k, o, want_features=True)
+    torch.cuda.synchronize()
+    assert torch.equal(ob.view(torch.int32), a), "blocking and graph outputs differ"
+    assert torch.equal(cb, g.chosen), "blocking and graph decisions differ"
+    say("full-size batch: blocking form identical to the graph")
