@@ -97,7 +97,7 @@ inline Layout plan_layout(uint64_t n, int key_bytes, int with_payload, bool need
     o = align_up(o + bytes, 256);
     return at;
   };
-  const uint64_t tile = (uint64_t)os_tile(key_bytes);
+  const uint64_t tile = (uint64_t)os_tile(key_bytes, with_payload != 0);
   const uint64_t tiles = ceil_div(n ? n : 1, tile);
   L.df = take(sizeof(DevFeatures));
   L.mm = take(sizeof(MinMaxPartial) * (size_t)minmax_blocks(n));

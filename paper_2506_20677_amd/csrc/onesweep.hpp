@@ -105,7 +105,17 @@ template <> struct Status<uint64_t> {
 // the pass is running); if that one only holds an aggregate it reads the
 // next LB_WIDTH predecessors with independent loads per round, so the
 // inclusive frontier is not limited to one tile per load latency.
-constexpr int LB_WIDTH = 8;
+#ifndef AHS_LB_WIDTH
+#define AHS_LB_WIDTH 4
+#endif
+#ifndef AHS_LB_SLEEP
+#define AHS_LB_SLEEP 1
+#endif
+constexpr int LB_WIDTH = AHS_LB_WIDTH;  // predecessors read per round of the walk (compile-time tunable)
+
+__device__ __forceinline__ void lb_pause() {
+  if constexpr (AHS_LB_SLEEP > 0) __builtin_amdgcn_s_sleep(AHS_LB_SLEEP);
+}
 
 template <int ND, typename ST>
 __device__ __forceinline__ uint64_t lookback(ST* __restrict__ status, uint32_t tile, uint32_t first_tile,
@@ -123,7 +133,7 @@ __device__ __forceinline__ uint64_t lookback(ST* __restrict__ status, uint32_t t
   for (;;) {
     const ST s = ld_agent(status + (uint64_t)j * ND + t);
     if ((s & S::FLAGS) == 0) {
-      __builtin_amdgcn_s_sleep(1);
+      lb_pause();
       continue;
     }
     excl += s & S::VAL;
@@ -151,7 +161,7 @@ __device__ __forceinline__ uint64_t lookback(ST* __restrict__ status, uint32_t t
       }
     }
     if (done) break;
-    if (q == 0) __builtin_amdgcn_s_sleep(1);
+    if (q == 0) lb_pause();
     j -= q;
   }
   st_agent(mine, (ST)(S::INC | (ST)(excl + count)));
@@ -187,7 +197,7 @@ __device__ __forceinline__ uint64_t lookback_end(ST* __restrict__ status, uint32
   ST s0 = first_read;
   for (;;) {
     if ((s0 & S::FLAGS) != 0) break;
-    __builtin_amdgcn_s_sleep(1);
+    lb_pause();
     s0 = ld_agent(status + (uint64_t)j * ND + t);
   }
   excl += s0 & S::VAL;
@@ -213,7 +223,7 @@ __device__ __forceinline__ uint64_t lookback_end(ST* __restrict__ status, uint32
       }
     }
     if (done) break;
-    if (q == 0) __builtin_amdgcn_s_sleep(1);
+    if (q == 0) lb_pause();
     j -= q;
   }
   st_agent(mine, (ST)(S::INC | (ST)(excl + count)));

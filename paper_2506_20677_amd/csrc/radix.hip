@@ -115,7 +115,8 @@ __global__ __launch_bounds__(OS_THREADS) void k_onesweep(OnesweepArgs a) {
 
 template <int KK, bool PAY>
 static hipError_t onesweep_kk(const OnesweepArgs& a, hipStream_t s) {
-  constexpr int IPT = sizeof(typename KeyTraits<KK>::K) == 4 ? 16 : 8;
+  constexpr int IPT = sizeof(typename KeyTraits<KK>::K) == 4 ? (PAY ? OS_IPT32P : OS_IPT32)
+                                                            : (PAY ? OS_IPT64P : OS_IPT64);
   constexpr int TILE = OS_THREADS * IPT;
   const uint64_t tiles = (a.n + TILE - 1) / TILE;
   if (a.n < STATUS32_MAX_N)

@@ -211,7 +211,7 @@ static ahs_status run_radix(SortJob& j, const std::vector<uint32_t>* ready_count
     AHS_HIP(j, launch_copy(j.vin, tmpv, 4 * (size_t)j.n, j.s), "copy");
     vsrc = tmpv;
   }
-  const uint64_t tiles = ceil_div(j.n, (uint64_t)os_tile(j.key_bytes));
+  const uint64_t tiles = ceil_div(j.n, (uint64_t)os_tile(j.key_bytes, j.vin != nullptr));
   uint32_t* status = at<uint32_t>(j.ws, j.L.status);
   const uint64_t status_words32 = tiles * 256 * status_word_bytes(j.n) / 4;
   uint32_t* counters = at<uint32_t>(j.ws, j.L.counters);
