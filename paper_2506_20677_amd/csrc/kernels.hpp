@@ -51,7 +51,8 @@ constexpr int OS_WAVES = OS_THREADS / 64;
 // shorten the look-back chain per key; the key-only sizes are the largest
 // that keep two 512-thread workgroups per CU (at most 128 VGPRs): measured
 // on 2^28 u32 / 2^27 u64 passes, 24 and 16 keys per thread beat 16 and 8 by
-// 18 % and 20 %.  Payload variants carry a second array and keep 16 and 8.
+// 18 % and 20 %.  Payload variants carry a second array: 16 (u32) and 12
+// (u64) keys per thread measured best (u64: 10 % over 8).
 #ifndef AHS_OS_IPT32
 #define AHS_OS_IPT32 24
 #endif
@@ -62,7 +63,7 @@ constexpr int OS_WAVES = OS_THREADS / 64;
 #define AHS_OS_IPT32P 16
 #endif
 #ifndef AHS_OS_IPT64P
-#define AHS_OS_IPT64P 8
+#define AHS_OS_IPT64P 12
 #endif
 constexpr int OS_IPT32 = AHS_OS_IPT32, OS_IPT64 = AHS_OS_IPT64;
 constexpr int OS_IPT32P = AHS_OS_IPT32P, OS_IPT64P = AHS_OS_IPT64P;

@@ -472,13 +472,13 @@ hipError_t launch_ss_tiles(SsSeg* segs, SsCounters* ctr, uint32_t tile_keys, uin
 
 template <int KK, bool PAY, typename ST>
 static const void* scatter_fn() {
-  constexpr int IPT = sizeof(typename KeyTraits<KK>::K) == 4 ? 16 : 8;
+  constexpr int IPT = sizeof(typename KeyTraits<KK>::K) == 4 ? SS_IPT32 : SS_IPT64;
   return reinterpret_cast<const void*>(&k_ss_scatter<KK, PAY, IPT, ST, true>);
 }
 
 template <int KK, bool PAY, bool PERSIST>
 static hipError_t scatter_kk(const SsScatterArgs& a, uint32_t grid, hipStream_t s) {
-  constexpr int IPT = sizeof(typename KeyTraits<KK>::K) == 4 ? 16 : 8;
+  constexpr int IPT = sizeof(typename KeyTraits<KK>::K) == 4 ? SS_IPT32 : SS_IPT64;
   if (a.max_seg < STATUS32_MAX_N)
     k_ss_scatter<KK, PAY, IPT, uint32_t, PERSIST><<<grid, SS_THREADS, 0, s>>>(a);
   else

@@ -15,7 +15,16 @@ constexpr int SS_SAMPLES = 8192;      // sample keys per segment
 constexpr int SS_CAP = 8192;          // largest bucket finished in LDS
 constexpr int SS_THREADS = 512;
 constexpr int SS_MAX_LEVELS = 48;
-inline int ss_tile(int key_bytes) { return SS_THREADS * (key_bytes == 4 ? 16 : 8); }
+// u32 scatter tiles of 24 keys per thread measured 6 % faster than 16 on
+// 2^28 keys; u64 keeps 8 (12 and 16 were slower).
+#ifndef AHS_SS_IPT32
+#define AHS_SS_IPT32 24
+#endif
+#ifndef AHS_SS_IPT64
+#define AHS_SS_IPT64 8
+#endif
+constexpr int SS_IPT32 = AHS_SS_IPT32, SS_IPT64 = AHS_SS_IPT64;  // scatter keys per thread (tunable)
+inline int ss_tile(int key_bytes) { return SS_THREADS * (key_bytes == 4 ? SS_IPT32 : SS_IPT64); }
 
 constexpr uint32_t SS_BUF_IN = 0, SS_BUF_OUT = 1, SS_BUF_TMP = 2;
 constexpr uint32_t SS_ITEM_COPY = 1;
