@@ -9,6 +9,19 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
+// Compile-time tunables of the LDS histograms: lanes that must start in the
+// first lane's bin for the wave to add that bin once; copies of the fused
+// digit counters for 4- and 8-byte keys.
+#ifndef AHS_HIST_GATE
+#define AHS_HIST_GATE 8
+#endif
+#ifndef AHS_DIG_COPIES32
+#define AHS_DIG_COPIES32 4
+#endif
+#ifndef AHS_DIG_COPIES64
+#define AHS_DIG_COPIES64 2
+#endif
+
 namespace ahs {
 
 // Streams the keys of [0, n) assigned to this thread with 16-byte loads
@@ -97,22 +110,45 @@ __device__ __forceinline__ void for_each_group(const K* __restrict__ keys, uint6
   }
 }
 
-// Counts m values of a run (bins b[0..m) of this lane) into LDS counters:
-// when every active lane holds m values of one and the same bin -- sorted
-// or run-structured input -- a single lane adds the whole wave's count;
-// otherwise each value is added by its own lane.  Returns nothing; used for
-// plain u32 counters.
+// True (in every lane) when at least a quarter of the wave's lanes start
+// with bin c, the first active lane's first bin: sorted, nearly sorted and
+// run-structured input, where one atomic per key would serialise on one LDS
+// address.  Random input fails this one-ballot test and keeps the plain
+// per-key path.
+template <int V>
+__device__ __forceinline__ bool wave_bin_dominant(const uint32_t (&b)[V], uint32_t c) {
+  return popc64(__ballot(b[0] == c)) >= AHS_HIST_GATE;
+}
+
+// Takes the wave's keys of bin c out of `pend` and returns their number
+// (the same in every lane).
+template <int V>
+__device__ __forceinline__ uint32_t take_wave_bin(const uint32_t (&b)[V], bool (&pend)[V], uint32_t c) {
+  uint32_t tot = 0;
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    const bool e = pend[i] && b[i] == c;
+    tot += popc64(__ballot(e));
+    pend[i] = pend[i] && !e;
+  }
+  return tot;
+}
+
+// Counts m values (bins b[0..m) of this lane) into plain u32 LDS counters:
+// one atomic per value, except that a dominant bin of the wave is added once
+// by one lane.
 template <int V>
 __device__ __forceinline__ void lds_count_group(uint32_t* __restrict__ h, const uint32_t (&b)[V], int m) {
-  bool same = true;
+  const uint32_t c = __builtin_amdgcn_readfirstlane(b[0]);
+  if (wave_bin_dominant<V>(b, c)) {
+    bool pend[V];
 #pragma unroll
-  for (int i = 1; i < V; ++i)
-    if (i < m) same &= b[i] == b[0];
-  const uint32_t b0 = __builtin_amdgcn_readfirstlane(b[0]);
-  const uint64_t active = __ballot(1);
-  const uint64_t uni = __ballot(same && b[0] == b0 && m == V);
-  if (uni == active) {
-    if (mbcnt(active) == 0) atomicAdd(&h[b0], (uint32_t)popc64(active) * V);
+    for (int i = 0; i < V; ++i) pend[i] = i < m;
+    const uint32_t hit = take_wave_bin<V>(b, pend, c);
+    if (mbcnt(__ballot(1)) == 0) atomicAdd(&h[c], hit);
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+      if (pend[i]) atomicAdd(&h[b[i]], 1u);
   } else {
 #pragma unroll
     for (int i = 0; i < V; ++i)
@@ -289,8 +325,15 @@ __global__ __launch_bounds__(HIST_LARGE_THREADS) void k_hist_large(const typenam
                                                                    const DevFeatures* __restrict__ plan) {
   using K = typename KeyTraits<KK>::K;
   constexpr int V = 16 / sizeof(K);  // keys per 16-byte load
+  // digit counters: DCOPY copies, lane l counting into copy l % DCOPY, so
+  // that lanes holding one frequent key (skewed input) hit DCOPY different
+  // addresses; copies are offset by 16 banks
+  constexpr int DMAX = sizeof(K);  // 8-bit digits of a key
+  constexpr int DCOPY = DIG ? (sizeof(K) == 4 ? AHS_DIG_COPIES32 : AHS_DIG_COPIES64) : 1;
+  constexpr int DSTRIDE = DMAX * 256 + 16;
   __shared__ uint32_t h[HIST_LARGE_WORDS];
-  __shared__ uint32_t dh[DIG ? 8 * 256 : 1];
+  __shared__ uint32_t dh[DIG ? DCOPY * DSTRIDE : 1];
+  static_assert(sizeof(h) + sizeof(dh) <= 160 * 1024, "LDS");
   if (plan) {
     const uint32_t p = plan->reserved;
     if ((p & PLAN_SKIP) || !(p & PLAN_LARGE)) return;
@@ -298,21 +341,25 @@ __global__ __launch_bounds__(HIST_LARGE_THREADS) void k_hist_large(const typenam
     shift = plan->shift;
     ndig = DIG ? plan_digits(p) : 0;
   }
+  ndig = ndig < DMAX ? ndig : DMAX;  // the counters hold one key's digits
   for (int i = threadIdx.x; i < HIST_LARGE_WORDS; i += HIST_LARGE_THREADS) h[i] = 0;
   if constexpr (DIG)
-    for (int i = threadIdx.x; i < 8 * 256; i += HIST_LARGE_THREADS) dh[i] = 0;
+    for (int i = threadIdx.x; i < DCOPY * DSTRIDE; i += HIST_LARGE_THREADS) dh[i] = 0;
   __syncthreads();
+  uint32_t* const mydh = dh + (DIG ? (lane_id() % DCOPY) * DSTRIDE : 0);
 
-  // Adds c to bin `bin` of the packed counters and repairs a 16-bit wrap.
-  auto add_packed = [&](uint32_t bin, uint32_t c) {
-    const uint32_t hi = bin & 1u;
-    const uint32_t old = atomicAdd(&h[bin >> 1], hi ? (c << 16) : c);
-    if (hi) {
+  // Repairs a 16-bit wrap after c was added to bin `bin`, whose word held
+  // `old` before the add.
+  auto fix_packed = [&](uint32_t bin, uint32_t old, uint32_t c) {
+    if (bin & 1u) {
       if ((old >> 16) + c > 0xFFFFu) add_agent(&corr[bin], 65536u);
     } else if ((old & 0xFFFFu) + c > 0xFFFFu) {
       add_agent(&corr[bin], 65536u);
       add_agent(&corr[bin + 1], (old >> 16) == 0xFFFFu ? 65535u : 0xFFFFFFFFu);
     }
+  };
+  auto packed_add = [&](uint32_t bin, uint32_t c) {
+    return atomicAdd(&h[bin >> 1], (bin & 1u) ? (c << 16) : c);
   };
 
   const uint64_t nthreads = (uint64_t)gridDim.x * HIST_LARGE_THREADS;
@@ -320,59 +367,33 @@ __global__ __launch_bounds__(HIST_LARGE_THREADS) void k_hist_large(const typenam
   for_each_group<K, 4>(keys, n, tid, nthreads, [&](const K (&kb)[V], int m) {
     K off[V];
     uint32_t bins[V];
+    bool pend[V];
 #pragma unroll
     for (int i = 0; i < V; ++i) {
       off[i] = map_key<KK>(kb[i]) - kmin;
       bins[i] = (uint32_t)(off[i] >> shift);
+      pend[i] = i < m;
     }
-    bool same = true;
-#pragma unroll
-    for (int i = 1; i < V; ++i)
-      if (i < m) same &= bins[i] == bins[0];
-    const uint32_t b0 = __builtin_amdgcn_readfirstlane(bins[0]);
-    const uint64_t active = __ballot(1);
-    if (__ballot(same && bins[0] == b0 && m == V) == active) {
-      if (mbcnt(active) == 0) add_packed(b0, (uint32_t)popc64(active) * V);
-    } else {
-      // per key slot: lanes sharing the first pending lane's bin (a hot or
-      // run-length bin) add together through one lane, if there are enough
-      bool pend[V];
-#pragma unroll
-      for (int i = 0; i < V; ++i) {
-        pend[i] = i < m;
-        const uint64_t pm = __ballot(pend[i]);
-        if (pm) {
-          const uint32_t c = __builtin_amdgcn_readlane(bins[i], __builtin_ctzll(pm));
-          const uint64_t sm = __ballot(pend[i] && bins[i] == c);
-          if (popc64(sm) >= 8) {
-            if (mbcnt(sm) == 0 && (sm >> lane_id()) & 1ull) add_packed(c, popc64(sm));
-            pend[i] = pend[i] && bins[i] != c;
-          }
-        }
-      }
-      // independent returning atomics first, overflow checks after
-      uint32_t olds[V];
-#pragma unroll
-      for (int i = 0; i < V; ++i)
-        if (pend[i]) olds[i] = atomicAdd(&h[bins[i] >> 1], (bins[i] & 1u) ? 0x10000u : 1u);
-#pragma unroll
-      for (int i = 0; i < V; ++i) {
-        if (!pend[i]) continue;
-        const uint32_t bin = bins[i], old = olds[i];
-        if (bin & 1u) {
-          if ((old >> 16) == 0xFFFFu) add_agent(&corr[bin], 65536u);
-        } else if ((old & 0xFFFFu) == 0xFFFFu) {
-          add_agent(&corr[bin], 65536u);
-          add_agent(&corr[bin + 1], old == 0xFFFFFFFFu ? 65535u : 0xFFFFFFFFu);
-        }
-      }
+    // a dominant bin of the wave through one lane; every other key with its
+    // own atomic: independent returning atomics first, overflow repairs after
+    const uint32_t c = __builtin_amdgcn_readfirstlane(bins[0]);
+    if (wave_bin_dominant<V>(bins, c)) {
+      const uint32_t hit = take_wave_bin<V>(bins, pend, c);
+      if (mbcnt(__ballot(1)) == 0) fix_packed(c, packed_add(c, hit), hit);
     }
+    uint32_t olds[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+      if (pend[i]) olds[i] = packed_add(bins[i], 1u);
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+      if (pend[i]) fix_packed(bins[i], olds[i], 1u);
     if constexpr (DIG) {
       for (int p = 0; p < ndig; ++p) {
         uint32_t dg[V];
 #pragma unroll
         for (int i = 0; i < V; ++i) dg[i] = (uint32_t)((off[i] >> (8 * p)) & 255u);
-        lds_count_group<V>(dh + p * 256, dg, m);
+        lds_count_group<V>(mydh + p * 256, dg, m);
       }
     }
   });
@@ -381,7 +402,12 @@ __global__ __launch_bounds__(HIST_LARGE_THREADS) void k_hist_large(const typenam
   for (int i = threadIdx.x; i < HIST_LARGE_WORDS; i += HIST_LARGE_THREADS) out[i] = h[i];
   if constexpr (DIG) {
     uint32_t* dout = digit_partials + (size_t)blockIdx.x * ndig * 256;
-    for (int i = threadIdx.x; i < ndig * 256; i += HIST_LARGE_THREADS) dout[i] = dh[i];
+    for (int i = threadIdx.x; i < ndig * 256; i += HIST_LARGE_THREADS) {
+      uint32_t t = 0;
+#pragma unroll
+      for (int r = 0; r < DCOPY; ++r) t += dh[r * DSTRIDE + i];
+      dout[i] = t;
+    }
   }
 }
 
@@ -400,7 +426,7 @@ static hipError_t hist_large_kk(const void* keys, uint64_t n, uint64_t kmin, uin
 hipError_t launch_hist_large(int kk, const void* keys, uint64_t n, uint64_t kmin, uint32_t shift,
                              uint32_t* partials, uint32_t* corr, int nblocks, int ndig,
                              uint32_t* digit_partials, hipStream_t s, const DevFeatures* plan) {
-  if (ndig < 0 || ndig > 8) return hipErrorInvalidValue;
+  if (ndig < 0 || ndig > key_bytes_of(kk)) return hipErrorInvalidValue;
   switch (kk) {
     case KK_U32: return hist_large_kk<KK_U32>(keys, n, kmin, shift, partials, corr, nblocks, ndig, digit_partials, s, plan);
     case KK_U64: return hist_large_kk<KK_U64>(keys, n, kmin, shift, partials, corr, nblocks, ndig, digit_partials, s, plan);
@@ -530,9 +556,15 @@ __global__ __launch_bounds__(DIGIT_HIST_THREADS) void k_digit_hist(const typenam
                                                                    uint64_t n, typename KeyTraits<KK>::K kmin, int ndig,
                                                                    uint32_t* __restrict__ digit_partials) {
   using K = typename KeyTraits<KK>::K;
-  __shared__ uint32_t dh[8 * 256];
-  for (int i = threadIdx.x; i < 8 * 256; i += DIGIT_HIST_THREADS) dh[i] = 0;
+  // copies of the counters as in the fused histogram: lane l counts into
+  // copy l % DCOPY
+  constexpr int DCOPY = sizeof(K) == 4 ? AHS_DIG_COPIES32 : AHS_DIG_COPIES64;
+  constexpr int DSTRIDE = (int)sizeof(K) * 256 + 16;
+  __shared__ uint32_t dh[DCOPY * DSTRIDE];
+  for (int i = threadIdx.x; i < DCOPY * DSTRIDE; i += DIGIT_HIST_THREADS) dh[i] = 0;
   __syncthreads();
+  uint32_t* const mydh = dh + (lane_id() % DCOPY) * DSTRIDE;
+  ndig = ndig < (int)sizeof(K) ? ndig : (int)sizeof(K);  // the counters hold one key's digits
   const uint64_t tid = (uint64_t)blockIdx.x * DIGIT_HIST_THREADS + threadIdx.x;
   constexpr int V = 16 / sizeof(K);
   for_each_group<K, 4>(keys, n, tid, (uint64_t)gridDim.x * DIGIT_HIST_THREADS, [&](const K (&kb)[V], int m) {
@@ -543,17 +575,22 @@ __global__ __launch_bounds__(DIGIT_HIST_THREADS) void k_digit_hist(const typenam
       uint32_t dg[V];
 #pragma unroll
       for (int i = 0; i < V; ++i) dg[i] = (uint32_t)((off[i] >> (8 * p)) & 255u);
-      lds_count_group<V>(dh + p * 256, dg, m);
+      lds_count_group<V>(mydh + p * 256, dg, m);
     }
   });
   __syncthreads();
   uint32_t* out = digit_partials + (size_t)blockIdx.x * ndig * 256;
-  for (int i = threadIdx.x; i < ndig * 256; i += DIGIT_HIST_THREADS) out[i] = dh[i];
+  for (int i = threadIdx.x; i < ndig * 256; i += DIGIT_HIST_THREADS) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int r = 0; r < DCOPY; ++r) t += dh[r * DSTRIDE + i];
+    out[i] = t;
+  }
 }
 
 hipError_t launch_digit_hist(int kk, const void* keys, uint64_t n, uint64_t kmin, int ndig,
                              uint32_t* digit_partials, int nblocks, hipStream_t s) {
-  if (ndig < 1 || ndig > 8) return hipErrorInvalidValue;
+  if (ndig < 1 || ndig > key_bytes_of(kk)) return hipErrorInvalidValue;
   switch (kk) {
     case KK_U32: k_digit_hist<KK_U32><<<nblocks, DIGIT_HIST_THREADS, 0, s>>>((const uint32_t*)keys, n, (uint32_t)kmin, ndig, digit_partials); break;
     case KK_U64: k_digit_hist<KK_U64><<<nblocks, DIGIT_HIST_THREADS, 0, s>>>((const uint64_t*)keys, n, kmin, ndig, digit_partials); break;

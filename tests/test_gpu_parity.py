@@ -86,6 +86,27 @@ def run_pair(keys, vals=None, strategy=ahs.AUTO, cfg_preset=0, in_place=False):
 
 
 # ------------------------------------------------------------------ features
+def _packed_pair(runs):
+    """Keys of the two bins sharing packed LDS word 0 (shift 16), each more
+    than 65,535 times per workgroup, so both 16-bit halves wrap, also while
+    the other half is full: in random order (dominant-bin adds of a wave)
+    or in runs of random length (dominant-bin adds plus runs merged inside
+    a lane), with sparse keys of other bins."""
+    r = np.random.default_rng(23 + runs)
+    n = 1 << 21
+    if runs:
+        lens = r.integers(1, 700, n // 100)
+        keys = np.repeat(np.where(np.arange(lens.size) % 2 == 0, 3, 65539), lens)[:n]
+        keys = np.concatenate([keys, np.full(n - keys.size, 3)])
+    else:
+        keys = np.where(r.random(n) < 0.5, 3, 65539)
+    keys = keys.astype(np.uint32)
+    other = r.integers(0, n, n // 500)
+    keys[other] = r.integers(0, 2**32, other.size, dtype=np.uint64).astype(np.uint32)
+    keys[0], keys[-1] = 0, 2**32 - 1
+    return keys
+
+
 FEATURE_CASES = [
     ("pr1", lambda: gen.pr1()),
     ("u32 uniform4096 1M", lambda: gen.strategy_sweep("uniform4096", n=1 << 20)),
@@ -102,6 +123,10 @@ FEATURE_CASES = [
     ("u32 span 65536", lambda: (np.arange(200_003) * 7 % 65537).astype(np.uint32)),
     ("u32 one hot bin overflow", lambda: np.concatenate([np.zeros(300_000, np.uint32), np.full(300_000, 1, np.uint32),
                                                          np.array([2**32 - 1], np.uint32)])),
+    ("u32 packed pair random", lambda: _packed_pair(False)),
+    ("u32 packed pair runs", lambda: _packed_pair(True)),
+    ("u32 swapped 4M", lambda: gen.strategy_sweep("swapped32", n=1 << 22)),
+    ("u32 sorted 4M", lambda: gen.strategy_sweep("sorted32", n=1 << 22)),
     ("u64 two", lambda: np.array([0, 2**64 - 1], np.uint64)),
     ("f32 signed zeros", lambda: np.array([0.0, -0.0] * 50, np.float32)),
     ("u32 n=1", lambda: np.array([12345], np.uint32)),
@@ -222,6 +247,21 @@ def test_auto_choices_match_oracle():
     for case, want in (("u64zipf4096", ahs.RADIX), ("f32normal", ahs.RADIX), ("f64normal", ahs.RADIX)):
         keys = gen.wide_keys(case, n=1 << 19)
         assert run_pair(keys, np.arange(keys.size, dtype=np.uint32)) == want
+
+
+def test_radix_on_sorted_low_entropy():
+    """Sorted keys of low entropy over a span above 2^20: AUTO plans radix
+    digits during the feature pass (fused digit counts of sorted, wave-
+    uniform digits) and picks radix; also nearly sorted."""
+    r = np.random.default_rng(29)
+    keys = (np.sort(r.zipf(1.3, 1 << 21) % 97).astype(np.uint64) * 40_009).astype(np.uint32)
+    assert run_pair(keys) == ahs.RADIX
+    assert run_pair(keys, np.arange(keys.size, dtype=np.uint32)) == ahs.RADIX
+    sw = keys.copy()
+    i = r.integers(0, keys.size, 5000)
+    j = r.integers(0, keys.size, 5000)
+    sw[i], sw[j] = keys[j], keys[i]
+    assert run_pair(sw) == ahs.RADIX
 
 
 def test_insertion_state():
