@@ -44,24 +44,31 @@ constexpr int DIGIT_HIST_THREADS = 256;
 constexpr int EXPAND_THREADS = 256;
 constexpr int EXPAND_TILE = EXPAND_THREADS * 4 * 8;   // positions per block
 
-// Onesweep tile shapes: 512 threads (8 waves); 16 keys per thread for 32-bit
-// keys, 8 for 64-bit keys.
-constexpr int OS_THREADS = 512;
+// Onesweep tile shapes: 512 threads (8 waves) per tile, two tiles resident
+// per CU (at most 128 VGPRs and 80 KiB of LDS each).
+#ifndef AHS_OS_THREADS
+#define AHS_OS_THREADS 512
+#endif
+constexpr int OS_THREADS = AHS_OS_THREADS;
 constexpr int OS_WAVES = OS_THREADS / 64;
-// Keys per thread of a onesweep tile (compile-time tunable).  Larger tiles
-// shorten the look-back chain per key; the key-only sizes are the largest
-// that keep two 512-thread workgroups per CU (at most 128 VGPRs): measured
-// on 2^28 u32 / 2^27 u64 passes, 24 and 16 keys per thread beat 16 and 8 by
-// 18 % and 20 %.  Payload variants carry a second array: 16 (u32) and 12
-// (u64) keys per thread measured best (u64: 10 % over 8).
+// Keys per thread of a onesweep tile (compile-time tunable): the largest
+// that keep two tiles per CU.  Larger tiles shorten the look-back chain and
+// lengthen the runs of consecutive addresses the scatter writes (one run
+// per digit and tile: at 48 keys per run a plain run-copy of 2^28 u32 keys
+// reaches 4.0 TB/s, at 96 keys 5.1 TB/s).  Measured on 2^28 u32 / 2^27 u64
+// passes: 32 keys per thread 0.690 ms against 0.744 ms at 24; 18 for u64
+// keys and for u32 keys with payload; 12 for u64 with payload (14 would
+// leave one tile per CU).  One tile per CU (1,024 threads or an 80 KiB+
+// tile) loses the overlap of one tile's memory phases with the other's
+// ranking and is slower at any tile size tried.
 #ifndef AHS_OS_IPT32
-#define AHS_OS_IPT32 24
+#define AHS_OS_IPT32 32
 #endif
 #ifndef AHS_OS_IPT64
-#define AHS_OS_IPT64 16
+#define AHS_OS_IPT64 18
 #endif
 #ifndef AHS_OS_IPT32P
-#define AHS_OS_IPT32P 16
+#define AHS_OS_IPT32P 18
 #endif
 #ifndef AHS_OS_IPT64P
 #define AHS_OS_IPT64P 12

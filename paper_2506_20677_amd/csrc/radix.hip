@@ -13,15 +13,19 @@ __global__ __launch_bounds__(OS_THREADS) void k_onesweep(OnesweepArgs a) {
   using K = typename KeyTraits<KK>::K;
   constexpr int TILE = OS_THREADS * IPT;
   constexpr int NW = OS_WAVES;
-  // The rank slots are only live until every key's local position is in a
-  // register, the key staging only after that, so they share LDS.
+  // One LDS region holds in turn the rank slots, the dense per-(wave,
+  // digit) position table (written once every slot count has been read,
+  // after the scan's first barrier) and the staged keys (once every key's
+  // tile position is in a register).
   constexpr size_t SLOT_BYTES = sizeof(RankSlot) * NW * 256;
   constexpr size_t KEY_BYTES = sizeof(K) * TILE;
+  static_assert(sizeof(uint32_t) * NW * 256 <= SLOT_BYTES, "position table fits over the slots");
   __shared__ __align__(16) unsigned char s_raw[SLOT_BYTES > KEY_BYTES ? SLOT_BYTES : KEY_BYTES];
   RankSlot(*s_slot)[256] = reinterpret_cast<RankSlot(*)[256]>(s_raw);
+  uint32_t(*s_pos)[256] = reinterpret_cast<uint32_t(*)[256]>(s_raw);
   K* s_keys = reinterpret_cast<K*>(s_raw);
   __shared__ uint32_t s_tstart[256];
-  __shared__ uint32_t s_dbase[256];
+  __shared__ uint32_t s_dadj[256];  // global position of the tile's key j with digit d: s_dadj[d] + j
   __shared__ uint32_t s_vals[PAY ? TILE : 1];
   __shared__ uint32_t s_scan[NW + 1];
   __shared__ uint32_t s_tile;
@@ -69,7 +73,16 @@ __global__ __launch_bounds__(OS_THREADS) void k_onesweep(OnesweepArgs a) {
   }
   __syncthreads();
 
-  uint32_t cnt = wave_prefix_per_digit<NW>(s_slot);
+  // per-wave exclusive prefixes of digit t, kept in registers until the
+  // tile's digit starts are known
+  uint32_t cnt = 0, wpre[NW];
+  if (t < 256) {
+#pragma unroll
+    for (int u = 0; u < NW; ++u) {
+      wpre[u] = cnt;
+      cnt += s_slot[u][t].count;
+    }
+  }
   const uint64_t valid64 = a.n - tbase < (uint64_t)TILE ? a.n - tbase : (uint64_t)TILE;
   const uint32_t valid = (uint32_t)valid64;
   if (t == 255) cnt -= (uint32_t)TILE - valid;
@@ -79,14 +92,15 @@ __global__ __launch_bounds__(OS_THREADS) void k_onesweep(OnesweepArgs a) {
   if (t < 256) {
     s_tstart[t] = tstart;
     pred = lookback_begin<256, ST>((ST*)a.status, tile, 0u, (uint32_t)t, cnt);
+    // dense table of tile positions per (wave, digit): one LDS read per key
+    // below instead of two strided ones
+#pragma unroll
+    for (int u = 0; u < NW; ++u) s_pos[u][t] = wpre[u] + tstart;
   }
   __syncthreads();
   // stage keys in digit order while the predecessor's status is in flight
 #pragma unroll
-  for (int i = 0; i < IPT; ++i) {
-    const uint32_t di = digit(k[i]);
-    r[i] += s_tstart[di] + s_slot[w][di].count;
-  }
+  for (int i = 0; i < IPT; ++i) r[i] += s_pos[w][digit(k[i])];
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
@@ -97,19 +111,32 @@ __global__ __launch_bounds__(OS_THREADS) void k_onesweep(OnesweepArgs a) {
   }
   if (t < 256) {
     const uint64_t excl = lookback_end<256, ST>((ST*)a.status, tile, 0u, (uint32_t)t, cnt, pred);
-    s_dbase[t] = doff + (uint32_t)excl;
+    s_dadj[t] = doff + (uint32_t)excl - tstart;  // modulo 2^32; + j lands in [0, n)
   }
   __syncthreads();
 
   K* __restrict__ dst = (K*)a.dst;
-  for (uint32_t j = t; j < valid; j += OS_THREADS) {
-    K x = s_keys[j];
-    const uint32_t dj = digit(x);
-    const uint32_t o = s_dbase[dj] + (j - s_tstart[dj]);
-    if (o >= a.n) continue;  // unreachable with consistent digit counts
+  auto put = [&](uint32_t j, K x, uint32_t o) {
+    if (o >= a.n) return;  // unreachable with consistent digit counts
     if constexpr (KeyTraits<KK>::FLT) x = a.unmap_out ? funmap(x) : x;
     dst[o] = x;
     if constexpr (PAY) a.vdst[o] = s_vals[j];
+  };
+  if (valid == (uint32_t)TILE) {
+    // full tile: all LDS reads first, then the stores
+    K x[IPT];
+    uint32_t o[IPT];
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) x[i] = s_keys[t + i * OS_THREADS];
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) o[i] = s_dadj[digit(x[i])] + (uint32_t)(t + i * OS_THREADS);
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) put((uint32_t)(t + i * OS_THREADS), x[i], o[i]);
+  } else {
+    for (uint32_t j = t; j < valid; j += OS_THREADS) {
+      const K x = s_keys[j];
+      put(j, x, s_dadj[digit(x)] + j);
+    }
   }
 }
 

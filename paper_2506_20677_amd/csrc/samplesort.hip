@@ -260,13 +260,18 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_scatter(SsScatterArgs a) {
   using K = typename KeyTraits<KK>::K;
   constexpr int TILE = SS_THREADS * IPT;
   constexpr int NW = SS_THREADS / WAVE;
+  // One LDS region holds in turn the rank slots, the dense per-(wave,
+  // bucket) position table (written once every slot count has been read,
+  // after the scan's first barrier) and the staged keys (once every key's
+  // tile position is in a register).
   constexpr size_t SLOT_BYTES = sizeof(RankSlot) * NW * SS_NB;
   constexpr size_t KEY_BYTES = sizeof(K) * TILE;
+  static_assert(sizeof(uint32_t) * NW * SS_NB <= SLOT_BYTES, "position table fits over the slots");
   __shared__ __align__(16) unsigned char s_raw[SLOT_BYTES > KEY_BYTES ? SLOT_BYTES : KEY_BYTES];
   RankSlot(*s_slot)[SS_NB] = reinterpret_cast<RankSlot(*)[SS_NB]>(s_raw);
+  uint32_t(*s_pos)[SS_NB] = reinterpret_cast<uint32_t(*)[SS_NB]>(s_raw);
   K* s_keys = reinterpret_cast<K*>(s_raw);
-  __shared__ uint32_t s_tstart[SS_NB];
-  __shared__ uint32_t s_dbase[SS_NB];
+  __shared__ uint32_t s_dadj[SS_NB];  // segment-relative position of tile key j with id b: s_dadj[b] + j
   __shared__ K s_spl[256];
   __shared__ uint32_t s_vals[PAY ? TILE : 1];
   __shared__ uint16_t s_dig[TILE];
@@ -324,16 +329,25 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_scatter(SsScatterArgs a) {
     rank_wave_items<IPT>(d, r, s_slot[w]);
     __syncthreads();
 
-    uint32_t cnt = wave_prefix_per_digit<NW, SS_NB>(s_slot);
+    // per-wave exclusive prefixes of bucket t (one bucket per thread)
+    static_assert(SS_THREADS == SS_NB, "one bucket id per thread");
+    uint32_t cnt = 0, wpre[NW];
+#pragma unroll
+    for (int u = 0; u < NW; ++u) {
+      wpre[u] = cnt;
+      cnt += s_slot[u][t].count;
+    }
     if (t == SS_NB - 1) cnt -= (uint32_t)TILE - valid;  // padding: last id, sorted last
     uint32_t total;
     const uint32_t tstart = block_excl_scan<SS_THREADS>(cnt, s_scan, total);
-    s_tstart[t] = tstart;
+    // dense table of tile positions: one LDS read per key below
+#pragma unroll
+    for (int u = 0; u < NW; ++u) s_pos[u][t] = wpre[u] + tstart;
     const uint64_t excl = lookback<SS_NB, ST>((ST*)a.status, tile, sg.first_tile, (uint32_t)t, cnt);
-    s_dbase[t] = a.offs[(size_t)sidx * SS_NB + t] + (uint32_t)excl;
+    s_dadj[t] = a.offs[(size_t)sidx * SS_NB + t] + (uint32_t)excl - tstart;  // modulo 2^32
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < IPT; ++i) r[i] += s_tstart[d[i]] + s_slot[w][d[i]].count;
+    for (int i = 0; i < IPT; ++i) r[i] += s_pos[w][d[i]];
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
@@ -346,13 +360,28 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_scatter(SsScatterArgs a) {
     __syncthreads();
 
     K* __restrict__ dst = (K*)a.dst;
-    for (uint32_t j = t; j < valid; j += SS_THREADS) {
-      const uint32_t dj = s_dig[j];
-      const uint32_t rel = s_dbase[dj] + (j - s_tstart[dj]);
-      if (rel >= sg.size) continue;  // unreachable with consistent counts
+    auto put = [&](uint32_t j, K x, uint32_t rel) {
+      if (rel >= sg.size) return;  // unreachable with consistent counts
       const uint64_t o = sg.start + rel;
-      dst[o] = s_keys[j];
+      dst[o] = x;
       if constexpr (PAY) a.vdst[o] = s_vals[j];
+    };
+    if (valid == (uint32_t)TILE) {
+      // full tile: all LDS reads first, then the stores
+      K x[IPT];
+      uint32_t rel[IPT];
+#pragma unroll
+      for (int i = 0; i < IPT; ++i) {
+        const uint32_t j = (uint32_t)(t + i * SS_THREADS);
+        x[i] = s_keys[j];
+        rel[i] = s_dig[j];
+      }
+#pragma unroll
+      for (int i = 0; i < IPT; ++i) rel[i] = s_dadj[rel[i]] + (uint32_t)(t + i * SS_THREADS);
+#pragma unroll
+      for (int i = 0; i < IPT; ++i) put((uint32_t)(t + i * SS_THREADS), x[i], rel[i]);
+    } else {
+      for (uint32_t j = t; j < valid; j += SS_THREADS) put(j, s_keys[j], s_dadj[s_dig[j]] + j);
     }
   }
 }
