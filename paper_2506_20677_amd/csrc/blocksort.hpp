@@ -13,8 +13,7 @@ template <typename K, bool PAY, int CAP = SS_CAP, int NT = SS_THREADS>
 struct BlockSortSmem {
   static_assert(NT >= 256 && CAP % NT == 0 && CAP / NT <= 16, "block sort shape");
   static constexpr int cap = CAP, nt = NT, nw = NT / WAVE;
-  RankSlot slot[NT / WAVE][256];
-  uint32_t tstart[256];
+  RankSlot slot[NT / WAVE][256];  // rank slots, then each pass's position table
   K keys[CAP];
   uint32_t vals[PAY ? CAP : 1];
   uint32_t scan[NT / WAVE + 1];
@@ -56,7 +55,6 @@ __device__ __forceinline__ void lds_sort_loaded(BlockSortSmem<K, PAY, CAP, NT>& 
   mn = wave_min(mn);
   mx = wave_max(mx);
   if (lane == 0) { sm.red[0][w] = mn; sm.red[1][w] = mx; }
-  for (int i = t; i < NW * 256; i += NT) (&sm.slot[0][0])[i].mask = 0ull;
   __syncthreads();
   mn = sm.red[0][0];
   mx = sm.red[1][0];
@@ -69,11 +67,16 @@ __device__ __forceinline__ void lds_sort_loaded(BlockSortSmem<K, PAY, CAP, NT>& 
   out_max = mx;
   const int npass = (bitlen64((uint64_t)(mx - mn)) + 7) / 8;
 
+  // items of this wave holding at least one key (wave-uniform): a wave whose
+  // items lie past `size` holds only padding, which sorts last and is never
+  // read back, so those items are neither ranked nor placed
+  const uint32_t wbase = (uint32_t)w * WAVE * IPT;
+  const uint32_t nfill = size > wbase ? (size - wbase + WAVE - 1) / WAVE : 0u;
+  const int nv = nfill < (uint32_t)IPT ? (int)nfill : IPT;
   for (int p = 0; p < npass; ++p) {
     K k[IPT];
     uint32_t v[IPT];
     uint32_t d[IPT];
-    const uint32_t wbase = (uint32_t)w * WAVE * IPT;
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
       const uint32_t idx = wbase + (uint32_t)i * WAVE + lane;
@@ -87,22 +90,42 @@ __device__ __forceinline__ void lds_sort_loaded(BlockSortSmem<K, PAY, CAP, NT>& 
         d[i] = 255u;
       }
     }
-    for (int i = t; i < NW * 256; i += NT) (&sm.slot[0][0])[i].count = 0u;
+    // the previous pass's position table overlays the slots: clear them whole
+    for (int i = t; i < NW * 256; i += NT) {
+      (&sm.slot[0][0])[i].mask = 0ull;
+      (&sm.slot[0][0])[i].count = 0u;
+    }
     __syncthreads();
     uint32_t r[IPT];
-    rank_wave_items<IPT>(d, r, sm.slot[w]);
+    rank_wave_items<IPT>(d, r, sm.slot[w], nv);
     __syncthreads();
-    const uint32_t cnt = wave_prefix_per_digit<NW>(sm.slot);
+    // per-wave exclusive prefixes of digit t in registers; after the scan's
+    // first barrier (every slot count read) a dense per-(wave, digit) table
+    // of tile positions overlays the slots: one LDS read per key
+    uint32_t cnt = 0, wpre[NW];
+    if (t < 256) {
+#pragma unroll
+      for (int u = 0; u < NW; ++u) {
+        wpre[u] = cnt;
+        cnt += sm.slot[u][t].count;
+      }
+    }
     uint32_t total;
     const uint32_t tstart = block_excl_scan<NT>(t < 256 ? cnt : 0u, sm.scan, total);
-    if (t < 256) sm.tstart[t] = tstart;
+    uint32_t(*pos)[256] = reinterpret_cast<uint32_t(*)[256]>(&sm.slot[0][0]);
+    if (t < 256) {
+#pragma unroll
+      for (int u = 0; u < NW; ++u) pos[u][t] = wpre[u] + tstart;
+    }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
-      const uint32_t lp = sm.tstart[d[i]] + sm.slot[w][d[i]].count + r[i];
-      if (lp < (uint32_t)CAP) {
-        sm.keys[lp] = k[i];
-        if constexpr (PAY) sm.vals[lp] = v[i];
+      if (i < nv) {
+        const uint32_t lp = pos[w][d[i]] + r[i];
+        if (lp < (uint32_t)CAP) {
+          sm.keys[lp] = k[i];
+          if constexpr (PAY) sm.vals[lp] = v[i];
+        }
       }
     }
     __syncthreads();

@@ -11,7 +11,9 @@
 //   2. each wave keeps running per-digit counts over its IPT items, so the
 //      rank of a key inside its wave is (earlier items) + (lower lanes);
 //   3. an exclusive scan over waves per digit gives wave prefixes, a scan
-//      over digits gives tile-local digit starts.
+//      over digits gives tile-local digit starts; their sums go into a
+//      dense per-(wave, digit) table of tile positions laid over the slots,
+//      so each key's position costs one LDS read.
 // Key order inside a tile is (wave, item, lane), i.e. increasing index, so
 // the ranks are stable.
 #pragma once
@@ -30,56 +32,43 @@ struct __align__(16) RankSlot {
   uint32_t pad;
 };
 
+// Ranks items [0, nitems) of the wave (nitems wave-uniform; later items
+// are left unranked and must not be used).
 template <int IPT>
 __device__ __forceinline__ void rank_wave_items(const uint32_t (&d)[IPT], uint32_t (&r)[IPT],
-                                                RankSlot* __restrict__ slots /* [ND] of this wave */) {
+                                                RankSlot* __restrict__ slots /* [ND] of this wave */,
+                                                int nitems = IPT) {
   const int lane = lane_id();
   const uint64_t mybit = 1ull << lane;
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
-    const uint32_t di = d[i];
-    const uint32_t d0 = __builtin_amdgcn_readfirstlane(di);
-    if (__ballot(di == d0) == ~0ull) {
-      // the whole wave shares one digit
-      const uint32_t base = slots[d0].count;
-      __builtin_amdgcn_wave_barrier();
-      r[i] = base + (uint32_t)lane;
-      if (lane == WAVE - 1) slots[d0].count = base + WAVE;
-    } else {
-      __hip_atomic_fetch_or(&slots[di].mask, mybit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      __builtin_amdgcn_wave_barrier();
-      const u32x4 sv = *reinterpret_cast<const volatile u32x4*>(&slots[di]);
-      __builtin_amdgcn_wave_barrier();
-      const uint64_t peers = (uint64_t)sv.x | ((uint64_t)sv.y << 32);
-      const uint32_t base = sv.z;
-      const uint32_t lt = mbcnt(peers);
-      const uint32_t cnt = popc64(peers);
-      r[i] = base + lt;
-      if (lt == cnt - 1) {
-        const u32x4 nv = {0u, 0u, base + cnt, 0u};
-        *reinterpret_cast<volatile u32x4*>(&slots[di]) = nv;
+    if (i < nitems) {  // uniform branch; the loop stays unrolled (static register indexing)
+      const uint32_t di = d[i];
+      const uint32_t d0 = __builtin_amdgcn_readfirstlane(di);
+      if (__ballot(di == d0) == ~0ull) {
+        // the whole wave shares one digit
+        const uint32_t base = slots[d0].count;
+        __builtin_amdgcn_wave_barrier();
+        r[i] = base + (uint32_t)lane;
+        if (lane == WAVE - 1) slots[d0].count = base + WAVE;
+      } else {
+        __hip_atomic_fetch_or(&slots[di].mask, mybit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __builtin_amdgcn_wave_barrier();
+        const u32x4 sv = *reinterpret_cast<const volatile u32x4*>(&slots[di]);
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t peers = (uint64_t)sv.x | ((uint64_t)sv.y << 32);
+        const uint32_t base = sv.z;
+        const uint32_t lt = mbcnt(peers);
+        const uint32_t cnt = popc64(peers);
+        r[i] = base + lt;
+        if (lt == cnt - 1) {
+          const u32x4 nv = {0u, 0u, base + cnt, 0u};
+          *reinterpret_cast<volatile u32x4*>(&slots[di]) = nv;
+        }
       }
     }
     __builtin_amdgcn_wave_barrier();
   }
-}
-
-// After rank_wave_items on every wave and a __syncthreads: threads t < ND
-// turn the per-wave counts of digit t into per-wave exclusive prefixes
-// (in place) and return the tile's count of digit t (0 for t >= ND).
-template <int NW, int ND = 256>
-__device__ __forceinline__ uint32_t wave_prefix_per_digit(RankSlot (*slots)[ND]) {
-  const int t = threadIdx.x;
-  uint32_t run = 0;
-  if (t < ND) {
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      const uint32_t c = slots[w][t].count;
-      slots[w][t].count = run;
-      run += c;
-    }
-  }
-  return run;
 }
 
 // Look-back status words.  32-bit words (flag in bits 31..30, value in
