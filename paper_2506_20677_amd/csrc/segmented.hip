@@ -203,7 +203,11 @@ template <int KK>
 __global__ __launch_bounds__(SEG_CH_THREADS) void k_seg_chunk(SegArgs a) {
   using K = typename KeyTraits<KK>::K;
   constexpr int NT = SEG_CH_THREADS, CPT = SEG_CH / NT;
-  __shared__ K s_k[SEG_CH + 2];  // s_k[j + 1] = key at chunk position j; halo keys at both ends
+  // LDS position p (chunk position p - 1; halo keys at both ends) lives at
+  // p + p / 32: each thread walks 32 consecutive positions, and the pad word
+  // per 32 puts the 64 lanes of a wave on distinct banks
+  __shared__ K s_k[SEG_CH + 2 + (SEG_CH + 2) / 32 + 1];
+  auto sk = [&](uint32_t p) -> K& { return s_k[p + (p >> 5)]; };
   __shared__ int s_max[NT / WAVE];
   __shared__ double s_red[NT / WAVE];
   __shared__ uint32_t s_carry;
@@ -226,20 +230,32 @@ __global__ __launch_bounds__(SEG_CH_THREADS) void k_seg_chunk(SegArgs a) {
       if constexpr (KeyTraits<KK>::FLT) x = fmap(x);
       return x;
     };
-    const K kmin = mapped(0);
-    uint32_t shift, nbins;
-    shift_nbins((uint64_t)(mapped(size - 1) - kmin), shift, nbins);
-    auto binof = [&](K x) { return (uint64_t)((x - kmin) >> shift); };
     const uint32_t c0 = (c - g.first_tile) * SEG_CH;
     const uint32_t cnt = size - c0 < SEG_CH ? size - c0 : SEG_CH;
-    for (uint32_t j = t; j < cnt; j += NT) s_k[j + 1] = mapped(c0 + j);
-    if (t == 0) s_k[0] = c0 > 0 ? mapped(c0 - 1) : K(0);
-    if (t == 1) s_k[cnt + 1] = c0 + cnt < size ? mapped(c0 + cnt) : K(0);
+    // every load of the chunk in flight at once: the segment's ends (its
+    // min and max, sorted), the chunk's keys and the halo keys
+    const K kmin = mapped(0), kmax = mapped(size - 1);
+    K v[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const uint32_t j = (uint32_t)t + (uint32_t)q * NT;
+      v[q] = j < cnt ? mapped(c0 + j) : K(0);
+    }
+    if (t == 0) sk(0) = c0 > 0 ? mapped(c0 - 1) : K(0);
+    if (t == 1) sk(cnt + 1) = c0 + cnt < size ? mapped(c0 + cnt) : K(0);
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const uint32_t j = (uint32_t)t + (uint32_t)q * NT;
+      if (j < cnt) sk(j + 1) = v[q];
+    }
+    uint32_t shift, nbins;
+    shift_nbins((uint64_t)(kmax - kmin), shift, nbins);
+    auto binof = [&](K x) { return (uint64_t)((x - kmin) >> shift); };
     __syncthreads();
-    const bool carry_needed = c0 > 0 && binof(s_k[0]) == binof(s_k[1]);
+    const bool carry_needed = c0 > 0 && binof(sk(0)) == binof(sk(1));
     if (carry_needed && t < WAVE) {
       // smallest position p <= c0 with bin(p) == bin(c0)
-      const uint64_t target = binof(s_k[1]);
+      const uint64_t target = binof(sk(1));
       int64_t R = c0;  // bin(R) == target
       int64_t step = 1, L = 0;
       for (;;) {
@@ -265,27 +281,34 @@ __global__ __launch_bounds__(SEG_CH_THREADS) void k_seg_chunk(SegArgs a) {
     }
     __syncthreads();
     const uint32_t carry = carry_needed ? s_carry : c0;
-    // run starts in my positions
+    // bins of my positions j0 - 1 .. j0 + CPT (LDS positions j0 .. j0 + CPT
+    // + 1), read once; a bin is below 65,536, so 32 bits hold it
     const uint32_t j0 = (uint32_t)t * CPT;
+    uint32_t b[CPT + 2];
+#pragma unroll
+    for (int q = 0; q < CPT + 2; ++q) b[q] = j0 + q <= cnt + 1 ? (uint32_t)binof(sk(j0 + q)) : 0u;
+    // run starts in my positions
     int last = -1;
+#pragma unroll
     for (int q = 0; q < CPT; ++q) {
       const uint32_t j = j0 + q;
-      if (j >= cnt) break;
-      const bool st = (c0 + j == 0) || binof(s_k[j]) != binof(s_k[j + 1]);
+      const bool st = j < cnt && ((c0 + j == 0) || b[q] != b[q + 1]);
       if (st) last = (int)j;
     }
     int cur = block_excl_max<NT>(last, s_max);
     const double inv_n = 1.0 / (double)size;
     double acc = 0.0;
+#pragma unroll
     for (int q = 0; q < CPT; ++q) {
       const uint32_t j = j0 + q;
-      if (j >= cnt) break;
-      if ((c0 + j == 0) || binof(s_k[j]) != binof(s_k[j + 1])) cur = (int)j;
-      const bool end = (c0 + j + 1 == size) || binof(s_k[j + 2]) != binof(s_k[j + 1]);
-      if (end) {
-        const uint32_t start = cur >= 0 ? c0 + (uint32_t)cur : carry;
-        const double p = (double)(c0 + j + 1 - start) * inv_n;
-        acc -= p * log2(p);
+      if (j < cnt) {  // a guard, not a loop exit: the loop stays unrolled over registers
+        if ((c0 + j == 0) || b[q] != b[q + 1]) cur = (int)j;
+        const bool end = (c0 + j + 1 == size) || b[q + 2] != b[q + 1];
+        if (end) {
+          const uint32_t start = cur >= 0 ? c0 + (uint32_t)cur : carry;
+          const double p = (double)(c0 + j + 1 - start) * inv_n;
+          acc -= p * log2(p);
+        }
       }
     }
     acc = wave_sum(acc);
