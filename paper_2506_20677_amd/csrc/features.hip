@@ -601,29 +601,46 @@ hipError_t launch_digit_hist(int kk, const void* keys, uint64_t n, uint64_t kmin
   return hipGetLastError();
 }
 
-// One thread per (pass, digit): sums the block partials; then each pass's
-// 256 counts are exclusively scanned by one wave group.
-__global__ __launch_bounds__(256) void k_digit_reduce(const uint32_t* __restrict__ parts, int nblocks, int ndig,
-                                                      uint32_t* __restrict__ counts, uint32_t* __restrict__ offsets,
-                                                      const DevFeatures* __restrict__ plan) {
-  const int p = blockIdx.x, d = threadIdx.x;
+// One workgroup per pass: four groups of 256 threads (one per digit) sum
+// interleaved quarters of the block partials with many loads in flight, the
+// groups are folded in LDS, and the pass's 256 counts are exclusively
+// scanned.
+constexpr int DIGIT_REDUCE_THREADS = 1024;
+__global__ __launch_bounds__(DIGIT_REDUCE_THREADS) void k_digit_reduce(const uint32_t* __restrict__ parts,
+                                                                       int nblocks, int ndig,
+                                                                       uint32_t* __restrict__ counts,
+                                                                       uint32_t* __restrict__ offsets,
+                                                                       const DevFeatures* __restrict__ plan) {
+  constexpr int G = DIGIT_REDUCE_THREADS / 256;
+  const int p = blockIdx.x, t = threadIdx.x, d = t % 256, g = t / 256;
   if (plan) {
     if (plan->reserved & PLAN_SKIP) return;
     ndig = plan_digits(plan->reserved);
   }
-  if (p >= ndig) return;
+  if (p >= ndig) return;  // uniform over the workgroup
   uint32_t c = 0;
-  for (int b = 0; b < nblocks; ++b) c += parts[((size_t)b * ndig + p) * 256 + d];
-  __shared__ uint32_t sm[8];
+#pragma unroll 16
+  for (int b = g; b < nblocks; b += G) c += parts[((size_t)b * ndig + p) * 256 + d];
+  __shared__ uint32_t s_grp[G][256];
+  __shared__ uint32_t s_scan[DIGIT_REDUCE_THREADS / WAVE + 1];
+  s_grp[g][d] = c;
+  __syncthreads();
+  if (t < 256) {
+    c = 0;
+#pragma unroll
+    for (int i = 0; i < G; ++i) c += s_grp[i][d];
+  }
   uint32_t total;
-  const uint32_t ex = block_excl_scan<256>(c, sm, total);
-  counts[p * 256 + d] = c;
-  offsets[p * 256 + d] = ex;
+  const uint32_t ex = block_excl_scan<DIGIT_REDUCE_THREADS>(t < 256 ? c : 0u, s_scan, total);
+  if (t < 256) {
+    counts[p * 256 + d] = c;
+    offsets[p * 256 + d] = ex;
+  }
 }
 
 hipError_t launch_digit_reduce(const uint32_t* digit_partials, int nblocks, int ndig, uint32_t* counts,
                                uint32_t* offsets, hipStream_t s, const DevFeatures* plan) {
-  k_digit_reduce<<<plan ? 8 : ndig, 256, 0, s>>>(digit_partials, nblocks, ndig, counts, offsets, plan);
+  k_digit_reduce<<<plan ? 8 : ndig, DIGIT_REDUCE_THREADS, 0, s>>>(digit_partials, nblocks, ndig, counts, offsets, plan);
   return hipGetLastError();
 }
 
