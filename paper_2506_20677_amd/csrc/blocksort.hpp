@@ -37,8 +37,47 @@ __device__ __forceinline__ void lds_load_mapped(SM& sm, const typename KeyTraits
   __syncthreads();
 }
 
+// Stable rank sort of sm.keys[0, size), size <= NT: thread t holds key t
+// and counts the keys that sort before it, smaller keys and equal keys at
+// lower indices (keys of lower waves: <=; of higher waves: <; of its own
+// wave: by lane).  One pass of size^2 / NT broadcast reads and compares: for
+// small buckets this beats the LSD passes, whose slot clearing, scans and
+// barriers cost about the same at any size.  Ends with a barrier.
+template <typename K, bool PAY, int CAP, int NT>
+__device__ __forceinline__ void lds_rank_sort(BlockSortSmem<K, PAY, CAP, NT>& sm, uint32_t size) {
+  const uint32_t t = threadIdx.x;
+  const uint32_t wlo = t / WAVE * WAVE;
+  K my = ~K(0);
+  uint32_t mv = 0, rank = 0;
+  if (wlo < size) {  // uniform over the wave
+    if (t < size) {
+      my = sm.keys[t];
+      if constexpr (PAY) mv = sm.vals[t];
+    }
+    const uint32_t whi = wlo + WAVE < size ? wlo + WAVE : size;
+#pragma unroll 8
+    for (uint32_t j = 0; j < wlo; ++j) rank += sm.keys[j] <= my ? 1u : 0u;
+    for (uint32_t j = wlo; j < whi; ++j) {
+      const K x = sm.keys[j];
+      rank += (x < my || (x == my && j < t)) ? 1u : 0u;
+    }
+#pragma unroll 8
+    for (uint32_t j = whi; j < size; ++j) rank += sm.keys[j] < my ? 1u : 0u;
+  }
+  __syncthreads();
+  if (t < size) {
+    sm.keys[rank] = my;
+    if constexpr (PAY) sm.vals[rank] = mv;
+  }
+  __syncthreads();
+}
+
+// Largest bucket the block sort ranks in one pass (one key per thread).
+constexpr uint32_t LDS_RANK_SORT_MAX = 512;
+
 // Stable LSD sort of sm.keys[0, size) (mapped keys) by 8-bit digits of
-// (key - min), as many passes as the span needs; payloads move along.
+// (key - min), as many passes as the span needs (a rank sort when the keys
+// fit one per thread); payloads move along.
 // Returns min and max (mapped).  Ends with a barrier.
 template <typename K, bool PAY, int CAP, int NT>
 __device__ __forceinline__ void lds_sort_loaded(BlockSortSmem<K, PAY, CAP, NT>& sm, uint32_t size, K& out_min,
@@ -66,6 +105,10 @@ __device__ __forceinline__ void lds_sort_loaded(BlockSortSmem<K, PAY, CAP, NT>& 
   out_min = mn;
   out_max = mx;
   const int npass = (bitlen64((uint64_t)(mx - mn)) + 7) / 8;
+  if (npass > 0 && size <= (uint32_t)NT && size <= LDS_RANK_SORT_MAX) {
+    lds_rank_sort(sm, size);
+    return;
+  }
 
   // items of this wave holding at least one key (wave-uniform): a wave whose
   // items lie past `size` holds only padding, which sorts last and is never
