@@ -187,9 +187,11 @@ def serving_section(args, ahs, gen, torch, np):
         return pools[kind][off:off + n], (pay_pool[off:off + n] if pay else None)
 
     def served(burst):
-        srv = ahs.Server(hbm_budget_bytes=int(args.serve_budget_gb * 1e9), slots=4, autotune=True)
+        srv = ahs.Server(hbm_budget_bytes=int(args.serve_budget_gb * 1e9), slots=args.serve_slots, autotune=True)
         start = srv.now_ms() + 20.0
-        i, outstanding, done, checked = 0, 0, 0, 0
+        i, outstanding, done = 0, 0, 0
+        held = []  # every 997th result, checked after the replay (its temporaries
+        #            would allocate device memory, which synchronises the device)
         while i < m or outstanding:
             now = srv.now_ms()
             while i < m and (burst or start + reqs[i][0] <= now):
@@ -200,18 +202,22 @@ def serving_section(args, ahs, gen, torch, np):
             for r in srv.poll(wait_ms=0.0 if i < m else 50.0):
                 if r["status"] != ahs.OK:
                     raise RuntimeError(f"request {r['id']} failed with status {r['status']}")
-                if done % 997 == 0 and r["n"] > 1:  # spot check on the device
-                    x = r["keys"]
-                    if x.dtype == torch.uint32:
-                        x = x.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
-                    elif x.dtype == torch.uint64:
-                        x = x.view(torch.int64) ^ (-(2 ** 63))  # unsigned order as signed
-                    assert bool((x[1:] >= x[:-1]).all().item()), "unsorted result"
-                    checked += 1
-                srv.release(r["id"])
+                if done % 997 == 0 and r["n"] > 1:
+                    held.append(r)
+                else:
+                    srv.release(r["id"])
                 outstanding -= 1
                 done += 1
         st = srv.stats()
+        for r in held:  # spot check on the device
+            x = r["keys"]
+            if x.dtype == torch.uint32:
+                x = x.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+            elif x.dtype == torch.uint64:
+                x = x.view(torch.int64) ^ (-(2 ** 63))  # unsigned order as signed
+            assert bool((x[1:] >= x[:-1]).all().item()), "unsorted result"
+            srv.release(r["id"])
+        checked = len(held)
         srv.close()
         return {"p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3), "max_ms": round(st["max_ms"], 3),
                 "gkeys_s": round(st["gkeys_per_s"], 3), "batches": st["batches"],
@@ -243,7 +249,7 @@ def serving_section(args, ahs, gen, torch, np):
 
     res = {"workload": f"Poisson arrivals 2000/s for {args.serve_seconds}s ({m} requests, {total_keys} keys), "
                        "sizes log-uniform on [2^10, 2^24], u32/u64/f32 (uniform or Zipf(1.0) over 4,096 values; "
-                       f"f32 Normal), half with payload; budget {args.serve_budget_gb} GB, 4 slots",
+                       f"f32 Normal), half with payload; budget {args.serve_budget_gb} GB, {args.serve_slots} slots",
            "offered_gkeys_s": round(total_keys / args.serve_seconds / 1e9, 3)}
     modes = args.serve_modes.split(",")
     for mode, burst in (("realtime", False), ("burst", True)):
@@ -287,6 +293,7 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="seconds of the Poisson request trace replayed in real time")
     ap.add_argument("--serve-budget-gb", type=float, default=48.0)
+    ap.add_argument("--serve-slots", type=int, default=4, help="stream slots of the server")
     ap.add_argument("--serve-modes", default="served,plain", help="which serving runs: served, plain or both")
     return ap.parse_args()
 

@@ -3,8 +3,9 @@
 // its HBM budget, admits a batch only when its buffers fit, groups pending
 // requests of one key class into a batch (continuous batching: a batch is
 // formed whenever a stream slot is free, from whatever is pending), sorts
-// each batch with the enqueue-only segmented sort on the slot's stream, and
-// reports per-request completion with event-timed latency.  Several slots
+// each batch with the enqueue-only segmented sort on the slot's stream (a
+// lone large request with the single-array AUTO path), and reports
+// per-request completion with event-timed latency.  Several slots
 // keep batches overlapping on the device.  The caller drives progress from
 // one host thread (submit / poll / release).
 #include <chrono>
@@ -102,6 +103,12 @@ struct ahs_server {
 
 namespace {
 
+// A batch of one request above this many keys is sorted by the single-array
+// AUTO path (features, host decision, then the strategy's kernels), straight
+// from the caller's buffer: alone in a batch, a large request gains nothing
+// from the batched sort, whose large segments always take the sample sort.
+constexpr uint64_t SERVE_SINGLE_MIN = 8192;
+
 ahs_status launch_batch(ahs_server* S, int si, const BatchPlan& plan, uint64_t arena_off, const BatchMem& m) {
   ahs_context* ctx = S->ctx;
   Slot& sl = S->slots[si];
@@ -116,6 +123,37 @@ ahs_status launch_batch(ahs_server* S, int si, const BatchPlan& plan, uint64_t a
   char* b = S->base + arena_off;
   const uint32_t nseg = (uint32_t)plan.ids.size();
   const uint64_t kb = (uint64_t)key_bytes(plan.dtype);
+  char* h_chosen = sl.pinned + S->pinned_bytes - a256(S->cfg.max_batch_requests) - 256;
+  char* h_status = sl.pinned + S->pinned_bytes - 256;
+  if (nseg == 1) {
+    Request& r = S->core.reqs.at(plan.ids[0]);
+    if (r.n > SERVE_SINGLE_MIN &&
+        ahs_workspace_bytes(r.n, (ahs_dtype)plan.dtype, plan.pay, AHS_AUTO) <= m.ws_bytes) {
+      if (r.ready && ctx->check(hipStreamWaitEvent(sl.s, (hipEvent_t)r.ready, 0), "wait input") != AHS_OK)
+        return AHS_E_DEVICE;
+      ahs_strategy chosen = AHS_AUTO;
+      // blocks for the feature read only; the sort itself stays enqueued
+      const ahs_status st = ahs_sort(ctx, r.kin, b + m.kout, plan.pay ? r.vin : nullptr,
+                                     plan.pay ? reinterpret_cast<uint32_t*>(b + m.vout) : nullptr, r.n,
+                                     (ahs_dtype)plan.dtype, AHS_AUTO, &S->cfg.cfg, b + m.ws, m.ws_bytes, sl.s,
+                                     &chosen, nullptr);
+      if (st == AHS_OK) {
+        h_chosen[0] = (char)chosen;
+        const uint32_t ok = 0;
+        memcpy(h_status, &ok, 4);
+        if (!B.done && ctx->check(hipEventCreate(&B.done), "event") != AHS_OK) return AHS_E_DEVICE;
+        if (ctx->check(hipEventRecord(B.done, sl.s), "record") != AHS_OK) return AHS_E_DEVICE;
+        sl.batch = bid;
+        S->batches_run += 1;
+        S->requests_batched += 1;
+        S->peak_used = std::max(S->peak_used, S->arena.used());
+        return AHS_OK;
+      }
+      // NaN keys (refused by the single-array path before writing anything)
+      // take the batched path below, which reports them per segment
+      if (st != AHS_E_NAN) return st;
+    }
+  }
   // host staging: offsets and copy descriptors
   uint64_t* h_offs = reinterpret_cast<uint64_t*>(sl.pinned);
   CopyDesc* h_desc = reinterpret_cast<CopyDesc*>(sl.pinned + a256(8 * ((uint64_t)S->cfg.max_batch_requests + 1)));
@@ -151,8 +189,6 @@ ahs_status launch_batch(ahs_server* S, int si, const BatchPlan& plan, uint64_t a
       plan.keys, plan.max_n, (ahs_dtype)plan.dtype, AHS_AUTO, &S->cfg.cfg, b + m.ws, m.ws_bytes, sl.s,
       reinterpret_cast<uint8_t*>(b + m.chosen), nullptr, reinterpret_cast<uint32_t*>(b + m.status));
   if (st != AHS_OK) return st;
-  char* h_chosen = sl.pinned + S->pinned_bytes - a256(S->cfg.max_batch_requests) - 256;
-  char* h_status = sl.pinned + S->pinned_bytes - 256;
   if (ctx->check(hipMemcpyAsync(h_chosen, b + m.chosen, nseg, hipMemcpyDeviceToHost, sl.s), "copy") != AHS_OK ||
       ctx->check(hipMemcpyAsync(h_status, b + m.status, 4, hipMemcpyDeviceToHost, sl.s), "copy") != AHS_OK)
     return AHS_E_DEVICE;
@@ -280,9 +316,12 @@ extern "C" ahs_status ahs_server_create(int device, const ahs_server_config* cfg
       return fail(AHS_E_OOM);
     }
   }
+  // the two clock origins are taken together: the GPU's (an event that has
+  // completed) and the host's right after it
   if (hipEventCreate(&S->t0_ev) != hipSuccess) return fail(AHS_E_DEVICE);
   if (hipEventRecord(S->t0_ev, S->slots[0].s) != hipSuccess || hipEventSynchronize(S->t0_ev) != hipSuccess)
     return fail(AHS_E_DEVICE);
+  S->t0_host = std::chrono::steady_clock::now();
   if (c.autotune) {
     for (int dt = 0; dt < 4; ++dt)
       for (int pay = 0; pay < 2; ++pay) {
@@ -290,7 +329,6 @@ extern "C" ahs_status ahs_server_create(int device, const ahs_server_config* cfg
         if (st != AHS_OK) return fail(st);
       }
   }
-  S->t0_host = std::chrono::steady_clock::now();
   *out = S;
   return AHS_OK;
 }

@@ -365,6 +365,26 @@ def test_quick_wide_and_duplicates(kind, n):
     run_pair(keys, None, ahs.QUICK)
 
 
+@pytest.mark.parametrize("kind", ["u32", "u64", "f32"])
+@pytest.mark.parametrize("n", [30_011, 120_007, 260_003])
+def test_quick_buckets_with_repeated_keys(kind, n):
+    """Each value 2-4 times, so equal keys fall inside block-sort buckets of
+    about n/256 keys (one-pass rank sort up to 512 keys, LSD passes above)
+    rather than into equality buckets: the payload pins their input order."""
+    r = np.random.default_rng(n + 3 * len(kind))
+    if kind == "u32":
+        vals_ = r.integers(0, 2**32, n // 3, dtype=np.uint64).astype(np.uint32)
+    elif kind == "u64":
+        vals_ = r.integers(0, 2**64, n // 3, dtype=np.uint64)
+    else:
+        vals_ = r.normal(0, 1e3, n // 3).astype(np.float32)
+        vals_[::7] = -0.0
+        vals_[::11] = 0.0
+    keys = vals_[r.integers(0, vals_.size, n)]
+    run_pair(keys, np.arange(n, dtype=np.uint32), ahs.QUICK)
+    run_pair(keys, None, ahs.QUICK)
+
+
 def test_quick_patterns():
     n = 400_000
     base = gen.strategy_sweep("uniform32", n=n)

@@ -181,3 +181,50 @@ def test_server_requests_arrive_while_others_run():
         s.release(rid)
     assert s.stats()["completed"] == len(ids)
     s.close()
+
+
+def test_server_lone_large_request_with_nan_matches_batched_sort():
+    """A lone large request is sorted by the single-array path, which refuses
+    NaN keys; such a request falls back to the batched sort and is reported
+    like a batched segment (status OK, decision code SEG_NAN, keys in bit-map
+    order), identical to ahs_sort_segmented of it alone."""
+    r = np.random.default_rng(66)
+    keys = r.normal(0, 1e3, 20_000).astype(np.float32)
+    keys[::997] = np.nan
+    keys[5] = -np.nan
+    vals = np.arange(keys.size, dtype=np.uint32)
+    k, v = to_dev(keys), to_dev(vals)
+    torch.cuda.synchronize()
+    s = ahs.Server(hbm_budget_bytes=1 << 30, slots=2)
+    rid = s.submit(k, v)
+    res = drain(s, 1)[rid]
+    assert res["status"] == ahs.OK and res["chosen"] == ahs.SEG_NAN
+    offs = torch.tensor([0, keys.size], dtype=torch.int64, device=DEV)
+    ko, vo, ch, _ = ahs.ahs_sort_segmented(k, offs, v)
+    torch.cuda.synchronize()
+    assert np.array_equal(host_bits(res["keys"]), host_bits(ko))
+    assert np.array_equal(host_bits(res["values"]), host_bits(vo))
+    assert int(ch[0].item()) == ahs.SEG_NAN
+    s.release(rid)
+    s.close()
+
+
+def test_server_latency_is_bounded_by_wall_time():
+    """The reported latency (completion on the GPU clock - arrival on the
+    server clock) never exceeds the wall time from submit to the end of the
+    drain: the two clocks share their origin even when the server autotunes
+    at creation (regression: the host origin was taken after autotuning)."""
+    import time
+    s = ahs.Server(hbm_budget_bytes=1 << 30, slots=2, autotune=True)
+    k = to_dev(gen.u32(67, 0, 50_000))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rid = s.submit(k)
+    res = drain(s, 1)[rid]
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    assert res["status"] == ahs.OK
+    st = s.stats()
+    say(st["max_ms"], wall_ms)
+    assert 0 < st["max_ms"] <= wall_ms + 2.0
+    s.release(rid)
+    s.close()
