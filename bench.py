@@ -127,6 +127,16 @@ def batched_section(args, ahs, gen, torch, np):
     same_chosen = bool(torch.equal(g.chosen, chosen_b))
     del g
     torch.cuda.empty_cache()
+    if not args.seg_loop:
+        res = {"workload": f"{args.seg_count} uint32 segments, sizes log-uniform on [16, 2^20] (seed 8), {n} keys",
+               "keys": n, "autotuned_caps": caps, "graph_ms": round(graph_s * 1e3, 3),
+               "graph_gkeys_s": round(n / graph_s / 1e9, 3), "blocking_ms": round(blocking_s * 1e3, 3),
+               "blocking_gkeys_s": round(n / blocking_s / 1e9, 3), "graph_status": status,
+               "identical_outputs": same_graph, "decisions_equal_graph_blocking": same_chosen}
+        log(f"[bench] batched {json.dumps(res)}")
+        del keys, offs, out_b
+        torch.cuda.empty_cache()
+        return res
     # host loop of plain per-array calls
     out_l = torch.empty_like(keys)
     ws = ctx.workspace(ahs.ahs_workspace_bytes(int(sizes.max()), ahs.U32, False, ahs.AUTO))
@@ -289,6 +299,8 @@ def parse():
     ap.add_argument("--batched", action=argparse.BooleanOptionalAction, default=True)
     ap.add_argument("--seg-count", type=int, default=65536, help="segments in the batched workload")
     ap.add_argument("--seg-reps", type=int, default=3, help="timed graph replays of the batched sort")
+    ap.add_argument("--seg-loop", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the host loop of per-array calls over the same segments")
     ap.add_argument("--serve", action=argparse.BooleanOptionalAction, default=True)
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="seconds of the Poisson request trace replayed in real time")
