@@ -44,7 +44,12 @@
 extern "C" {
 #endif
 
-typedef enum { AHS_U32 = 0, AHS_U64 = 1, AHS_F32 = 2, AHS_F64 = 3 } ahs_dtype;
+/* Key types.  Floating keys are ordered by their IEEE bit pattern mapped
+ * order-preservingly onto unsigned integers (-0.0 before +0.0, infinities at
+ * the ends, NaN refused by the single-array calls); signed keys by flipping
+ * the sign bit, the GPU counterpart of the two-bucket signed radix of
+ * Listing 7.  Features (min_key, max_key) are reported in the mapped domain. */
+typedef enum { AHS_U32 = 0, AHS_U64 = 1, AHS_F32 = 2, AHS_F64 = 3, AHS_I32 = 4, AHS_I64 = 5 } ahs_dtype;
 
 /* AHS_INSERTION is only reported: it is the n <= n_small state of the FSM
  * (Sec. III-A, Listing 1); it cannot be requested. */

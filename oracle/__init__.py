@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-U32, U64, F32, F64 = 0, 1, 2, 3
+U32, U64, F32, F64, I32, I64 = 0, 1, 2, 3, 4, 5
 AUTO, COUNTING, RADIX, QUICK, INSERTION = 0, 1, 2, 3, 4
 STRATEGY_NAMES = {AUTO: "auto", COUNTING: "counting", RADIX: "radix",
                   QUICK: "quick", INSERTION: "insertion"}
@@ -26,7 +26,8 @@ OK, E_INVALID_ARG, E_UNSUPPORTED, E_NAN, E_OOM, E_NO_MODEL, E_DEPTH, E_PARSE = (
     0, -1, -2, -3, -5, -7, -8, -9)
 
 _DTYPES = {np.dtype(np.uint32): U32, np.dtype(np.uint64): U64,
-           np.dtype(np.float32): F32, np.dtype(np.float64): F64}
+           np.dtype(np.float32): F32, np.dtype(np.float64): F64,
+           np.dtype(np.int32): I32, np.dtype(np.int64): I64}
 
 
 class Features(C.Structure):

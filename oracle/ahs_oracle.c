@@ -48,13 +48,24 @@ static int nan64(uint64_t b) {
          (b & 0x000FFFFFFFFFFFFFull) != 0ull;
 }
 
+/* Signed keys (the paper's negative-number handling, Listing 7, splits them */
+/* into two buckets): as unsigned keys they are v - INT_MIN, computed with    */
+/* wrap-around, which is order-preserving.                                    */
 int ref_map_keys(int dtype, const void* keys, uint64_t n, uint64_t* mapped,
                  uint64_t* nan_count) {
   uint64_t i, nans = 0;
-  if (dtype < REF_U32 || dtype > REF_F64) return REF_E_INVALID_ARG;
+  if (dtype < REF_U32 || dtype > REF_I64) return REF_E_INVALID_ARG;
   if (n && (!keys || !mapped)) return REF_E_INVALID_ARG;
   for (i = 0; i < n; i++) {
-    if (dtype == REF_U32) {
+    if (dtype == REF_I32) {
+      int32_t v;
+      memcpy(&v, (const char*)keys + 4 * i, 4);
+      mapped[i] = (uint64_t)((int64_t)v - (int64_t)INT32_MIN);
+    } else if (dtype == REF_I64) {
+      int64_t v;
+      memcpy(&v, (const char*)keys + 8 * i, 8);
+      mapped[i] = (uint64_t)v - (uint64_t)INT64_MIN;
+    } else if (dtype == REF_U32) {
       mapped[i] = ((const uint32_t*)keys)[i];
     } else if (dtype == REF_U64) {
       mapped[i] = ((const uint64_t*)keys)[i];
@@ -76,10 +87,16 @@ int ref_map_keys(int dtype, const void* keys, uint64_t n, uint64_t* mapped,
 
 int ref_unmap_keys(int dtype, const uint64_t* mapped, uint64_t n, void* keys) {
   uint64_t i;
-  if (dtype < REF_U32 || dtype > REF_F64) return REF_E_INVALID_ARG;
+  if (dtype < REF_U32 || dtype > REF_I64) return REF_E_INVALID_ARG;
   for (i = 0; i < n; i++) {
     uint64_t m = mapped[i];
-    if (dtype == REF_U32) {
+    if (dtype == REF_I32) {
+      const int32_t v = (int32_t)((int64_t)m + (int64_t)INT32_MIN);
+      memcpy((char*)keys + 4 * i, &v, 4);
+    } else if (dtype == REF_I64) {
+      const uint64_t u = m + (uint64_t)INT64_MIN;
+      memcpy((char*)keys + 8 * i, &u, 8);
+    } else if (dtype == REF_U32) {
       ((uint32_t*)keys)[i] = (uint32_t)m;
     } else if (dtype == REF_U64) {
       ((uint64_t*)keys)[i] = m;
@@ -148,7 +165,7 @@ int ref_features_compute(int dtype, const void* keys, uint64_t n,
   int st;
   if (!out) return REF_E_INVALID_ARG;
   memset(out, 0, sizeof *out);
-  if (dtype < REF_U32 || dtype > REF_F64) return REF_E_INVALID_ARG;
+  if (dtype < REF_U32 || dtype > REF_I64) return REF_E_INVALID_ARG;
   out->n = n;
   if (n == 0) return REF_OK;
   if (!keys) return REF_E_INVALID_ARG;
@@ -462,7 +479,7 @@ int ref_sort(int dtype, const void* keys_in, void* keys_out,
   memset(&f, 0, sizeof f);
   if (chosen) *chosen = REF_AUTO;
   if (feats) memset(feats, 0, sizeof *feats);
-  if (dtype < REF_U32 || dtype > REF_F64 || !cfg) return REF_E_INVALID_ARG;
+  if (dtype < REF_U32 || dtype > REF_I64 || !cfg) return REF_E_INVALID_ARG;
   if (requested < REF_AUTO || requested > REF_INSERTION) return REF_E_INVALID_ARG;
   if ((vals_in == NULL) != (vals_out == NULL)) return REF_E_INVALID_ARG;
   if (n && (!keys_in || !keys_out)) return REF_E_INVALID_ARG;

@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-enum { REF_U32 = 0, REF_U64 = 1, REF_F32 = 2, REF_F64 = 3 };
+enum { REF_U32 = 0, REF_U64 = 1, REF_F32 = 2, REF_F64 = 3, REF_I32 = 4, REF_I64 = 5 };
 
 enum {
   REF_AUTO = 0,

@@ -22,7 +22,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libahs.so")
 
-U32, U64, F32, F64 = 0, 1, 2, 3
+U32, U64, F32, F64, I32, I64 = 0, 1, 2, 3, 4, 5
 AUTO, COUNTING, RADIX, QUICK, INSERTION = 0, 1, 2, 3, 4
 STRATEGY_NAMES = {AUTO: "auto", COUNTING: "counting", RADIX: "radix", QUICK: "quick", INSERTION: "insertion"}
 STRATEGY_CODES = {v: k for k, v in STRATEGY_NAMES.items()}
@@ -30,9 +30,11 @@ OK, E_INVALID_ARG, E_UNSUPPORTED, E_NAN, E_WORKSPACE, E_OOM, E_DEVICE, E_NO_MODE
     0, -1, -2, -3, -4, -5, -6, -7, -9)
 PRESET_GPU, PRESET_PAPER_TEXT, PRESET_PAPER_TABLE2 = 0, 1, 2
 
-_TORCH_DTYPES = {torch.uint32: U32, torch.int32: U32, torch.uint64: U64, torch.int64: U64,
+# signed tensors sort as signed numbers (sign-bit map); pass dtype=U32 / U64
+# explicitly to order a signed tensor's raw bits as unsigned
+_TORCH_DTYPES = {torch.uint32: U32, torch.int32: I32, torch.uint64: U64, torch.int64: I64,
                  torch.float32: F32, torch.float64: F64}
-_KEY_BYTES = {U32: 4, U64: 8, F32: 4, F64: 8}
+_KEY_BYTES = {U32: 4, U64: 8, F32: 4, F64: 8, I32: 4, I64: 8}
 
 
 class AhsError(RuntimeError):
@@ -588,7 +590,8 @@ class Server:
         self.close()
 
 
-_KEY_TORCH = {U32: torch.int32, U64: torch.int64, F32: torch.float32, F64: torch.float64}
+_KEY_TORCH = {U32: torch.int32, U64: torch.int64, F32: torch.float32, F64: torch.float64, I32: torch.int32,
+              I64: torch.int64}
 
 
 class _DevBuf:

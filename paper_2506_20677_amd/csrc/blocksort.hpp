@@ -30,7 +30,7 @@ __device__ __forceinline__ void lds_load_mapped(SM& sm, const typename KeyTraits
   using K = typename KeyTraits<KK>::K;
   for (uint32_t j = threadIdx.x; j < size; j += SM::nt) {
     K x = src[j];
-    if constexpr (KeyTraits<KK>::FLT) x = raw ? fmap(x) : x;
+    if constexpr (key_mapped<KK>) x = raw ? map_key<KK>(x) : x;
     sm.keys[j] = x;
     if constexpr (PAY) sm.vals[j] = vsrc[j];
   }

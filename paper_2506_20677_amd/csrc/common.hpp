@@ -15,11 +15,18 @@ constexpr int WAVE = 64;
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
+// K: the unsigned word a key is handled as.  FLT: IEEE keys (NaN possible,
+// sign-magnitude bit map).  SGN: two's-complement keys (sign-bit flip).
+// MAPPED: the stored bits are mapped on the first read and unmapped on the
+// last write.
 template <int KK> struct KeyTraits;
-template <> struct KeyTraits<KK_U32> { using K = uint32_t; static constexpr bool FLT = false; };
-template <> struct KeyTraits<KK_U64> { using K = uint64_t; static constexpr bool FLT = false; };
-template <> struct KeyTraits<KK_F32> { using K = uint32_t; static constexpr bool FLT = true; };
-template <> struct KeyTraits<KK_F64> { using K = uint64_t; static constexpr bool FLT = true; };
+template <> struct KeyTraits<KK_U32> { using K = uint32_t; static constexpr bool FLT = false, SGN = false; };
+template <> struct KeyTraits<KK_U64> { using K = uint64_t; static constexpr bool FLT = false, SGN = false; };
+template <> struct KeyTraits<KK_F32> { using K = uint32_t; static constexpr bool FLT = true, SGN = false; };
+template <> struct KeyTraits<KK_F64> { using K = uint64_t; static constexpr bool FLT = true, SGN = false; };
+template <> struct KeyTraits<KK_I32> { using K = uint32_t; static constexpr bool FLT = false, SGN = true; };
+template <> struct KeyTraits<KK_I64> { using K = uint64_t; static constexpr bool FLT = false, SGN = true; };
+template <int KK> constexpr bool key_mapped = KeyTraits<KK>::FLT || KeyTraits<KK>::SGN;
 
 // Order-preserving map of IEEE bit patterns onto unsigned integers: a set
 // sign bit flips every bit, a clear one sets the sign bit.
@@ -40,13 +47,24 @@ __device__ __forceinline__ bool fnan(uint64_t b) {
   return (b & 0x7FFFFFFFFFFFFFFFull) > 0x7FF0000000000000ull;
 }
 
+// Order-preserving map of two's-complement keys onto unsigned integers (and
+// its inverse): flip the sign bit.
+template <typename K>
+__device__ __forceinline__ K smap(K b) {
+  return b ^ (K(1) << (8 * sizeof(K) - 1));
+}
+
 template <int KK>
 __device__ __forceinline__ typename KeyTraits<KK>::K map_key(typename KeyTraits<KK>::K b) {
-  if constexpr (KeyTraits<KK>::FLT) return fmap(b); else return b;
+  if constexpr (KeyTraits<KK>::FLT) return fmap(b);
+  else if constexpr (KeyTraits<KK>::SGN) return smap(b);
+  else return b;
 }
 template <int KK>
 __device__ __forceinline__ typename KeyTraits<KK>::K unmap_key(typename KeyTraits<KK>::K m) {
-  if constexpr (KeyTraits<KK>::FLT) return funmap(m); else return m;
+  if constexpr (KeyTraits<KK>::FLT) return funmap(m);
+  else if constexpr (KeyTraits<KK>::SGN) return smap(m);
+  else return m;
 }
 
 // ------------------------------------------------------------------ lanes

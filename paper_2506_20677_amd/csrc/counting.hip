@@ -109,7 +109,9 @@ hipError_t launch_expand(int kk, const uint32_t* offsets, uint32_t nbins, uint64
     case KK_U32: return expand_kk<KK_U32>(offsets, nbins, kmin, out, n, s);
     case KK_U64: return expand_kk<KK_U64>(offsets, nbins, kmin, out, n, s);
     case KK_F32: return expand_kk<KK_F32>(offsets, nbins, kmin, out, n, s);
+    case KK_I32: return expand_kk<KK_I32>(offsets, nbins, kmin, out, n, s);
     case KK_F64: return expand_kk<KK_F64>(offsets, nbins, kmin, out, n, s);
+    case KK_I64: return expand_kk<KK_I64>(offsets, nbins, kmin, out, n, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -164,7 +166,9 @@ hipError_t launch_small_sort(int kk, const void* src, void* dst, const uint32_t*
     case KK_U32: return small_kk<KK_U32>(src, dst, vsrc, vdst, n, s);
     case KK_U64: return small_kk<KK_U64>(src, dst, vsrc, vdst, n, s);
     case KK_F32: return small_kk<KK_F32>(src, dst, vsrc, vdst, n, s);
+    case KK_I32: return small_kk<KK_I32>(src, dst, vsrc, vdst, n, s);
     case KK_F64: return small_kk<KK_F64>(src, dst, vsrc, vdst, n, s);
+    case KK_I64: return small_kk<KK_I64>(src, dst, vsrc, vdst, n, s);
     default: return hipErrorInvalidValue;
   }
 }

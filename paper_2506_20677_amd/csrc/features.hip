@@ -248,7 +248,9 @@ hipError_t launch_minmax(int kk, const void* keys, uint64_t n, MinMaxPartial* pa
     case KK_U32: k_minmax<KK_U32><<<nblocks, MINMAX_THREADS, 0, s>>>((const uint32_t*)keys, n, partials); break;
     case KK_U64: k_minmax<KK_U64><<<nblocks, MINMAX_THREADS, 0, s>>>((const uint64_t*)keys, n, partials); break;
     case KK_F32: k_minmax<KK_F32><<<nblocks, MINMAX_THREADS, 0, s>>>((const uint32_t*)keys, n, partials); break;
+    case KK_I32: k_minmax<KK_I32><<<nblocks, MINMAX_THREADS, 0, s>>>((const uint32_t*)keys, n, partials); break;
     case KK_F64: k_minmax<KK_F64><<<nblocks, MINMAX_THREADS, 0, s>>>((const uint64_t*)keys, n, partials); break;
+    case KK_I64: k_minmax<KK_I64><<<nblocks, MINMAX_THREADS, 0, s>>>((const uint64_t*)keys, n, partials); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
@@ -298,7 +300,9 @@ hipError_t launch_hist_small(int kk, const void* keys, uint64_t n, uint64_t kmin
     case KK_U32: k_hist_small<KK_U32><<<nblocks, HIST_SMALL_THREADS, 0, s>>>((const uint32_t*)keys, n, (uint32_t)kmin, shift, nbins, partials, plan); break;
     case KK_U64: k_hist_small<KK_U64><<<nblocks, HIST_SMALL_THREADS, 0, s>>>((const uint64_t*)keys, n, kmin, shift, nbins, partials, plan); break;
     case KK_F32: k_hist_small<KK_F32><<<nblocks, HIST_SMALL_THREADS, 0, s>>>((const uint32_t*)keys, n, (uint32_t)kmin, shift, nbins, partials, plan); break;
+    case KK_I32: k_hist_small<KK_I32><<<nblocks, HIST_SMALL_THREADS, 0, s>>>((const uint32_t*)keys, n, (uint32_t)kmin, shift, nbins, partials, plan); break;
     case KK_F64: k_hist_small<KK_F64><<<nblocks, HIST_SMALL_THREADS, 0, s>>>((const uint64_t*)keys, n, kmin, shift, nbins, partials, plan); break;
+    case KK_I64: k_hist_small<KK_I64><<<nblocks, HIST_SMALL_THREADS, 0, s>>>((const uint64_t*)keys, n, kmin, shift, nbins, partials, plan); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -431,7 +435,9 @@ hipError_t launch_hist_large(int kk, const void* keys, uint64_t n, uint64_t kmin
     case KK_U32: return hist_large_kk<KK_U32>(keys, n, kmin, shift, partials, corr, nblocks, ndig, digit_partials, s, plan);
     case KK_U64: return hist_large_kk<KK_U64>(keys, n, kmin, shift, partials, corr, nblocks, ndig, digit_partials, s, plan);
     case KK_F32: return hist_large_kk<KK_F32>(keys, n, kmin, shift, partials, corr, nblocks, ndig, digit_partials, s, plan);
+    case KK_I32: return hist_large_kk<KK_I32>(keys, n, kmin, shift, partials, corr, nblocks, ndig, digit_partials, s, plan);
     case KK_F64: return hist_large_kk<KK_F64>(keys, n, kmin, shift, partials, corr, nblocks, ndig, digit_partials, s, plan);
+    case KK_I64: return hist_large_kk<KK_I64>(keys, n, kmin, shift, partials, corr, nblocks, ndig, digit_partials, s, plan);
     default: return hipErrorInvalidValue;
   }
 }
@@ -595,7 +601,9 @@ hipError_t launch_digit_hist(int kk, const void* keys, uint64_t n, uint64_t kmin
     case KK_U32: k_digit_hist<KK_U32><<<nblocks, DIGIT_HIST_THREADS, 0, s>>>((const uint32_t*)keys, n, (uint32_t)kmin, ndig, digit_partials); break;
     case KK_U64: k_digit_hist<KK_U64><<<nblocks, DIGIT_HIST_THREADS, 0, s>>>((const uint64_t*)keys, n, kmin, ndig, digit_partials); break;
     case KK_F32: k_digit_hist<KK_F32><<<nblocks, DIGIT_HIST_THREADS, 0, s>>>((const uint32_t*)keys, n, (uint32_t)kmin, ndig, digit_partials); break;
+    case KK_I32: k_digit_hist<KK_I32><<<nblocks, DIGIT_HIST_THREADS, 0, s>>>((const uint32_t*)keys, n, (uint32_t)kmin, ndig, digit_partials); break;
     case KK_F64: k_digit_hist<KK_F64><<<nblocks, DIGIT_HIST_THREADS, 0, s>>>((const uint64_t*)keys, n, kmin, ndig, digit_partials); break;
+    case KK_I64: k_digit_hist<KK_I64><<<nblocks, DIGIT_HIST_THREADS, 0, s>>>((const uint64_t*)keys, n, kmin, ndig, digit_partials); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

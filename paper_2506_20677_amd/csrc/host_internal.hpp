@@ -42,10 +42,10 @@ struct ahs_context {
 
   // Batched sort: LDS kernel variant (0..3, capacity 1024 << v) per key
   // type, payload flag and size class; set by the autotuner.
-  int seg_variant[4][2][4] = {{{0, 1, 2, 3}, {0, 1, 2, 3}},
-                              {{0, 1, 2, 3}, {0, 1, 2, 3}},
-                              {{0, 1, 2, 3}, {0, 1, 2, 3}},
-                              {{0, 1, 2, 3}, {0, 1, 2, 3}}};
+  int seg_variant[ahs::NUM_KEY_KINDS][2][4] = {{{0, 1, 2, 3}, {0, 1, 2, 3}}, {{0, 1, 2, 3}, {0, 1, 2, 3}},
+                                          {{0, 1, 2, 3}, {0, 1, 2, 3}}, {{0, 1, 2, 3}, {0, 1, 2, 3}},
+                                          {{0, 1, 2, 3}, {0, 1, 2, 3}}, {{0, 1, 2, 3}, {0, 1, 2, 3}}};
+  static_assert(ahs::NUM_KEY_KINDS == 6, "one row of defaults per key kind");
 
   ~ahs_context();
   ahs_status fail(ahs_status s, const char* fmt, ...);

@@ -10,8 +10,9 @@
 namespace ahs {
 
 // Key kinds: the dtype enum of the ABI, as template parameters.
-enum KeyKind : int { KK_U32 = 0, KK_U64 = 1, KK_F32 = 2, KK_F64 = 3 };
-inline int key_bytes_of(int kk) { return (kk == KK_U64 || kk == KK_F64) ? 8 : 4; }
+enum KeyKind : int { KK_U32 = 0, KK_U64 = 1, KK_F32 = 2, KK_F64 = 3, KK_I32 = 4, KK_I64 = 5 };
+constexpr int NUM_KEY_KINDS = 6;  // tables indexed by the key kind have this many rows
+inline int key_bytes_of(int kk) { return (kk == KK_U64 || kk == KK_F64 || kk == KK_I64) ? 8 : 4; }
 
 // Bit length of a 64-bit value (0 for 0).
 __host__ __device__ __forceinline__ int bitlen64(uint64_t x) { return x ? 64 - __builtin_clzll(x) : 0; }

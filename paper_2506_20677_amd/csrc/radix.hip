@@ -60,7 +60,7 @@ __global__ __launch_bounds__(OS_THREADS) void k_onesweep(OnesweepArgs a) {
   const bool full = tbase + TILE <= a.n;
 #pragma unroll
   for (int i = 0; i < IPT; ++i) {
-    if constexpr (KeyTraits<KK>::FLT) k[i] = a.map_in ? fmap(k[i]) : k[i];
+    if constexpr (key_mapped<KK>) k[i] = a.map_in ? map_key<KK>(k[i]) : k[i];
     if (!full && wbase + (uint64_t)i * WAVE + lane >= a.n) k[i] = kmin + (K)(255ull << shift);
   }
 
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(OS_THREADS) void k_onesweep(OnesweepArgs a) {
   K* __restrict__ dst = (K*)a.dst;
   auto put = [&](uint32_t j, K x, uint32_t o) {
     if (o >= a.n) return;  // unreachable with consistent digit counts
-    if constexpr (KeyTraits<KK>::FLT) x = a.unmap_out ? funmap(x) : x;
+    if constexpr (key_mapped<KK>) x = a.unmap_out ? unmap_key<KK>(x) : x;
     dst[o] = x;
     if constexpr (PAY) a.vdst[o] = s_vals[j];
   };
@@ -161,9 +161,13 @@ hipError_t launch_onesweep(int kk, int with_vals, const OnesweepArgs& a, hipStre
     case KK_U64 * 2: return onesweep_kk<KK_U64, false>(a, s);
     case KK_U64 * 2 + 1: return onesweep_kk<KK_U64, true>(a, s);
     case KK_F32 * 2: return onesweep_kk<KK_F32, false>(a, s);
+    case KK_I32 * 2: return onesweep_kk<KK_I32, false>(a, s);
     case KK_F32 * 2 + 1: return onesweep_kk<KK_F32, true>(a, s);
+    case KK_I32 * 2 + 1: return onesweep_kk<KK_I32, true>(a, s);
     case KK_F64 * 2: return onesweep_kk<KK_F64, false>(a, s);
+    case KK_I64 * 2: return onesweep_kk<KK_I64, false>(a, s);
     case KK_F64 * 2 + 1: return onesweep_kk<KK_F64, true>(a, s);
+    case KK_I64 * 2 + 1: return onesweep_kk<KK_I64, true>(a, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -70,7 +70,7 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_sample(const typename KeyTrai
       const uint64_t h = ss_mix(base + (uint64_t)(j + 1) * 0x9E3779B97F4A7C15ull);
       const uint64_t pos = sg.start + (((h >> 32) * (uint64_t)sg.size) >> 32);
       K x = src[pos];
-      if constexpr (KeyTraits<KK>::FLT) x = map_in ? fmap(x) : x;
+      if constexpr (key_mapped<KK>) x = map_in ? map_key<KK>(x) : x;
       s[j] = x;
     }
     __syncthreads();
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_count(const typename KeyTrait
       for (int i = 0; i < IPT; ++i) {
         const uint32_t idx = b0 + (uint32_t)i * SS_THREADS + t;
         K y = x[i];
-        if constexpr (KeyTraits<KK>::FLT) y = map_in ? fmap(y) : y;
+        if constexpr (key_mapped<KK>) y = map_in ? map_key<KK>(y) : y;
         if (idx < cnt) atomicAdd(&s_cnt[ss_classify<K>(y, s_spl)], 1u);
       }
     }
@@ -315,7 +315,7 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_scatter(SsScatterArgs a) {
     for (int i = 0; i < IPT; ++i) {
       const uint32_t idx = wbase + (uint32_t)i * WAVE + lane;
       K x = k[i];
-      if constexpr (KeyTraits<KK>::FLT) x = a.map_in ? fmap(x) : x;
+      if constexpr (key_mapped<KK>) x = a.map_in ? map_key<KK>(x) : x;
       if (idx < valid) {
         k[i] = x;
         d[i] = ss_classify<K>(x, s_spl);
@@ -405,7 +405,7 @@ __device__ __forceinline__ void ss_block_item(const SsBlockArgs& a, BlockSortSme
   if (it.flags & SS_ITEM_COPY) {
     for (uint32_t j = t; j < size; j += SS_THREADS) {
       K x = src[base + j];
-      if constexpr (KeyTraits<KK>::FLT) x = raw ? x : funmap(x);
+      if constexpr (key_mapped<KK>) x = raw ? x : unmap_key<KK>(x);
       dst[base + j] = x;
       if constexpr (PAY) a.vout[base + j] = vsrc[base + j];
     }
@@ -416,7 +416,7 @@ __device__ __forceinline__ void ss_block_item(const SsBlockArgs& a, BlockSortSme
   lds_sort_loaded(sm, size, mn, mx);
   for (uint32_t j = t; j < size; j += SS_THREADS) {
     K x = sm.keys[j];
-    if constexpr (KeyTraits<KK>::FLT) x = funmap(x);
+    if constexpr (key_mapped<KK>) x = unmap_key<KK>(x);
     dst[base + j] = x;
     if constexpr (PAY) a.vout[base + j] = sm.vals[j];
   }
@@ -454,7 +454,9 @@ hipError_t launch_ss_sample(int kk, const void* src, int map_in, const SsSeg* se
     case KK_U32: k_ss_sample<KK_U32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, lv, (uint32_t*)spl, counts, seed); break;
     case KK_U64: k_ss_sample<KK_U64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, lv, (uint64_t*)spl, counts, seed); break;
     case KK_F32: k_ss_sample<KK_F32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, lv, (uint32_t*)spl, counts, seed); break;
+    case KK_I32: k_ss_sample<KK_I32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, lv, (uint32_t*)spl, counts, seed); break;
     case KK_F64: k_ss_sample<KK_F64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, lv, (uint64_t*)spl, counts, seed); break;
+    case KK_I64: k_ss_sample<KK_I64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, lv, (uint64_t*)spl, counts, seed); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -473,12 +475,14 @@ hipError_t launch_ss_zero_status(void* status, const SsLevelIn& lv, uint32_t wor
 hipError_t launch_ss_count(int kk, const void* src, int map_in, const SsSeg* segs, const SsLevelIn& lv,
                            const void* spl, uint32_t* counts, int nblocks, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
-  const uint32_t tk = (uint32_t)ss_tile(kk == KK_U32 || kk == KK_F32 ? 4 : 8);
+  const uint32_t tk = (uint32_t)ss_tile(key_bytes_of(kk));
   switch (kk) {
     case KK_U32: k_ss_count<KK_U32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, lv, tk, (const uint32_t*)spl, counts); break;
     case KK_U64: k_ss_count<KK_U64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, lv, tk, (const uint64_t*)spl, counts); break;
     case KK_F32: k_ss_count<KK_F32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, lv, tk, (const uint32_t*)spl, counts); break;
+    case KK_I32: k_ss_count<KK_I32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, lv, tk, (const uint32_t*)spl, counts); break;
     case KK_F64: k_ss_count<KK_F64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, lv, tk, (const uint64_t*)spl, counts); break;
+    case KK_I64: k_ss_count<KK_I64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, lv, tk, (const uint64_t*)spl, counts); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -523,9 +527,13 @@ static hipError_t scatter_any(int kk, int with_vals, const SsScatterArgs& a, uin
     case KK_U64 * 2: return scatter_kk<KK_U64, false, PERSIST>(a, grid, s);
     case KK_U64 * 2 + 1: return scatter_kk<KK_U64, true, PERSIST>(a, grid, s);
     case KK_F32 * 2: return scatter_kk<KK_F32, false, PERSIST>(a, grid, s);
+    case KK_I32 * 2: return scatter_kk<KK_I32, false, PERSIST>(a, grid, s);
     case KK_F32 * 2 + 1: return scatter_kk<KK_F32, true, PERSIST>(a, grid, s);
+    case KK_I32 * 2 + 1: return scatter_kk<KK_I32, true, PERSIST>(a, grid, s);
     case KK_F64 * 2: return scatter_kk<KK_F64, false, PERSIST>(a, grid, s);
+    case KK_I64 * 2: return scatter_kk<KK_I64, false, PERSIST>(a, grid, s);
     case KK_F64 * 2 + 1: return scatter_kk<KK_F64, true, PERSIST>(a, grid, s);
+    case KK_I64 * 2 + 1: return scatter_kk<KK_I64, true, PERSIST>(a, grid, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -549,9 +557,13 @@ static hipError_t block_any(int kk, int with_vals, const SsBlockArgs& a, uint32_
     case KK_U64 * 2: k_ss_block<KK_U64, false, PERSIST><<<grid, SS_THREADS, 0, s>>>(a); break;
     case KK_U64 * 2 + 1: k_ss_block<KK_U64, true, PERSIST><<<grid, SS_THREADS, 0, s>>>(a); break;
     case KK_F32 * 2: k_ss_block<KK_F32, false, PERSIST><<<grid, SS_THREADS, 0, s>>>(a); break;
+    case KK_I32 * 2: k_ss_block<KK_I32, false, PERSIST><<<grid, SS_THREADS, 0, s>>>(a); break;
     case KK_F32 * 2 + 1: k_ss_block<KK_F32, true, PERSIST><<<grid, SS_THREADS, 0, s>>>(a); break;
+    case KK_I32 * 2 + 1: k_ss_block<KK_I32, true, PERSIST><<<grid, SS_THREADS, 0, s>>>(a); break;
     case KK_F64 * 2: k_ss_block<KK_F64, false, PERSIST><<<grid, SS_THREADS, 0, s>>>(a); break;
+    case KK_I64 * 2: k_ss_block<KK_I64, false, PERSIST><<<grid, SS_THREADS, 0, s>>>(a); break;
     case KK_F64 * 2 + 1: k_ss_block<KK_F64, true, PERSIST><<<grid, SS_THREADS, 0, s>>>(a); break;
+    case KK_I64 * 2 + 1: k_ss_block<KK_I64, true, PERSIST><<<grid, SS_THREADS, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -587,8 +599,12 @@ uint32_t ss_scatter_resident(int kk, int with_vals, uint64_t max_seg, uint32_t c
     case KK_U64 * 2: fn = s32 ? scatter_fn<KK_U64, false, uint32_t>() : scatter_fn<KK_U64, false, uint64_t>(); break;
     case KK_U64 * 2 + 1: fn = s32 ? scatter_fn<KK_U64, true, uint32_t>() : scatter_fn<KK_U64, true, uint64_t>(); break;
     case KK_F32 * 2: fn = s32 ? scatter_fn<KK_F32, false, uint32_t>() : scatter_fn<KK_F32, false, uint64_t>(); break;
+    case KK_I32 * 2: fn = s32 ? scatter_fn<KK_I32, false, uint32_t>() : scatter_fn<KK_I32, false, uint64_t>(); break;
     case KK_F32 * 2 + 1: fn = s32 ? scatter_fn<KK_F32, true, uint32_t>() : scatter_fn<KK_F32, true, uint64_t>(); break;
+    case KK_I32 * 2 + 1: fn = s32 ? scatter_fn<KK_I32, true, uint32_t>() : scatter_fn<KK_I32, true, uint64_t>(); break;
     case KK_F64 * 2: fn = s32 ? scatter_fn<KK_F64, false, uint32_t>() : scatter_fn<KK_F64, false, uint64_t>(); break;
+    case KK_I64 * 2: fn = s32 ? scatter_fn<KK_I64, false, uint32_t>() : scatter_fn<KK_I64, false, uint64_t>(); break;
+    case KK_I64 * 2 + 1: fn = s32 ? scatter_fn<KK_I64, true, uint32_t>() : scatter_fn<KK_I64, true, uint64_t>(); break;
     default: fn = s32 ? scatter_fn<KK_F64, true, uint32_t>() : scatter_fn<KK_F64, true, uint64_t>(); break;
   }
   return resident(fn, SS_THREADS, cu_count);
@@ -602,8 +618,12 @@ uint32_t ss_block_resident(int kk, int with_vals, uint32_t cu_count) {
     case KK_U64 * 2: fn = reinterpret_cast<const void*>(&k_ss_block<KK_U64, false, true>); break;
     case KK_U64 * 2 + 1: fn = reinterpret_cast<const void*>(&k_ss_block<KK_U64, true, true>); break;
     case KK_F32 * 2: fn = reinterpret_cast<const void*>(&k_ss_block<KK_F32, false, true>); break;
+    case KK_I32 * 2: fn = reinterpret_cast<const void*>(&k_ss_block<KK_I32, false, true>); break;
     case KK_F32 * 2 + 1: fn = reinterpret_cast<const void*>(&k_ss_block<KK_F32, true, true>); break;
+    case KK_I32 * 2 + 1: fn = reinterpret_cast<const void*>(&k_ss_block<KK_I32, true, true>); break;
     case KK_F64 * 2: fn = reinterpret_cast<const void*>(&k_ss_block<KK_F64, false, true>); break;
+    case KK_I64 * 2: fn = reinterpret_cast<const void*>(&k_ss_block<KK_I64, false, true>); break;
+    case KK_I64 * 2 + 1: fn = reinterpret_cast<const void*>(&k_ss_block<KK_I64, true, true>); break;
     default: fn = reinterpret_cast<const void*>(&k_ss_block<KK_F64, true, true>); break;
   }
   return resident(fn, SS_THREADS, cu_count);

@@ -90,11 +90,11 @@ struct LevelPlan {
 };
 
 ahs_status launch_level(SortJob& j, const SsLayout& S, const SsTables& T, const LevelPlan& P, uint64_t max_seg) {
-  const bool flt = j.kk == KK_F32 || j.kk == KK_F64;
+  const bool mapped = j.kk == KK_F32 || j.kk == KK_F64 || j.kk == KK_I32 || j.kk == KK_I64;
   const int pay = j.vin != nullptr;
   const void* bufs[3] = {j.kin, j.kout, at<void>(j.ws, j.L.tmpk)};
   const uint32_t* vbufs[3] = {j.vin, j.vout, j.vin ? at<uint32_t>(j.ws, j.L.tmpv) : nullptr};
-  const int map_in = (flt && P.src_buf == SS_BUF_IN) ? 1 : 0;
+  const int map_in = (mapped && P.src_buf == SS_BUF_IN) ? 1 : 0;
   const uint32_t sw = (uint32_t)status_word_bytes(max_seg);
   {
     ProfScope p(j.ctx, "ss_sample", j.s);
@@ -108,7 +108,7 @@ ahs_status launch_level(SortJob& j, const SsLayout& S, const SsTables& T, const 
     SS_HIP(launch_ss_count(j.kk, bufs[P.src_buf], map_in, T.segs[P.cur], P.lv, T.spl, T.counts, P.count_grid, j.s),
            "count");
   }
-  SS_HIP(launch_ss_plan(T.segs[P.cur], P.lv, T.counts, T.offs, P.dst_buf, flt ? 1 : 0, T.segs[P.cur ^ 1], T.items,
+  SS_HIP(launch_ss_plan(T.segs[P.cur], P.lv, T.counts, T.offs, P.dst_buf, mapped ? 1 : 0, T.segs[P.cur ^ 1], T.items,
                         T.ctr + P.level, (uint32_t)S.item_cap, (uint32_t)S.seg_cap, P.plan_grid, j.s),
          "plan");
   SsScatterArgs sa;

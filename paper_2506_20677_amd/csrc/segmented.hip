@@ -98,7 +98,7 @@ __global__ __launch_bounds__(NT) void k_seg_small(SegArgs a, int cls) {
     if (size > 0) lds_sort_loaded(sm, size, mn, mx);
     for (uint32_t j = t; j < size; j += NT) {
       K x = sm.keys[j];
-      if constexpr (KeyTraits<KK>::FLT) x = funmap(x);
+      if constexpr (key_mapped<KK>) x = unmap_key<KK>(x);
       kout[j] = x;
       if constexpr (PAY) a.vout[base + j] = sm.vals[j];
     }
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(SEG_CH_THREADS) void k_seg_chunk(SegArgs a) {
     const K* __restrict__ keys = (const K*)a.kout + g.start;
     auto mapped = [&](uint32_t j) {
       K x = keys[j];
-      if constexpr (KeyTraits<KK>::FLT) x = fmap(x);
+      if constexpr (key_mapped<KK>) x = map_key<KK>(x);
       return x;
     };
     const uint32_t c0 = (c - g.first_tile) * SEG_CH;
@@ -353,9 +353,9 @@ __global__ __launch_bounds__(256) void k_seg_large_final(SegArgs a) {
     } else {
       const K* __restrict__ keys = (const K*)a.kout + g.start;
       K mn = keys[0], mx = keys[g.size - 1];
-      if constexpr (KeyTraits<KK>::FLT) {
-        mn = fmap(mn);
-        mx = fmap(mx);
+      if constexpr (key_mapped<KK>) {
+        mn = map_key<KK>(mn);
+        mx = map_key<KK>(mx);
       }
       f.min_key = mn;
       f.max_key = mx;
@@ -390,9 +390,9 @@ __global__ __launch_bounds__(256) void k_tune_fill(typename KeyTraits<KK>::K* __
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     z ^= z >> 31;
-    if constexpr (KK == KK_U32) {
+    if constexpr (KK == KK_U32 || KK == KK_I32) {
       keys[i] = (uint32_t)(z >> 32);
-    } else if constexpr (KK == KK_U64) {
+    } else if constexpr (KK == KK_U64 || KK == KK_I64) {
       keys[i] = z;
     } else if constexpr (KK == KK_F32) {
       const float x = (float)(z >> 40) * (1.0f / 16777216.0f) * 2000.0f - 1000.0f;
@@ -450,9 +450,13 @@ hipError_t launch_seg_small(int kk, int with_vals, const SegArgs& a, int cls, in
     case KK_U64 * 2: return small_kk<KK_U64, false>(a, cls, variant, nblocks, s);
     case KK_U64 * 2 + 1: return small_kk<KK_U64, true>(a, cls, variant, nblocks, s);
     case KK_F32 * 2: return small_kk<KK_F32, false>(a, cls, variant, nblocks, s);
+    case KK_I32 * 2: return small_kk<KK_I32, false>(a, cls, variant, nblocks, s);
     case KK_F32 * 2 + 1: return small_kk<KK_F32, true>(a, cls, variant, nblocks, s);
+    case KK_I32 * 2 + 1: return small_kk<KK_I32, true>(a, cls, variant, nblocks, s);
     case KK_F64 * 2: return small_kk<KK_F64, false>(a, cls, variant, nblocks, s);
+    case KK_I64 * 2: return small_kk<KK_I64, false>(a, cls, variant, nblocks, s);
     case KK_F64 * 2 + 1: return small_kk<KK_F64, true>(a, cls, variant, nblocks, s);
+    case KK_I64 * 2 + 1: return small_kk<KK_I64, true>(a, cls, variant, nblocks, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -465,8 +469,12 @@ uint32_t seg_small_resident(int kk, int with_vals, int variant, uint32_t cu_coun
     case KK_U64 * 2: fn = small_fn<KK_U64, false>(variant); break;
     case KK_U64 * 2 + 1: fn = small_fn<KK_U64, true>(variant); break;
     case KK_F32 * 2: fn = small_fn<KK_F32, false>(variant); break;
+    case KK_I32 * 2: fn = small_fn<KK_I32, false>(variant); break;
     case KK_F32 * 2 + 1: fn = small_fn<KK_F32, true>(variant); break;
+    case KK_I32 * 2 + 1: fn = small_fn<KK_I32, true>(variant); break;
     case KK_F64 * 2: fn = small_fn<KK_F64, false>(variant); break;
+    case KK_I64 * 2: fn = small_fn<KK_I64, false>(variant); break;
+    case KK_I64 * 2 + 1: fn = small_fn<KK_I64, true>(variant); break;
     default: fn = small_fn<KK_F64, true>(variant); break;
   }
   int per_cu = 0;
@@ -503,6 +511,16 @@ hipError_t launch_seg_large(int kk, const SegArgs& a, uint32_t bound_blocks, uin
       k_seg_chunk<KK_F64><<<chunk_blocks, SEG_CH_THREADS, 0, s>>>(a);
       k_seg_large_final<KK_F64><<<final_blocks, 256, 0, s>>>(a);
       break;
+    case KK_I32:
+      k_seg_bounds<KK_I32><<<bound_blocks, 64, 0, s>>>(a);
+      k_seg_chunk<KK_I32><<<chunk_blocks, SEG_CH_THREADS, 0, s>>>(a);
+      k_seg_large_final<KK_I32><<<final_blocks, 256, 0, s>>>(a);
+      break;
+    case KK_I64:
+      k_seg_bounds<KK_I64><<<bound_blocks, 64, 0, s>>>(a);
+      k_seg_chunk<KK_I64><<<chunk_blocks, SEG_CH_THREADS, 0, s>>>(a);
+      k_seg_large_final<KK_I64><<<final_blocks, 256, 0, s>>>(a);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -512,6 +530,8 @@ uint32_t seg_chunk_resident(int kk, uint32_t cu_count) {
   const void* fn = kk == KK_U32 ? reinterpret_cast<const void*>(&k_seg_chunk<KK_U32>)
                  : kk == KK_U64 ? reinterpret_cast<const void*>(&k_seg_chunk<KK_U64>)
                  : kk == KK_F32 ? reinterpret_cast<const void*>(&k_seg_chunk<KK_F32>)
+                 : kk == KK_I32 ? reinterpret_cast<const void*>(&k_seg_chunk<KK_I32>)
+                 : kk == KK_I64 ? reinterpret_cast<const void*>(&k_seg_chunk<KK_I64>)
                                 : reinterpret_cast<const void*>(&k_seg_chunk<KK_F64>);
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, SEG_CH_THREADS, 0) != hipSuccess || per_cu < 1)
@@ -533,7 +553,9 @@ hipError_t launch_tune_fill(int kk, void* keys, uint64_t n, uint64_t seed, hipSt
     case KK_U32: k_tune_fill<KK_U32><<<grid, 256, 0, s>>>((uint32_t*)keys, n, seed); break;
     case KK_U64: k_tune_fill<KK_U64><<<grid, 256, 0, s>>>((uint64_t*)keys, n, seed); break;
     case KK_F32: k_tune_fill<KK_F32><<<grid, 256, 0, s>>>((uint32_t*)keys, n, seed); break;
+    case KK_I32: k_tune_fill<KK_I32><<<grid, 256, 0, s>>>((uint32_t*)keys, n, seed); break;
     case KK_F64: k_tune_fill<KK_F64><<<grid, 256, 0, s>>>((uint64_t*)keys, n, seed); break;
+    case KK_I64: k_tune_fill<KK_I64><<<grid, 256, 0, s>>>((uint64_t*)keys, n, seed); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -38,7 +38,7 @@ SegLayout seg_layout(size_t base, uint64_t n_total, uint32_t nseg) {
   return L;
 }
 
-int key_bytes_of(ahs_dtype d) { return (d == AHS_U32 || d == AHS_F32) ? 4 : 8; }
+int key_bytes_of(ahs_dtype d) { return (d == AHS_U32 || d == AHS_F32 || d == AHS_I32) ? 4 : 8; }
 
 // One batched call: arguments checked, tables placed, SegArgs filled.
 struct SegCall {
@@ -59,7 +59,7 @@ ahs_status seg_setup(SegCall& C, ahs_context* ctx, const void* d_keys_in, void* 
                      ahs_dtype dtype, ahs_strategy requested, const ahs_config* cfg, void* d_ws, size_t ws_bytes,
                      void* stream, uint8_t* d_chosen, ahs_feature_vector* d_feats) {
   if (!ctx) return AHS_E_INVALID_ARG;
-  if ((int)dtype < 0 || (int)dtype > 3) return ctx->fail(AHS_E_INVALID_ARG, "bad dtype");
+  if ((int)dtype < 0 || (int)dtype > (int)AHS_I64) return ctx->fail(AHS_E_INVALID_ARG, "bad dtype");
   if ((int)requested < AHS_AUTO || (int)requested > AHS_QUICK)
     return ctx->fail(AHS_E_INVALID_ARG, "strategy %d cannot be requested", (int)requested);
   if ((d_vals_in == nullptr) != (d_vals_out == nullptr))
@@ -190,7 +190,7 @@ ahs_status seg_enqueue_async(SegCall& C, uint64_t n_total, uint64_t max_seg_hint
 using namespace ahs;
 
 extern "C" size_t ahs_segmented_workspace_bytes(uint64_t n_total, uint32_t nseg, ahs_dtype dtype, int with_payload) {
-  if ((int)dtype < 0 || (int)dtype > 3) return 0;
+  if ((int)dtype < 0 || (int)dtype > (int)AHS_I64) return 0;
   const Layout L = plan_layout(n_total, key_bytes_of(dtype), with_payload ? 1 : 0, true);
   return seg_layout(L.total, n_total, nseg).total;
 }
@@ -315,7 +315,7 @@ extern "C" void ahs_graph_destroy(ahs_graph* g) {
 }
 
 extern "C" ahs_status ahs_segmented_get_variants(ahs_context* ctx, ahs_dtype dtype, int with_payload, int* h_caps) {
-  if (!ctx || !h_caps || (int)dtype < 0 || (int)dtype > 3) return AHS_E_INVALID_ARG;
+  if (!ctx || !h_caps || (int)dtype < 0 || (int)dtype > (int)AHS_I64) return AHS_E_INVALID_ARG;
   for (int c = 0; c < SEG_NCLASS; ++c)
     h_caps[c] = (int)SEG_CLASS_CAP[ctx->seg_variant[dtype][with_payload ? 1 : 0][c]];
   return AHS_OK;
@@ -323,7 +323,7 @@ extern "C" ahs_status ahs_segmented_get_variants(ahs_context* ctx, ahs_dtype dty
 
 extern "C" ahs_status ahs_segmented_set_variants(ahs_context* ctx, ahs_dtype dtype, int with_payload,
                                                  const int* h_caps) {
-  if (!ctx || !h_caps || (int)dtype < 0 || (int)dtype > 3) return AHS_E_INVALID_ARG;
+  if (!ctx || !h_caps || (int)dtype < 0 || (int)dtype > (int)AHS_I64) return AHS_E_INVALID_ARG;
   int v[SEG_NCLASS];
   for (int c = 0; c < SEG_NCLASS; ++c) {
     v[c] = -1;
@@ -337,7 +337,7 @@ extern "C" ahs_status ahs_segmented_set_variants(ahs_context* ctx, ahs_dtype dty
 
 extern "C" ahs_status ahs_segmented_autotune(ahs_context* ctx, ahs_dtype dtype, int with_payload, void* stream,
                                              int* h_caps, double* h_ms) {
-  if (!ctx || (int)dtype < 0 || (int)dtype > 3) return AHS_E_INVALID_ARG;
+  if (!ctx || (int)dtype < 0 || (int)dtype > (int)AHS_I64) return AHS_E_INVALID_ARG;
   const int kb = key_bytes_of(dtype);
   const int pay = with_payload ? 1 : 0;
   hipStream_t s = (hipStream_t)stream;

@@ -21,7 +21,7 @@ using namespace ahs;
 
 namespace {
 
-int key_bytes(int dtype) { return (dtype == AHS_U32 || dtype == AHS_F32) ? 4 : 8; }
+int key_bytes(int dtype) { return (dtype == AHS_U32 || dtype == AHS_F32 || dtype == AHS_I32) ? 4 : 8; }
 uint64_t a256(uint64_t x) { return (x + 255) / 256 * 256; }
 
 struct BatchMem {
@@ -323,7 +323,7 @@ extern "C" ahs_status ahs_server_create(int device, const ahs_server_config* cfg
     return fail(AHS_E_DEVICE);
   S->t0_host = std::chrono::steady_clock::now();
   if (c.autotune) {
-    for (int dt = 0; dt < 4; ++dt)
+    for (int dt = 0; dt < NUM_KEY_KINDS; ++dt)
       for (int pay = 0; pay < 2; ++pay) {
         st = ahs_segmented_autotune(S->ctx, (ahs_dtype)dt, pay, S->slots[0].s, nullptr, nullptr);
         if (st != AHS_OK) return fail(st);
@@ -339,7 +339,7 @@ extern "C" ahs_status ahs_server_submit(ahs_server* S, ahs_dtype dtype, uint64_t
                                         const uint32_t* d_vals, void* src_stream, double arrival_ms,
                                         uint64_t* out_id) {
   if (!S || !out_id) return AHS_E_INVALID_ARG;
-  if ((int)dtype < 0 || (int)dtype > 3) return S->ctx->fail(AHS_E_INVALID_ARG, "bad dtype");
+  if ((int)dtype < 0 || (int)dtype > (int)AHS_I64) return S->ctx->fail(AHS_E_INVALID_ARG, "bad dtype");
   if (n >= (1ull << 32)) return S->ctx->fail(AHS_E_UNSUPPORTED, "requests hold fewer than 2^32 keys");
   if (n && !d_keys) return S->ctx->fail(AHS_E_INVALID_ARG, "null key pointer");
   if ((reinterpret_cast<uintptr_t>(d_keys) | reinterpret_cast<uintptr_t>(d_vals)) & 3u)

@@ -11,7 +11,7 @@
 
 namespace ahs {
 
-static int key_bytes_of(ahs_dtype d) { return (d == AHS_U32 || d == AHS_F32) ? 4 : 8; }
+static int key_bytes_of(ahs_dtype d) { return (d == AHS_U32 || d == AHS_F32 || d == AHS_I32) ? 4 : 8; }
 
 static bool partial_overlap(const void* a, const void* b, size_t bytes) {
   if (a == b || bytes == 0) return false;
@@ -216,7 +216,7 @@ static ahs_status run_radix(SortJob& j, const std::vector<uint32_t>* ready_count
   const uint64_t status_words32 = tiles * 256 * status_word_bytes(j.n) / 4;
   uint32_t* counters = at<uint32_t>(j.ws, j.L.counters);
   AHS_HIP(j, launch_fill_u32(counters, 64, 0u, j.s), "fill");
-  const bool flt = j.kk == KK_F32 || j.kk == KK_F64;
+  const bool mapped = j.kk == KK_F32 || j.kk == KK_F64 || j.kk == KK_I32 || j.kk == KK_I64;
   for (int q = 0; q < m; ++q) {
     const bool to_out = ((m - 1 - q) % 2) == 0;
     void* dst = to_out ? j.kout : tmpk;
@@ -229,8 +229,8 @@ static ahs_status run_radix(SortJob& j, const std::vector<uint32_t>* ready_count
     a.n = j.n;
     a.kmin = j.f.min_key;
     a.digit_shift = 8u * (uint32_t)passes[q];
-    a.map_in = (flt && q == 0) ? 1u : 0u;
-    a.unmap_out = (flt && q == m - 1) ? 1u : 0u;
+    a.map_in = (mapped && q == 0) ? 1u : 0u;
+    a.unmap_out = (mapped && q == m - 1) ? 1u : 0u;
     a.digit_offsets = at<uint32_t>(j.ws, j.L.doffs) + 256 * passes[q];
     a.status = status;
     a.tile_counter = counters + q;
@@ -274,14 +274,14 @@ static ahs_status run_small(SortJob& j) {
 using namespace ahs;
 
 extern "C" size_t ahs_workspace_bytes(uint64_t n, ahs_dtype dtype, int with_payload, ahs_strategy strategy) {
-  if ((int)dtype < 0 || (int)dtype > 3) return 0;
+  if ((int)dtype < 0 || (int)dtype > (int)AHS_I64) return 0;
   const bool ss = strategy == AHS_AUTO || strategy == AHS_QUICK;
   return plan_layout(n, key_bytes_of(dtype), with_payload ? 1 : 0, ss).total;
 }
 
 static ahs_status common_checks(ahs_context* ctx, uint64_t n, ahs_dtype dtype) {
   if (!ctx) return AHS_E_INVALID_ARG;
-  if ((int)dtype < 0 || (int)dtype > 3) return ctx->fail(AHS_E_INVALID_ARG, "bad dtype %d", (int)dtype);
+  if ((int)dtype < 0 || (int)dtype > (int)AHS_I64) return ctx->fail(AHS_E_INVALID_ARG, "bad dtype %d", (int)dtype);
   if (n >= (1ull << 32)) return ctx->fail(AHS_E_UNSUPPORTED, "n must be below 2^32");
   return AHS_OK;
 }

@@ -480,3 +480,81 @@ def test_radix_counting_large(case):
     assert np.array_equal(ko.cpu().numpy(), rk)
     ko, _, chosen, _ = ahs.ahs_sort(to_dev(keys), None, ahs.AUTO)
     assert np.array_equal(ko.cpu().numpy(), rk)
+
+
+# ------------------------------------------------------------------ signed keys
+def _signed(kind, n, seed):
+    """Signed keys of one family, with both ends of the type, -1 and 0 planted."""
+    r = np.random.default_rng(seed)
+    dt = np.int32 if kind.startswith("i32") else np.int64
+    info = np.iinfo(dt)
+    if kind.endswith("uniform"):
+        keys = r.integers(int(info.min), int(info.max), n, dtype=np.int64, endpoint=True).astype(dt)
+    elif kind.endswith("zipf"):
+        # few distinct values spread over the whole signed range
+        keys = gen.zipf_keys(seed, n, 256, 1.1, 32 if dt == np.int32 else 64)
+        keys = keys.astype(np.uint32 if dt == np.int32 else np.uint64).view(dt)
+        return keys
+    else:  # narrow span straddling zero
+        keys = r.integers(-1800, 1800, n).astype(dt)
+        return keys
+    if n > 4:
+        keys[::101] = info.min
+        keys[::103] = info.max
+        keys[::107] = -1
+        keys[::109] = 0
+    return keys
+
+
+@pytest.mark.parametrize("kind", ["i32uniform", "i32zipf", "i32narrow", "i64uniform", "i64zipf", "i64narrow"])
+def test_signed_features_parity(kind):
+    keys = _signed(kind, 300_007, 41)
+    say(f"signed features {kind} n={keys.size}")
+    hist = torch.zeros(65536, dtype=torch.int32, device=DEV)
+    f = ahs.ahs_features(to_dev(keys), hist)
+    torch.cuda.synchronize()
+    st, rf, rhist = O.features(keys)
+    assert st == O.OK
+    check_features(f, rf, hist.cpu().numpy().view(np.uint32), rhist)
+
+
+@pytest.mark.parametrize("n", [1, 21, 4097, 100_003, 1_000_003])
+@pytest.mark.parametrize("kind", ["i32uniform", "i64uniform", "i32zipf"])
+def test_signed_radix(n, kind):
+    keys = _signed(kind, n, n + 3)
+    run_pair(keys, np.arange(n, dtype=np.uint32), ahs.RADIX)
+    run_pair(keys, None, ahs.RADIX)
+
+
+@pytest.mark.parametrize("kind", ["i32narrow", "i64narrow"])
+@pytest.mark.parametrize("n", [21, 8193, 1_000_003])
+def test_signed_counting(kind, n):
+    keys = _signed(kind, n, n + 5)
+    run_pair(keys, None, ahs.COUNTING)
+    run_pair(keys, np.arange(n, dtype=np.uint32), ahs.COUNTING)
+    if kind == "i64narrow":
+        # a narrow span at the bottom of the type
+        run_pair(np.iinfo(np.int64).min + keys.astype(np.int64) + 1800, None, ahs.COUNTING)
+
+
+@pytest.mark.parametrize("kind", ["i32uniform", "i64uniform", "i64zipf"])
+@pytest.mark.parametrize("n", [8193, 300_007])
+def test_signed_quick(kind, n):
+    keys = _signed(kind, n, n + 9)
+    run_pair(keys, np.arange(n, dtype=np.uint32), ahs.QUICK)
+    run_pair(keys, None, ahs.QUICK)
+
+
+def test_signed_auto_choices_and_in_place():
+    """AUTO on signed keys takes the oracle's decision for each family:
+    narrow span -> counting, few values over the full range -> radix,
+    uniform over the full range -> quicksort; in place as well."""
+    want = {"i32narrow": ahs.COUNTING, "i32zipf": ahs.RADIX, "i32uniform": ahs.QUICK,
+            "i64narrow": ahs.COUNTING, "i64zipf": ahs.RADIX, "i64uniform": ahs.QUICK}
+    for kind, s in want.items():
+        keys = _signed(kind, 1 << 20, 43)
+        assert run_pair(keys, np.arange(keys.size, dtype=np.uint32)) == s, kind
+        assert run_pair(keys, None, in_place=True) == s, kind
+    for n in (1, 7, 20):
+        keys = np.array([-3, 2**31 - 1, -2**31, 0, -1, 5, -3] * 3, np.int32)[:n]
+        assert run_pair(keys, np.arange(n, dtype=np.uint32)) == ahs.INSERTION

@@ -172,6 +172,32 @@ def test_segmented_u64_payload():
     run_segments(keys, offsets_of(sizes), np.arange(n, dtype=np.uint32))
 
 
+@pytest.mark.parametrize("dt", [np.int32, np.int64])
+def test_segmented_signed_payload(dt):
+    """Signed keys in every segment class: narrow spans around zero
+    (counting), full-range uniform (quicksort), few values over the full
+    range (radix), with both ends of the type planted."""
+    sizes = mixed_sizes(90, 29, 1 << 15)
+    sizes[-3:] = [40_000, 30_000, 20_000]
+    n = int(np.sum(sizes))
+    info = np.iinfo(dt)
+    r = np.random.default_rng(29)
+    keys = r.integers(int(info.min), int(info.max), n, dtype=np.int64, endpoint=True).astype(dt)
+    offs = offsets_of(sizes)
+    for s in range(0, len(sizes), 3):
+        a, b = int(offs[s]), int(offs[s + 1])
+        keys[a:b] = r.integers(-1500, 1500, b - a).astype(dt)
+    a = int(offs[-2])
+    bits_ = 32 if dt == np.int32 else 64
+    z = gen.zipf_keys(30, n - a, 64, 1.1, bits_).astype(np.uint32 if dt == np.int32 else np.uint64).view(dt)
+    keys[a:] = z
+    keys[::97] = info.min
+    keys[::89] = info.max
+    chosen = run_segments(keys, offs, np.arange(n, dtype=np.uint32))
+    assert {ahs.INSERTION, ahs.COUNTING, ahs.QUICK} <= set(chosen.tolist())
+    run_segments(keys, offs)
+
+
 @pytest.mark.parametrize("case", ["f32normal", "f64normal"])
 def test_segmented_float_with_nan(case):
     sizes = mixed_sizes(60, 26, 1 << 14)

@@ -183,6 +183,30 @@ def test_server_requests_arrive_while_others_run():
     s.close()
 
 
+def test_server_signed_requests():
+    """Signed 32- and 64-bit requests beside unsigned ones: each key type
+    forms its own batches; results equal the oracle's."""
+    rng = np.random.default_rng(63)
+    reqs = []
+    for i in range(24):
+        n = int(2 ** (4 + 11 * rng.random()))
+        dt = (np.int32, np.int64, np.uint32)[i % 3]
+        info = np.iinfo(dt)
+        if i % 2:  # narrow span (around zero for the signed types)
+            lo = 0 if dt == np.uint32 else -1000
+            keys = rng.integers(lo, lo + 2000, n).astype(dt)
+        else:  # the whole range of the type
+            keys = rng.integers(int(info.min), int(info.max), n, dtype=np.int64, endpoint=True).astype(dt) \
+                if dt != np.uint32 else gen.u32(63, i, n)
+        vals = np.arange(n, dtype=np.uint32) if i % 4 < 2 else None
+        reqs.append((keys, vals))
+    s = ahs.Server(hbm_budget_bytes=1 << 30, slots=2, lazy_dispatch=True)
+    say("server signed mix of 24 requests")
+    run_mix(s, reqs)
+    assert s.stats()["failed"] == 0
+    s.close()
+
+
 def test_server_lone_large_request_with_nan_matches_batched_sort():
     """A lone large request is sorted by the single-array path, which refuses
     NaN keys; such a request falls back to the batched sort and is reported

@@ -261,6 +261,58 @@ def test_bruteforce_all_permutations(n):
                 assert np.array_equal(ko, keys[want] if n else keys)
 
 
+@pytest.mark.parametrize("n", range(0, 6))
+@pytest.mark.parametrize("dtype", [np.int32, np.int64])
+def test_bruteforce_signed_permutations(n, dtype):
+    """Signed keys: every permutation of every multiset pattern over values
+    that straddle zero and reach both ends of the type, every sort, against
+    Python's stable sorted() on the integer values."""
+    cfg = O.config(0)
+    info = np.iinfo(dtype)
+    scale = [int(info.min), int(info.min) + 1, -70000, -1, 0, 1, int(info.max)]
+    for pat in _multisets(n):
+        base = np.array([scale[p] for p in pat], dtype=dtype)
+        for perm in set(itertools.permutations(range(n))):
+            keys = base[list(perm)] if n else base
+            vals = np.arange(n, dtype=np.uint32)
+            want = np.array(sorted(range(n), key=lambda i: int(keys[i])), dtype=np.int64)
+            for s in SORTS:
+                st, ko, vo, _, _ = O.sort(keys, vals, s, cfg)
+                if s == O.COUNTING and n and int(keys.max()) - int(keys.min()) >= cfg.k_count_cap:
+                    assert st == O.E_UNSUPPORTED
+                    continue
+                assert st == O.OK
+                assert np.array_equal(vo, want.astype(np.uint32)), (s, keys, vo, want)
+                assert np.array_equal(ko, keys[want] if n else keys)
+
+
+@pytest.mark.parametrize("dtype,udtype", [(np.int32, np.uint32), (np.int64, np.uint64)])
+def test_signed_map_is_offset_by_type_minimum(dtype, udtype):
+    """The signed map sends v to v - min(type): order preserving and onto the
+    unsigned range, so min -> 0, -1 -> 2^(w-1) - 1, 0 -> 2^(w-1), max -> 2^w - 1;
+    the features of signed keys equal those of the same values shifted by
+    -min(type) into the unsigned type (span, bins and entropy are translation
+    invariant)."""
+    info = np.iinfo(dtype)
+    w = np.dtype(dtype).itemsize * 8
+    keys = np.array([info.min, -1, 0, info.max], dtype=dtype)
+    st, m, nans = O.map_keys(keys)
+    assert st == O.OK and nans == 0
+    assert [int(x) for x in m] == [0, 2**(w - 1) - 1, 2**(w - 1), 2**w - 1]
+    assert np.array_equal(O.unmap_keys(m, dtype), keys)
+    r = np.random.default_rng(7)
+    for lo, hi in ((-3000, 1000), (int(info.min), int(info.min) + 5000), (-2**20, 2**20)):
+        sk = r.integers(lo, hi, 20000, dtype=np.int64).astype(dtype)
+        # shift by -min(type) in Python integers, then into the unsigned type
+        uk = np.array([int(v) - int(info.min) for v in sk], dtype=np.uint64).astype(udtype)
+        st1, fs, hs = O.features(sk)
+        st2, fu, hu = O.features(uk)
+        assert st1 == st2 == O.OK
+        assert (fs.n, fs.span, fs.nbins, fs.exact) == (fu.n, fu.span, fu.nbins, fu.exact)
+        assert fs.span == int(sk.max()) - int(sk.min())
+        assert fs.entropy_bits == fu.entropy_bits and np.array_equal(hs, hu)
+
+
 def _check_sorted_stable(keys, ko, vo):
     srt = np.argsort(keys, kind="stable")  # numpy's stable sort: an independent reference
     if keys.dtype.kind == "f":
@@ -281,6 +333,11 @@ GEN_CASES = [
     ("f64 normal+zeros", lambda r, n: np.where(r.random(n) < 0.1, np.where(r.random(n) < .5, -0.0, 0.0),
                                                r.normal(0, 1, n))),
     ("f32 inf mix", lambda r, n: r.choice(np.array([-np.inf, np.inf, -0.0, 0.0, 1.5, -1.5], np.float32), n)),
+    ("i32 mixed sign", lambda r, n: r.integers(-2**31, 2**31, n, dtype=np.int64).astype(np.int32)),
+    ("i32 narrow around zero", lambda r, n: r.integers(-1500, 1500, n).astype(np.int32)),
+    ("i32 extremes", lambda r, n: r.choice(np.array([-2**31, -1, 0, 1, 2**31 - 1], np.int32), n)),
+    ("i64 mixed sign", lambda r, n: r.integers(-2**63, 2**63 - 1, n, dtype=np.int64)),
+    ("i64 narrow negative", lambda r, n: r.integers(-2**40 - 3000, -2**40, n, dtype=np.int64)),
 ]
 
 
