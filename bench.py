@@ -406,6 +406,28 @@ def main():
                         "GBps": round(v[2] / (v[1] / 1e3) / 1e9, 1) if v[1] > 0 else None}
                     for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
 
+    # ------------------------------------------------------------ practical ceilings
+    # a plain device copy (read + write) and a plain read-only reduction of
+    # one array, timed with events: what streaming kernels reach on this GPU
+    def event_ms(fn, reps=5):
+        ts = []
+        for _ in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return statistics.median(ts[1:])
+    src32 = dkeys[cases[0]].view(torch.int32)
+    copy_ms = event_ms(lambda: out.view(torch.int32).copy_(src32))
+    read_ms = event_ms(lambda: torch.amax(src32))
+    ceilings = {"copy_GBps": round(2 * 4 * n / copy_ms / 1e6, 1), "read_GBps": round(4 * n / read_ms / 1e6, 1),
+                "how": f"torch copy (read + write) and torch.amax (read) of 2^{args.log2n} int32, event-timed medians"}
+    ceilings["copy_frac"] = round(ceilings["copy_GBps"] / HBM_PEAK_GBS, 4)
+    ceilings["read_frac"] = round(ceilings["read_GBps"] / HBM_PEAK_GBS, 4)
+    log(f"[bench] ceilings {ceilings}")
+
     # ------------------------------------------------------------ per array and strategy
     per_case = []
     if args.cases:
@@ -495,7 +517,8 @@ def main():
         "config": {"workload": f"strategy sweep: {len(cases)} arrays x 2^{args.log2n} uint32 ({', '.join(cases)}), "
                                "AHS AUTO per array (FSM + selector trained on MI355X measurements)",
                    "n_per_array": n, "arrays": cases, "auto_choices": chosen},
-        "roofline": roofline, "cpu_baseline": cpu, "step_kernels": step_kernels, "per_case": per_case,
+        "roofline": roofline, "ceilings": ceilings, "cpu_baseline": cpu, "step_kernels": step_kernels,
+        "per_case": per_case,
         "batched": batched, "serving": serving,
     }
     print(json.dumps(res), flush=True)
