@@ -13,7 +13,10 @@ Prints one JSON line: whole-job Gkeys/s, the dominant kernel's roofline
 with HIP events on the launch stream), the CPU oracle on a bounded sample,
 and per-array AUTO-vs-forced-strategy timings with %HBM of each path.
 
-Two further sections, reported beside the headline (not in `value`):
+Three further sections, reported beside the headline (not in `value`):
+* paper_sweep: the paper's dataset families (uniform, rounded Gaussian as
+  signed keys, Zipf(1.5), edge patterns, full-range signed keys, stand-ins
+  with the (n, k, H) of its real datasets); AUTO against each forced strategy.
 * batched: 65,536 uint32 segments, sizes log-uniform on [16, 2^20] (about
   6.2e9 keys), distributions mixed per segment; the autotuned, graph-captured
   batched sort against a host loop of per-array AHS AUTO calls.
@@ -279,6 +282,84 @@ def serving_section(args, ahs, gen, torch, np):
     return res
 
 
+def paper_sweep_section(args, ahs, gen, torch, np):
+    """The paper's dataset families (Sec. III-B) at their default sizes: AUTO
+    (FSM + selector, and FSM only) against each forced strategy, with every
+    strategy's output checked bitwise against the others and for order."""
+    dev = torch.device("cuda:0")
+    ctx = ahs.default_context(0)
+    ctx.set_model(ahs.default_model())
+    cfg_auto = ahs.ahs_config_init(ahs.PRESET_GPU, use_model=1)
+    cfg_fsm = ahs.ahs_config_init(ahs.PRESET_GPU)
+    rows = []
+    for case in gen.PAPER_CASES:
+        t = time.time()
+        keys = torch.from_numpy(gen.paper_sweep(case)).to(dev)
+        n = keys.numel()
+        out = torch.empty_like(keys)
+        torch.cuda.synchronize()
+        row = {"case": case, "dtype": str(keys.dtype).replace("torch.", ""), "n": n}
+        ref = None
+        for sname, strat, cfg in (("auto", ahs.AUTO, cfg_auto), ("auto_fsm", ahs.AUTO, cfg_fsm),
+                                  ("counting", ahs.COUNTING, cfg_fsm), ("radix", ahs.RADIX, cfg_fsm),
+                                  ("quick", ahs.QUICK, cfg_fsm)):
+            times = []
+            try:
+                for r in range(args.reps + 1):  # the first run is not timed
+                    torch.cuda.synchronize()
+                    a = time.perf_counter()
+                    _, _, ch, f = ahs.ahs_sort(keys, strategy=strat, cfg=cfg, out=out, ctx=ctx, want_features=r == 0)
+                    torch.cuda.synchronize()
+                    if r == 0:
+                        feats = f
+                    else:
+                        times.append(time.perf_counter() - a)
+            except ahs.AhsError as e:
+                row[sname] = {"status": e.status}
+                continue
+            if ref is None:
+                ref = out.clone()
+                if keys.dtype in (torch.int32, torch.int64):
+                    x = out
+                elif keys.dtype == torch.uint32:
+                    x = out.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+                else:
+                    x = out.view(torch.int64) ^ (-(2 ** 63))  # unsigned order as signed
+                row["sorted_ok"] = bool((x[1:] >= x[:-1]).all().item())
+                row.update({"span": feats.span, "nbins": feats.nbins, "entropy_bits": round(feats.entropy_bits, 4)})
+                del x
+                agree = True
+            else:
+                agree = bool(torch.equal(ref.view(torch.uint8), out.view(torch.uint8)))
+            med = statistics.median(times)
+            row[sname] = {"ms": round(med * 1e3, 4), "Gkeys_s": round(n / med / 1e9, 2),
+                          "chosen": ahs.STRATEGY_NAMES[ch], "agrees": agree}
+        forced = {k: row[k]["ms"] for k in ("counting", "radix", "quick") if "ms" in row[k]}
+        best = min(forced, key=forced.get)
+        row["best_forced"] = best
+        row["auto_over_best"] = round(row["auto"]["ms"] / forced[best], 4)
+        row["auto_fsm_over_best"] = round(row["auto_fsm"]["ms"] / forced[best], 4)
+        rows.append(row)
+        log(f"[bench] paper case {case} in {time.time() - t:.1f}s: auto {row['auto']['chosen']} "
+            f"{row['auto']['ms']} ms, best {best} {forced[best]} ms, fsm {row['auto_fsm']['chosen']}")
+        del keys, out, ref
+        torch.cuda.empty_cache()
+    ratios = [r["auto_over_best"] for r in rows]
+    fsm = [r["auto_fsm_over_best"] for r in rows]
+    return {"workload": "the paper's dataset families: uniform k in {1e2, 1e4, 1e6}, Normal(0, k/4) rounded "
+                        "(int32) for k in 1e2..1e6, Zipf(1.5) ranks over k in {1e2, 1e4, 1e6}, constant, ascending, "
+                        "descending, sawtooth, alternating, full-range int32/int64, and synthetic (n, k, H) "
+                        "stand-ins for the taxi, sensor and k-mer datasets; 2^24 keys unless the paper gives n",
+            "auto_over_best_geomean": round(float(np.exp(np.mean(np.log(ratios)))), 4),
+            "auto_over_best_max": max(ratios),
+            "auto_fsm_over_best_geomean": round(float(np.exp(np.mean(np.log(fsm)))), 4),
+            "auto_fsm_over_best_max": max(fsm),
+            "all_sorted_and_agreeing": all(r["sorted_ok"] and all(r[k].get("agrees", True) for k in
+                                                                  ("auto", "auto_fsm", "counting", "radix", "quick"))
+                                           for r in rows),
+            "cases": rows}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -296,6 +377,8 @@ def parse():
                     help="run one plain elementwise copy of 2^log2n 32-bit words first (counter calibration)")
     ap.add_argument("--headline", action=argparse.BooleanOptionalAction, default=True,
                     help="the strategy sweep (the reported value); --no-headline runs only the other sections")
+    ap.add_argument("--paper-sweep", action=argparse.BooleanOptionalAction, default=True,
+                    help="the paper's dataset families, AUTO vs each forced strategy")
     ap.add_argument("--batched", action=argparse.BooleanOptionalAction, default=True)
     ap.add_argument("--seg-count", type=int, default=65536, help="segments in the batched workload")
     ap.add_argument("--seg-reps", type=int, default=3, help="timed graph replays of the batched sort")
@@ -327,7 +410,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     if not args.headline:
-        side = {"batched": batched_section(args, ahs, gen, torch, np) if args.batched else None,
+        side = {"paper_sweep": paper_sweep_section(args, ahs, gen, torch, np) if args.paper_sweep else None,
+                "batched": batched_section(args, ahs, gen, torch, np) if args.batched else None,
                 "serving": serving_section(args, ahs, gen, torch, np) if args.serve else None}
         print(json.dumps({"metric": METRIC, "value": None, "note": "sections only (--no-headline)", **side}),
               flush=True)
@@ -507,6 +591,7 @@ def main():
     # ------------------------------------------------------------ batched and serving sections
     del dkeys, out, host
     torch.cuda.empty_cache()
+    paper = paper_sweep_section(args, ahs, gen, torch, np) if args.paper_sweep else None
     batched = batched_section(args, ahs, gen, torch, np) if args.batched else None
     serving = serving_section(args, ahs, gen, torch, np) if args.serve else None
 
@@ -518,7 +603,7 @@ def main():
                                "AHS AUTO per array (FSM + selector trained on MI355X measurements)",
                    "n_per_array": n, "arrays": cases, "auto_choices": chosen},
         "roofline": roofline, "ceilings": ceilings, "cpu_baseline": cpu, "step_kernels": step_kernels,
-        "per_case": per_case,
+        "per_case": per_case, "paper_sweep": paper,
         "batched": batched, "serving": serving,
     }
     print(json.dumps(res), flush=True)

@@ -14,6 +14,10 @@ into the workloads used for parity and measurement:
   +-0.0 values.
 * ``segments``: many uneven u32 arrays with sizes log-uniform on [16, 2^20].
 * ``request_trace``: Poisson arrivals with log-uniform sizes and mixed types.
+* ``paper_sweep``: the paper's synthetic families (uniform over k values,
+  rounded Gaussians of variance k/4 as signed keys, Zipf(1.5) over k ranks),
+  its edge patterns, full-range signed keys, and synthetic arrays with the
+  (n, k, H) of its three real datasets.
 
 The paper's own datasets (taxi timestamps, sensor readings, k-mers) are not
 available; these synthetic families stand in for its uniform, skewed and
@@ -257,3 +261,88 @@ def request_trace(duration_s=60.0, rate=2000.0, seed=9, lo_exp=10, span_exp=14, 
     pay = index(seed, 4, m, 2).astype(np.int64)
     offs = index(seed, 5, m, 1 << 30).astype(np.int64)
     return {"arrival_s": t, "size": sizes, "dtype": dt, "dist": dist, "payload": pay, "offset": offs}
+
+
+# the paper's dataset families (Sec. III-B) ----------------------------------
+PAPER_CASES = (
+    "uniform_k1e2", "uniform_k1e4", "uniform_k1e6",
+    "gauss_k1e2", "gauss_k1e3", "gauss_k1e4", "gauss_k1e5", "gauss_k1e6",
+    "zipf1.5_k1e2", "zipf1.5_k1e4", "zipf1.5_k1e6",
+    "constant", "ascending", "descending", "sawtooth", "alternating",
+    "i32_uniform", "i64_uniform",
+    "taxi_like", "iot_like", "kmer_like",
+)
+
+# (n, k, H) the paper gives for its real datasets; the stand-ins match them
+PAPER_REAL = {"taxi_like": (10**7, 10**9, 8.2), "iot_like": (10**6, 500, 1.1), "kmer_like": (10**8, 4**30, 3.7)}
+
+
+def paper_sweep_default_n(case):
+    return PAPER_REAL[case][0] if case in PAPER_REAL else 1 << 24
+
+
+def paper_sweep(case, n=None, seed=None):
+    """Keys of one family of the paper's datasets (default seed 20 + the
+    case's position in PAPER_CASES):
+
+    * uniform_k*: u32 uniform on [0, k).
+    * gauss_k*: Normal(0, variance k/4) rounded to the nearest integer, as
+      int32 (negative and positive keys).
+    * zipf1.5_k*: u32 Zipf(1.5) ranks 0 .. k-1 (rank r+1 has weight (r+1)^-1.5).
+    * constant (one value), ascending / descending (sorted uniform 32-bit
+      keys), sawtooth (runs of 2^16 rising then falling keys, spaced 65,537
+      apart), alternating (small and large keys in turn).
+    * i32_uniform, i64_uniform: the whole signed range.
+    * taxi_like: u32, 294 equally likely values over [0, 10^9) with both ends
+      present: k = 10^9, H = log2(294) = 8.2 bits.
+    * iot_like: u32 over [0, 500): one value with probability 0.92, the other
+      499 equally likely: H = 1.1 bits.
+    * kmer_like: u64, 13 equally likely 60-bit values (30-mers at 2 bits per
+      base) with 0 and 4^30 - 1 present: k = 4^30, H = log2(13) = 3.7 bits.
+    """
+    if n is None:
+        n = paper_sweep_default_n(case)
+    s = 20 + PAPER_CASES.index(case) if seed is None else seed
+    if case.startswith("uniform_k"):
+        return index(s, 0, n, int(float(case[9:]))).astype(np.uint32)
+    if case.startswith("gauss_k"):
+        k = float(case[7:])
+        return np.rint(normal(s, 0, n, float(np.sqrt(k / 4.0)))).astype(np.int32)
+    if case.startswith("zipf1.5_k"):
+        return zipf_index(s, 0, n, 1.5, int(float(case[9:])))
+    if case == "constant":
+        return np.full(n, 0x9E3779B9, np.uint32)
+    if case in ("ascending", "descending"):
+        x = u32(s, 0, n)
+        x.sort()
+        return x if case == "ascending" else np.ascontiguousarray(x[::-1])
+    if case == "sawtooth":
+        i = np.arange(n, dtype=np.uint64)
+        r = i & np.uint64(0xFFFF)
+        up = ((i >> np.uint64(16)) & np.uint64(1)) == 0
+        return (np.where(up, r, np.uint64(0xFFFF) - r) * np.uint64(65537)).astype(np.uint32)
+    if case == "alternating":
+        i = np.arange(n, dtype=np.uint64)
+        return np.where(i % np.uint64(2) == 0, i // np.uint64(2), np.uint64(0xFFFFFFFF) - i // np.uint64(2)).astype(
+            np.uint32)
+    if case == "i32_uniform":
+        return u32(s, 0, n).view(np.int32)
+    if case == "i64_uniform":
+        return u64(s, 0, n).view(np.int64)
+    if case == "taxi_like":
+        vals = (distinct(s, 1, 294, 32).astype(np.uint64) * np.uint64(10**9)) >> np.uint64(32)
+        x = vals[index(s, 2, n, 294).astype(np.int64)].astype(np.uint32)
+        if n >= 2:
+            x[0], x[n // 2] = 0, 10**9 - 1
+        return x
+    if case == "iot_like":
+        other = index(s, 1, n, 499).astype(np.uint32)
+        other += (other >= 250).astype(np.uint32)  # the 499 values besides 250
+        return np.where(unit(s, 2, n) < 0.92, np.uint32(250), other).astype(np.uint32)
+    if case == "kmer_like":
+        vals = distinct(s, 1, 13, 64) >> np.uint64(4)
+        x = vals[index(s, 2, n, 13).astype(np.int64)]
+        if n >= 2:
+            x[0], x[n // 2] = 0, (1 << 60) - 1
+        return x
+    raise ValueError(case)

@@ -7,9 +7,12 @@ device, the host round trips each path needs included).  These are the
 labels the selector model of Sec. III-H is trained on (train_gbt.py).
 
 Workloads: u32 keys uniform over k values (k from 16 to 2^32), 64..65,536
-distinct values drawn with Zipf ranks, sorted and reversed uniform keys;
-u64 keys uniform over 2^64 / 2^32 / 2^16 values and Zipf over 4,096 values;
-f32 and f64 Normal(0, 1e3); n from 2^10 to 2^28.  Keys are drawn on the
+distinct values drawn with Zipf ranks, 4..64 equally likely values spread
+over the whole range, sorted and reversed uniform keys; u64 keys uniform
+over 2^64 / 2^48 / 2^32 / 2^16 values, Zipf over 4,096 values and 4..256
+equally likely values spread over [0, 2^40), [0, 2^60) or the whole range
+(both ends present, so the span is exact); f32 and f64 Normal(0, 1e3); n from 2^10
+to 2^28.  Keys are drawn on the
 device from a seeded torch generator (the labels are measurements, not
 parity data).
 """
@@ -35,12 +38,17 @@ def workloads(max_log2n):
             out.append(("u32", lg, "uniform", k))
         for m, s in ((64, 1.1), (256, 1.1), (4096, 1.1), (65536, 1.1), (256, 1.5)):
             out.append(("u32", lg, f"zipf{s}", m))
+        for m in (4, 16, 64):
+            out.append(("u32", lg, "fewvals32", m))
         out.append(("u32", lg, "sorted", 1 << 32))
         out.append(("u32", lg, "reverse", 1 << 32))
         if lg <= max_log2n - 2:
-            for k in (1 << 16, 1 << 32, 1 << 64):
+            for k in (1 << 16, 1 << 32, 1 << 48, 1 << 64):
                 out.append(("u64", lg, "uniform", k))
             out.append(("u64", lg, "zipf1.0", 4096))
+            for bits in (40, 60, 64):
+                for m in (4, 16, 256):
+                    out.append(("u64", lg, f"fewvals{bits}", m))
             out.append(("f32", lg, "normal", 0))
             out.append(("f64", lg, "normal", 0))
     return out
@@ -55,6 +63,16 @@ def make_keys(dtype, lg, dist, param, g, dev):
             x = torch.randint(0, param, (n,), generator=g, device=dev, dtype=torch.int64)
         if dist != "uniform":
             x = torch.sort(x, descending=(dist == "reverse")).values
+    elif dist.startswith("fewvals"):
+        # param equally likely values over [0, 2^bits), both ends among them
+        bits = int(dist[7:])
+        if bits >= 64:
+            vals = torch.randint(-(1 << 63), (1 << 63) - 1, (param,), generator=g, device=dev, dtype=torch.int64)
+            vals[0], vals[1] = 0, -1  # 0 and 2^64 - 1 as two's complement
+        else:
+            vals = torch.randint(0, 1 << bits, (param,), generator=g, device=dev, dtype=torch.int64)
+            vals[0], vals[1] = 0, (1 << bits) - 1
+        x = vals[torch.randint(0, param, (n,), generator=g, device=dev, dtype=torch.int64)]
     elif dist.startswith("zipf"):
         s = float(dist[4:])
         vals = torch.randint(0, 1 << 32 if dtype == "u32" else (1 << 62), (param,), generator=g, device=dev,

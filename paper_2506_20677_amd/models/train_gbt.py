@@ -65,16 +65,51 @@ def export(clf, path):
         f.write("\n".join(lines) + "\n")
 
 
+def held_out_regret(times, pred):
+    """Time of the predicted strategy over the best time, per row (inf if infeasible)."""
+    out = []
+    for t, c in zip(times, pred):
+        out.append(t[c] / np.nanmin(t) if math.isfinite(t[c]) else float("inf"))
+    return np.array(out)
+
+
+def cross_validate(X, y, w, times):
+    from sklearn.ensemble import GradientBoostingClassifier
+    from sklearn.model_selection import KFold
+
+    folds = list(KFold(n_splits=5, shuffle=True, random_state=0).split(X))
+    print("stages depth | held-out accuracy | mean time over best | worst")
+    for depth in (1, 2, 3):
+        for stages in (5, 10, 20, 40):
+            acc, reg = [], []
+            for tr, te in folds:
+                clf = GradientBoostingClassifier(n_estimators=stages, max_depth=depth, learning_rate=0.3,
+                                                 random_state=0)
+                clf.fit(X[tr], y[tr], sample_weight=w[tr])
+                p = clf.predict(X[te])
+                acc.append(np.mean(p == y[te]))
+                reg.extend(held_out_regret(times[te], p))
+            reg = np.array(reg)
+            fin = reg[np.isfinite(reg)]
+            print(f"{stages:6d} {depth:5d} | {np.mean(acc):.3f} | {np.mean(fin):.4f} | "
+                  f"{reg.max():.2f} ({int((~np.isfinite(reg)).sum())} infeasible)")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--labels", default=os.path.join(HERE, "mi355x_labels.csv"))
     ap.add_argument("--out", default=os.path.join(HERE, "mi355x_selector.gbt"))
     ap.add_argument("--trees", type=int, default=10)
     ap.add_argument("--depth", type=int, default=2)
+    ap.add_argument("--cv", action="store_true",
+                    help="only report 5-fold cross-validation over a grid of tree counts and depths")
     args = ap.parse_args()
     from sklearn.ensemble import GradientBoostingClassifier
 
     rows, X, y, w, times = load(args.labels)
+    if args.cv:
+        cross_validate(X, y, w, times)
+        return
     clf = GradientBoostingClassifier(n_estimators=args.trees, max_depth=args.depth, learning_rate=0.3,
                                      random_state=0)
     clf.fit(X, y, sample_weight=w)

@@ -68,3 +68,42 @@ def test_segment_sizes_log_uniform_bounds():
     # log2 sizes spread evenly over [4, 20): each quarter holds about 1/4
     q = np.histogram(np.log2(s), bins=4, range=(4, 20))[0] / s.size
     assert np.all(np.abs(q - 0.25) < 0.02)
+
+
+def _value_entropy(x):
+    _, c = np.unique(x, return_counts=True)
+    p = c / x.size
+    return float(-(p * np.log2(p)).sum())
+
+
+def test_paper_real_dataset_stand_ins_have_the_papers_n_k_h():
+    """The synthetic stand-ins carry the range k = max - min + 1 and the value
+    entropy H the paper gives for its taxi, sensor and k-mer datasets
+    (Sec. III-B); n is the paper's by default (checked on smaller draws)."""
+    for case, (n_paper, k_paper, h_paper) in gen.PAPER_REAL.items():
+        assert gen.paper_sweep_default_n(case) == n_paper
+        x = gen.paper_sweep(case, n=1 << 20)
+        k = int(x.max()) - int(x.min()) + 1
+        assert k == k_paper, (case, k)
+        assert abs(_value_entropy(x) - h_paper) < 0.05, (case, _value_entropy(x))
+
+
+def test_paper_synthetic_families_shapes():
+    n = 1 << 18
+    for name, k in (("uniform_k1e2", 100), ("uniform_k1e4", 10**4), ("uniform_k1e6", 10**6)):
+        x = gen.paper_sweep(name, n=n)
+        assert x.dtype == np.uint32 and x.min() >= 0 and x.max() < k
+    for e in range(2, 7):
+        x = gen.paper_sweep(f"gauss_k1e{e}", n=n)
+        assert x.dtype == np.int32 and (x < 0).any() and (x > 0).any()
+        assert abs(float(np.var(x.astype(np.float64))) / (10**e / 4) - 1) < 0.05
+    z = gen.paper_sweep("zipf1.5_k1e2", n=n)
+    c = np.bincount(z, minlength=100)
+    assert c.argmax() == 0 and abs(c[0] / c[1] - 2 ** 1.5) < 0.1 * 2 ** 1.5
+    s = gen.paper_sweep("sawtooth", n=1 << 18)
+    d = np.diff(s.astype(np.int64))
+    assert ((d > 0) | (d < 0) | (np.arange(d.size) % 65536 == 65535)).all()
+    a = gen.paper_sweep("alternating", n=1000)
+    assert (a[0::2] < a[1::2]).all() and (np.diff(a[0::2].astype(np.int64)) > 0).all()
+    assert np.unique(gen.paper_sweep("constant", n=100)).size == 1
+    assert gen.paper_sweep("i64_uniform", n=n).dtype == np.int64

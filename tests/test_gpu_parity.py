@@ -69,12 +69,14 @@ def run_pair(keys, vals=None, strategy=ahs.AUTO, cfg_preset=0, in_place=False):
         ko, vo, chosen, f = ahs.ahs_sort(k, v, strategy, cfg, want_features=True)
     torch.cuda.synchronize()
     st, rk, rv, rchosen, rf = O.sort(keys, vals, strategy, O.config(cfg_preset))
-    if st == O.E_DEPTH and strategy == ahs.QUICK:
-        # the oracle's median-of-three quicksort refuses adversarial inputs
-        # (sawtooth); its four sorts are pinned to agree, so radix gives the
-        # same unique stable result
+    if st == O.E_DEPTH:
+        # the oracle's median-of-three quicksort (forced, or chosen by AUTO)
+        # refuses adversarial inputs (sawtooth); its four sorts are pinned to
+        # agree, so radix gives the same unique stable result
+        assert strategy in (ahs.QUICK, ahs.AUTO)
+        rchosen = O.QUICK if strategy == ahs.QUICK else O.select(rf, O.config(cfg_preset))[1]
+        assert rchosen == O.QUICK
         st, rk, rv, _, rf = O.sort(keys, vals, O.RADIX, O.config(cfg_preset))
-        rchosen = O.QUICK
     assert st == O.OK, st
     assert np.array_equal(bits(ko.cpu().numpy()), bits(rk)), "keys differ"
     if vals is not None:
