@@ -291,6 +291,7 @@ def paper_sweep_section(args, ahs, gen, torch, np):
     ctx.set_model(ahs.default_model())
     cfg_auto = ahs.ahs_config_init(ahs.PRESET_GPU, use_model=1)
     cfg_fsm = ahs.ahs_config_init(ahs.PRESET_GPU)
+    cfg_cal = ahs.ahs_config_init(ahs.PRESET_MI355X_CALIBRATED)  # thresholds recalibrated by eq. (1)
     rows = []
     for case in gen.PAPER_CASES:
         t = time.time()
@@ -301,6 +302,7 @@ def paper_sweep_section(args, ahs, gen, torch, np):
         row = {"case": case, "dtype": str(keys.dtype).replace("torch.", ""), "n": n}
         ref = None
         for sname, strat, cfg in (("auto", ahs.AUTO, cfg_auto), ("auto_fsm", ahs.AUTO, cfg_fsm),
+                                  ("auto_fsm_calibrated", ahs.AUTO, cfg_cal),
                                   ("counting", ahs.COUNTING, cfg_fsm), ("radix", ahs.RADIX, cfg_fsm),
                                   ("quick", ahs.QUICK, cfg_fsm)):
             times = []
@@ -339,6 +341,7 @@ def paper_sweep_section(args, ahs, gen, torch, np):
         row["best_forced"] = best
         row["auto_over_best"] = round(row["auto"]["ms"] / forced[best], 4)
         row["auto_fsm_over_best"] = round(row["auto_fsm"]["ms"] / forced[best], 4)
+        row["auto_fsm_calibrated_over_best"] = round(row["auto_fsm_calibrated"]["ms"] / forced[best], 4)
         rows.append(row)
         log(f"[bench] paper case {case} in {time.time() - t:.1f}s: auto {row['auto']['chosen']} "
             f"{row['auto']['ms']} ms, best {best} {forced[best]} ms, fsm {row['auto_fsm']['chosen']}")
@@ -346,6 +349,7 @@ def paper_sweep_section(args, ahs, gen, torch, np):
         torch.cuda.empty_cache()
     ratios = [r["auto_over_best"] for r in rows]
     fsm = [r["auto_fsm_over_best"] for r in rows]
+    cal = [r["auto_fsm_calibrated_over_best"] for r in rows]
     return {"workload": "the paper's dataset families: uniform k in {1e2, 1e4, 1e6}, Normal(0, k/4) rounded "
                         "(int32) for k in 1e2..1e6, Zipf(1.5) ranks over k in {1e2, 1e4, 1e6}, constant, ascending, "
                         "descending, sawtooth, alternating, full-range int32/int64, and synthetic (n, k, H) "
@@ -354,8 +358,11 @@ def paper_sweep_section(args, ahs, gen, torch, np):
             "auto_over_best_max": max(ratios),
             "auto_fsm_over_best_geomean": round(float(np.exp(np.mean(np.log(fsm)))), 4),
             "auto_fsm_over_best_max": max(fsm),
+            "auto_fsm_calibrated_over_best_geomean": round(float(np.exp(np.mean(np.log(cal)))), 4),
+            "auto_fsm_calibrated_over_best_max": max(cal),
             "all_sorted_and_agreeing": all(r["sorted_ok"] and all(r[k].get("agrees", True) for k in
-                                                                  ("auto", "auto_fsm", "counting", "radix", "quick"))
+                                                                  ("auto", "auto_fsm", "auto_fsm_calibrated",
+                                                                   "counting", "radix", "quick"))
                                            for r in rows),
             "cases": rows}
 

@@ -112,16 +112,19 @@ typedef struct {
 } ahs_config;
 
 enum {
-  AHS_PRESET_GPU = 0,         /* k_count 4096 (default) */
-  AHS_PRESET_PAPER_TEXT = 1,  /* k_count 1000 (Sec. III-A) */
-  AHS_PRESET_PAPER_TABLE2 = 2 /* k_count 1024 (Table II) */
+  AHS_PRESET_GPU = 0,              /* k_count 4096 (default) */
+  AHS_PRESET_PAPER_TEXT = 1,       /* k_count 1000 (Sec. III-A) */
+  AHS_PRESET_PAPER_TABLE2 = 2,     /* k_count 1024 (Table II) */
+  AHS_PRESET_MI355X_CALIBRATED = 3 /* n_small 48, k_count 5000: eq. (1) of Sec. III-C (alpha 0.7) minimised
+                                      over n_t in [10, 50], k_t in [500, 5000] on MI355X timings */
 };
 
 typedef struct ahs_context ahs_context;
 typedef struct ahs_model ahs_model;
 
-/* Fills *cfg with a preset: n_small 20, k_radix 1e6, h_ratio 0.7,
- * ml_min_n 1000, k_count_cap 65,536, use_model 0, and the preset's k_count. */
+/* Fills *cfg with a preset: n_small 20 (48 for the calibrated preset),
+ * k_radix 1e6, h_ratio 0.7, ml_min_n 1000, k_count_cap 65,536, use_model 0,
+ * and the preset's k_count.  An unknown preset is AHS_E_INVALID_ARG. */
 ahs_status ahs_config_init(ahs_config* cfg, int preset);
 
 /* Creates host-side state bound to HIP device `device`: device properties,

@@ -32,6 +32,11 @@ int ref_config_init(ref_config* cfg, int preset) {
   if (preset == 0) return REF_OK;
   if (preset == 1) { cfg->k_count = 1000; return REF_OK; }
   if (preset == 2) { cfg->k_count = 1024; return REF_OK; }
+  if (preset == 3) {       /* thresholds recalibrated by eq. (1) (Sec. III-C) */
+    cfg->n_small = 48;
+    cfg->k_count = 5000;
+    return REF_OK;
+  }
   return REF_E_INVALID_ARG;
 }
 

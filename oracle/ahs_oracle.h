@@ -27,7 +27,8 @@
  *
  * Readings where the paper is silent, garbled or self-contradictory (each
  * also listed in the design notes of the repository):
- *   R1  K_c is a configuration value (preset 4096; paper presets 1000, 1024).
+ *   R1  K_c is a configuration value (preset 4096; paper presets 1000, 1024;
+ *       preset 3 holds n_small 48 and K_c 5000, recalibrated by eq. (1)).
  *   R2  The entropy test is relative: H < h_ratio * log2(B), strict.
  *   R3  H is computed over at most 65,536 bins of (m - min) >> s with the
  *       smallest such shift s; exact per value when span <= 65,535.  The

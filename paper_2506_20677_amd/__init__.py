@@ -28,7 +28,7 @@ STRATEGY_NAMES = {AUTO: "auto", COUNTING: "counting", RADIX: "radix", QUICK: "qu
 STRATEGY_CODES = {v: k for k, v in STRATEGY_NAMES.items()}
 OK, E_INVALID_ARG, E_UNSUPPORTED, E_NAN, E_WORKSPACE, E_OOM, E_DEVICE, E_NO_MODEL, E_PARSE = (
     0, -1, -2, -3, -4, -5, -6, -7, -9)
-PRESET_GPU, PRESET_PAPER_TEXT, PRESET_PAPER_TABLE2 = 0, 1, 2
+PRESET_GPU, PRESET_PAPER_TEXT, PRESET_PAPER_TABLE2, PRESET_MI355X_CALIBRATED = 0, 1, 2, 3
 
 # signed tensors sort as signed numbers (sign-bit map); pass dtype=U32 / U64
 # explicitly to order a signed tensor's raw bits as unsigned

@@ -202,6 +202,10 @@ extern "C" ahs_status ahs_config_init(ahs_config* cfg, int preset) {
     case AHS_PRESET_GPU: return AHS_OK;
     case AHS_PRESET_PAPER_TEXT: cfg->k_count = 1000; return AHS_OK;
     case AHS_PRESET_PAPER_TABLE2: cfg->k_count = 1024; return AHS_OK;
+    case AHS_PRESET_MI355X_CALIBRATED:  // Sec. III-C, eq. (1) on this GPU's timings
+      cfg->n_small = 48;
+      cfg->k_count = 5000;
+      return AHS_OK;
   }
   return AHS_E_INVALID_ARG;
 }

@@ -369,6 +369,14 @@ extern "C" ahs_status ahs_sort(ahs_context* ctx, const void* d_keys_in, void* d_
   const bool want_feats = h_feats != nullptr;
   const bool model_decides = requested == AHS_AUTO && c.use_model && n >= c.ml_min_n;
   if (model_decides && !ctx->model) return ctx->fail(AHS_E_NO_MODEL, "use_model set but no model attached");
+  // The FSM's first state depends on n alone: integer keys (nothing to
+  // reject as NaN) whose features the caller did not ask for go straight to
+  // the small-input sort, with no feature pass and no host round trip.
+  if (requested == AHS_AUTO && !flt && !want_feats && n <= (uint64_t)c.n_small && n <= (uint64_t)SMALL_SORT_MAX) {
+    AHS_TRY(run_small(j));
+    if (h_chosen) *h_chosen = AHS_INSERTION;
+    return AHS_OK;
+  }
   const bool need_minmax = flt || requested != AHS_QUICK || want_feats;
   uint32_t plan = 0;
   std::vector<uint32_t> dcounts;

@@ -35,10 +35,13 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_config_presets():
-    for preset, kc in ((0, 4096), (1, 1000), (2, 1024)):
+    for preset, ns, kc in ((0, 20, 4096), (1, 20, 1000), (2, 20, 1024), (3, 48, 5000)):
         c = ahs.ahs_config_init(preset)
+        o = O.config(preset)
         assert (c.n_small, c.k_count, c.k_radix, c.h_ratio, c.ml_min_n, c.k_count_cap, c.use_model) == (
-            20, kc, 1000000, 0.7, 1000, 65536, 0)
+            ns, kc, 1000000, 0.7, 1000, 65536, 0)
+        assert (o.n_small, o.k_count, o.k_radix, o.h_ratio, o.ml_min_n, o.k_count_cap, o.use_model) == (
+            ns, kc, 1000000, 0.7, 1000, 65536, 0)
     with pytest.raises(ahs.AhsError):
         ahs.ahs_config_init(7)
 

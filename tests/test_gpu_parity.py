@@ -560,3 +560,47 @@ def test_signed_auto_choices_and_in_place():
     for n in (1, 7, 20):
         keys = np.array([-3, 2**31 - 1, -2**31, 0, -1, 5, -3] * 3, np.int32)[:n]
         assert run_pair(keys, np.arange(n, dtype=np.uint32)) == ahs.INSERTION
+
+
+def test_small_input_state_without_features():
+    """n <= n_small with integer keys and no feature request: the decision
+    needs only n, so the sort runs without the feature pass; the result and
+    the reported state equal the oracle's, in place too, and for a raised
+    n_small up to the small sort's limit."""
+    cfg0 = O.config(0)
+    for dt in (np.uint32, np.int32, np.uint64, np.int64):
+        for n in (1, 2, 7, 20):
+            r = np.random.default_rng(n)
+            info = np.iinfo(dt)
+            keys = r.integers(int(info.min), int(info.max), n, dtype=np.int64 if dt != np.uint64 else np.uint64,
+                              endpoint=True).astype(dt)
+            keys[: n // 2] = keys[n - 1]  # duplicates
+            vals = np.arange(n, dtype=np.uint32)
+            st, rk, rv, rch, _ = O.sort(keys, vals, O.AUTO, cfg0)
+            assert st == O.OK and rch == O.INSERTION
+            k = to_dev(keys)
+            ko, vo, ch, f = ahs.ahs_sort(k, to_dev(vals))
+            assert f is None and ch == ahs.INSERTION
+            assert np.array_equal(bits(ko.cpu().numpy()), bits(rk)) and np.array_equal(vo.cpu().numpy(), rv)
+            ko, _, ch, _ = ahs.ahs_sort(k, out=k)
+            torch.cuda.synchronize()
+            assert ch == ahs.INSERTION and np.array_equal(bits(k.cpu().numpy()), bits(rk))
+    keys = np.random.default_rng(3).integers(0, 50, 1000).astype(np.uint32)
+    cfg = ahs.ahs_config_init(0, n_small=1000)
+    ko, _, ch, _ = ahs.ahs_sort(to_dev(keys), cfg=cfg)
+    st, rk, _, rch, _ = O.sort(keys, None, O.AUTO, O.config(0, n_small=1000))
+    assert ch == ahs.INSERTION == rch and np.array_equal(ko.cpu().numpy(), rk)
+
+
+def test_calibrated_preset_decisions():
+    """The thresholds recalibrated by eq. (1) (n_small 48, K_c 5000): 48 keys
+    take the small-input state, a span of 4,999 the counting sort, a span of
+    5,000 the general path, matching the oracle under the same preset."""
+    r = np.random.default_rng(47)
+    keys = r.integers(0, 2**32, 48, dtype=np.uint64).astype(np.uint32)
+    assert run_pair(keys, np.arange(48, dtype=np.uint32), cfg_preset=ahs.PRESET_MI355X_CALIBRATED) == ahs.INSERTION
+    keys = (r.integers(0, 5000, 100_000) + 7).astype(np.uint32)
+    keys[0], keys[1] = 7, 7 + 4999
+    assert run_pair(keys, None, cfg_preset=ahs.PRESET_MI355X_CALIBRATED) == ahs.COUNTING
+    keys[1] = 7 + 5000
+    assert run_pair(keys, None, cfg_preset=ahs.PRESET_MI355X_CALIBRATED) == ahs.QUICK
