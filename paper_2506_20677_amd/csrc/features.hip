@@ -343,7 +343,7 @@ __global__ __launch_bounds__(HIST_LARGE_THREADS) void k_hist_large(const typenam
     if ((p & PLAN_SKIP) || !(p & PLAN_LARGE)) return;
     kmin = (K)plan->min_key;
     shift = plan->shift;
-    ndig = DIG ? plan_digits(p) : 0;
+    ndig = DIG ? plan_fused_digits(p, shift) : 0;
   }
   ndig = ndig < DMAX ? ndig : DMAX;  // the counters hold one key's digits
   for (int i = threadIdx.x; i < HIST_LARGE_WORDS; i += HIST_LARGE_THREADS) h[i] = 0;
@@ -609,29 +609,104 @@ hipError_t launch_digit_hist(int kk, const void* keys, uint64_t n, uint64_t kmin
   return hipGetLastError();
 }
 
-// One workgroup per pass: four groups of 256 threads (one per digit) sum
-// interleaved quarters of the block partials with many loads in flight, the
-// groups are folded in LDS, and the pass's 256 counts are exclusively
-// scanned.
+// Counts of one radix digit summed from the reduced 65,536-bin histogram,
+// for a digit whose bits lie at q = 8p - shift >= 0 inside the bin: bins
+// come in runs of 2^q sharing the digit (run index) & 255.  Pieces of L
+// bins (a whole run when q <= 6, else 64 bins of one run) are summed in
+// registers, each lane taking 64 / L pieces with all its loads in flight;
+// lanes take consecutive pieces, so with L = 2^q the digits of a wave's
+// atomics are distinct.  The histogram buffer holds 65,536 counts: loads
+// past nbins stay inside it and are masked.
+template <int L>
+__device__ __forceinline__ void derived_digit_pieces(const uint32_t* __restrict__ hist, uint32_t nb, int q,
+                                                     uint32_t* __restrict__ cnt, int t) {
+  constexpr int NT = 1024;
+  constexpr int PIECES = 64 / L;  // 65,536 bins / NT threads / L
+  uint32_t acc[PIECES];
+  if constexpr (L >= 4) {
+    u32x4 w[PIECES][L / 4];
+#pragma unroll
+    for (int u = 0; u < PIECES; ++u) {
+      const u32x4* hv = reinterpret_cast<const u32x4*>(hist + (size_t)(t + u * NT) * L);
+#pragma unroll
+      for (int k = 0; k < L / 4; ++k) w[u][k] = hv[k];
+    }
+#pragma unroll
+    for (int u = 0; u < PIECES; ++u) {
+      const uint32_t b0 = (uint32_t)(t + u * NT) * L;
+      uint32_t a = 0;
+#pragma unroll
+      for (int k = 0; k < L / 4; ++k) {
+        const uint32_t b = b0 + 4 * k;
+        a += (b < nb ? w[u][k].x : 0u) + (b + 1 < nb ? w[u][k].y : 0u) + (b + 2 < nb ? w[u][k].z : 0u) +
+             (b + 3 < nb ? w[u][k].w : 0u);
+      }
+      acc[u] = a;
+    }
+  } else {
+    uint32_t v[PIECES][L];
+#pragma unroll
+    for (int u = 0; u < PIECES; ++u)
+#pragma unroll
+      for (int k = 0; k < L; ++k) v[u][k] = hist[(uint32_t)(t + u * NT) * L + k];
+#pragma unroll
+    for (int u = 0; u < PIECES; ++u) {
+      const uint32_t b0 = (uint32_t)(t + u * NT) * L;
+      uint32_t a = 0;
+#pragma unroll
+      for (int k = 0; k < L; ++k) a += b0 + k < nb ? v[u][k] : 0u;
+      acc[u] = a;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < PIECES; ++u)
+    if (acc[u]) atomicAdd(&cnt[(((uint32_t)(t + u * NT) * L) >> q) & 255u], acc[u]);
+}
+
+// One workgroup per pass.  A digit counted per key: four groups of 256
+// threads (one per digit) sum interleaved quarters of the block partials
+// with many loads in flight and are folded in LDS.  With a plan, a digit at
+// or above the histogram's shift is summed from the reduced histogram
+// instead (its value is a function of the bin; a wave whose 64 bins share
+// the digit adds once).  The pass's 256 counts are then exclusively scanned.
 constexpr int DIGIT_REDUCE_THREADS = 1024;
+static_assert(DIGIT_REDUCE_THREADS * 64 == 65536, "derived digits: 64 bins per thread");
 __global__ __launch_bounds__(DIGIT_REDUCE_THREADS) void k_digit_reduce(const uint32_t* __restrict__ parts,
+                                                                       const uint32_t* __restrict__ hist,
                                                                        int nblocks, int ndig,
                                                                        uint32_t* __restrict__ counts,
                                                                        uint32_t* __restrict__ offsets,
                                                                        const DevFeatures* __restrict__ plan) {
   constexpr int G = DIGIT_REDUCE_THREADS / 256;
   const int p = blockIdx.x, t = threadIdx.x, d = t % 256, g = t / 256;
+  int nf = ndig;  // digits the block partials hold
   if (plan) {
     if (plan->reserved & PLAN_SKIP) return;
     ndig = plan_digits(plan->reserved);
+    nf = plan_fused_digits(plan->reserved, plan->shift);
   }
   if (p >= ndig) return;  // uniform over the workgroup
-  uint32_t c = 0;
-#pragma unroll 16
-  for (int b = g; b < nblocks; b += G) c += parts[((size_t)b * ndig + p) * 256 + d];
   __shared__ uint32_t s_grp[G][256];
   __shared__ uint32_t s_scan[DIGIT_REDUCE_THREADS / WAVE + 1];
-  s_grp[g][d] = c;
+  uint32_t c = 0;
+  if (p < nf) {
+#pragma unroll 16
+    for (int b = g; b < nblocks; b += G) c += parts[((size_t)b * nf + p) * 256 + d];
+    s_grp[g][d] = c;
+  } else {
+    s_grp[g][d] = 0;
+    __syncthreads();
+    const int q = 8 * p - (int)plan->shift;  // 0 <= q <= 15: digit bits lie within the bin
+    switch (q < 6 ? q : 6) {
+      case 0: derived_digit_pieces<1>(hist, plan->nbins, q, s_grp[0], t); break;
+      case 1: derived_digit_pieces<2>(hist, plan->nbins, q, s_grp[0], t); break;
+      case 2: derived_digit_pieces<4>(hist, plan->nbins, q, s_grp[0], t); break;
+      case 3: derived_digit_pieces<8>(hist, plan->nbins, q, s_grp[0], t); break;
+      case 4: derived_digit_pieces<16>(hist, plan->nbins, q, s_grp[0], t); break;
+      case 5: derived_digit_pieces<32>(hist, plan->nbins, q, s_grp[0], t); break;
+      default: derived_digit_pieces<64>(hist, plan->nbins, q, s_grp[0], t); break;
+    }
+  }
   __syncthreads();
   if (t < 256) {
     c = 0;
@@ -646,9 +721,11 @@ __global__ __launch_bounds__(DIGIT_REDUCE_THREADS) void k_digit_reduce(const uin
   }
 }
 
-hipError_t launch_digit_reduce(const uint32_t* digit_partials, int nblocks, int ndig, uint32_t* counts,
-                               uint32_t* offsets, hipStream_t s, const DevFeatures* plan) {
-  k_digit_reduce<<<plan ? 8 : ndig, DIGIT_REDUCE_THREADS, 0, s>>>(digit_partials, nblocks, ndig, counts, offsets, plan);
+hipError_t launch_digit_reduce(const uint32_t* digit_partials, const uint32_t* hist, int nblocks, int ndig,
+                               uint32_t* counts, uint32_t* offsets, hipStream_t s, const DevFeatures* plan) {
+  if (plan && !hist) return hipErrorInvalidValue;  // derived digits read the reduced histogram
+  k_digit_reduce<<<plan ? 8 : ndig, DIGIT_REDUCE_THREADS, 0, s>>>(digit_partials, hist, nblocks, ndig, counts,
+                                                                   offsets, plan);
   return hipGetLastError();
 }
 

@@ -95,6 +95,14 @@ constexpr uint32_t PLAN_ON = 1u << 31;
 constexpr uint32_t PLAN_LARGE = 1u;  // the 65,536-bin packed histogram (else the exact small one)
 constexpr uint32_t PLAN_SKIP = 2u;   // no histogram needed
 inline __host__ __device__ int plan_digits(uint32_t plan) { return (int)((plan >> 4) & 15u); }
+// Of those digits, the ones the fused histogram counts per key: digit p
+// (bits 8p .. 8p+7 of key - min) with 8p >= shift is (bin >> (8p - shift))
+// & 255 for the key's histogram bin, so its counts follow from the reduced
+// histogram; only the digits below the shift need a count per key.
+inline __host__ __device__ int plan_fused_digits(uint32_t plan, uint32_t shift) {
+  const int below = (int)((shift + 7u) / 8u);
+  return plan_digits(plan) < below ? plan_digits(plan) : below;
+}
 struct FeaturePlanCfg {
   uint64_t kcount_minus1, k_radix, n_small;
   uint32_t enabled, model, want_hist, pad;
@@ -127,7 +135,7 @@ hipError_t launch_digit_hist(int kk, const void* keys, uint64_t n, uint64_t kmin
                              uint32_t* digit_partials, int nblocks, hipStream_t s);
 // Sums per-block digit counts into counts[ndig][256] and their exclusive
 // scans into offsets[ndig][256].
-hipError_t launch_digit_reduce(const uint32_t* digit_partials, int nblocks, int ndig,
+hipError_t launch_digit_reduce(const uint32_t* digit_partials, const uint32_t* hist, int nblocks, int ndig,
                                uint32_t* counts, uint32_t* offsets, hipStream_t s,
                                const DevFeatures* plan = nullptr);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t count, uint64_t value, hipStream_t s);

@@ -67,7 +67,7 @@ static ahs_status step_hist(SortJob& j, uint32_t* hist_out, int ndig_fused) {
   }
   if (ndig_fused > 0) {
     ProfScope p(j.ctx, "digit_reduce", j.s);
-    AHS_HIP(j, launch_digit_reduce(at<uint32_t>(j.ws, j.L.dparts), groups, ndig_fused,
+    AHS_HIP(j, launch_digit_reduce(at<uint32_t>(j.ws, j.L.dparts), nullptr, groups, ndig_fused,
                                    at<uint32_t>(j.ws, j.L.dcounts), at<uint32_t>(j.ws, j.L.doffs), j.s),
             "digit reduce");
   }
@@ -116,7 +116,8 @@ static ahs_status step_features_auto(SortJob& j, const ahs_config& c, bool model
   {
     ProfScope p(j.ctx, "digit_reduce", j.s);
     AHS_HIP(j,
-            launch_digit_reduce(at<uint32_t>(j.ws, j.L.dparts), gl, 0, at<uint32_t>(j.ws, j.L.dcounts),
+            launch_digit_reduce(at<uint32_t>(j.ws, j.L.dparts), at<uint32_t>(j.ws, j.L.hist), gl, 0,
+                                at<uint32_t>(j.ws, j.L.dcounts),
                                 at<uint32_t>(j.ws, j.L.doffs), j.s, df),
             "digit reduce");
   }
@@ -177,7 +178,7 @@ static ahs_status run_radix(SortJob& j, const std::vector<uint32_t>* ready_count
       AHS_HIP(j, launch_digit_hist(j.kk, j.kin, j.n, j.f.min_key, ndig, at<uint32_t>(j.ws, j.L.dparts), nb, j.s),
               "digit histogram");
     }
-    AHS_HIP(j, launch_digit_reduce(at<uint32_t>(j.ws, j.L.dparts), nb, ndig, at<uint32_t>(j.ws, j.L.dcounts),
+    AHS_HIP(j, launch_digit_reduce(at<uint32_t>(j.ws, j.L.dparts), nullptr, nb, ndig, at<uint32_t>(j.ws, j.L.dcounts),
                                    at<uint32_t>(j.ws, j.L.doffs), j.s),
             "digit reduce");
     char* pin = static_cast<char*>(j.ctx->pinned);

@@ -42,15 +42,15 @@ def workloads(max_log2n):
             out.append(("u32", lg, "fewvals32", m))
         out.append(("u32", lg, "sorted", 1 << 32))
         out.append(("u32", lg, "reverse", 1 << 32))
-        if lg <= max_log2n - 2:
-            for k in (1 << 16, 1 << 32, 1 << 48, 1 << 64):
-                out.append(("u64", lg, "uniform", k))
-            out.append(("u64", lg, "zipf1.0", 4096))
-            for bits in (40, 60, 64):
-                for m in (4, 16, 256):
-                    out.append(("u64", lg, f"fewvals{bits}", m))
-            out.append(("f32", lg, "normal", 0))
-            out.append(("f64", lg, "normal", 0))
+        # 64-bit and float keys at the same sizes (2^28 u64 keys = 2 GiB)
+        for k in (1 << 16, 1 << 32, 1 << 48, 1 << 64):
+            out.append(("u64", lg, "uniform", k))
+        out.append(("u64", lg, "zipf1.0", 4096))
+        for bits in (40, 60, 64):
+            for m in (4, 16, 256):
+                out.append(("u64", lg, f"fewvals{bits}", m))
+        out.append(("f32", lg, "normal", 0))
+        out.append(("f64", lg, "normal", 0))
     return out
 
 
