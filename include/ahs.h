@@ -21,13 +21,16 @@
  *     keys are ordered by an order-preserving bit map (sign bit set: flip all
  *     bits; clear: set the sign bit), so -0.0 sorts before +0.0, -inf first
  *     and +inf last; NaN is rejected with AHS_E_NAN.  The paper accepts only
- *     integers (Sec. III-K); floats are this library's extension.
+ *     integers (Sec. III-K); floats are this library's extension.  Signed
+ *     integer keys (AHS_I32, AHS_I64) are ordered by their value through a
+ *     flip of the sign bit.
  *   - Payloads are optional uint32 arrays permuted with the keys.  Every
  *     strategy is stable, so the payload result is unique.
  *   - `stream` is a hipStream_t passed as void* (0 = the null stream).  Calls
  *     that must decide on the host (AUTO, float NaN checks, radix pass
  *     planning) synchronise that stream once or twice; the others only
- *     enqueue work.
+ *     enqueue work.  AUTO on integer keys with n <= n_small and no feature
+ *     request only enqueues: that state depends on n alone.
  *   - `d_ws` is caller-provided device scratch of at least
  *     ahs_workspace_bytes(...) bytes, 256-byte aligned.  The library never
  *     allocates device memory inside a sort call.
