@@ -262,19 +262,22 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_scatter(SsScatterArgs a) {
   constexpr int NW = SS_THREADS / WAVE;
   // One LDS region holds in turn the rank slots, the dense per-(wave,
   // bucket) position table (written once every slot count has been read,
-  // after the scan's first barrier) and the staged keys (once every key's
-  // tile position is in a register).
+  // after the scan's first barrier) and the staged keys with their bucket
+  // ids (once every key's tile position is in a register).  Sharing it keeps
+  // a u32 tile near 75 KiB, so two tiles fit in a CU's LDS.
   constexpr size_t SLOT_BYTES = sizeof(RankSlot) * NW * SS_NB;
   constexpr size_t KEY_BYTES = sizeof(K) * TILE;
+  constexpr size_t STAGE_BYTES = KEY_BYTES + sizeof(uint16_t) * TILE;
   static_assert(sizeof(uint32_t) * NW * SS_NB <= SLOT_BYTES, "position table fits over the slots");
-  __shared__ __align__(16) unsigned char s_raw[SLOT_BYTES > KEY_BYTES ? SLOT_BYTES : KEY_BYTES];
+  static_assert(KEY_BYTES % 16 == 0, "bucket ids start aligned after the keys");
+  __shared__ __align__(16) unsigned char s_raw[SLOT_BYTES > STAGE_BYTES ? SLOT_BYTES : STAGE_BYTES];
   RankSlot(*s_slot)[SS_NB] = reinterpret_cast<RankSlot(*)[SS_NB]>(s_raw);
   uint32_t(*s_pos)[SS_NB] = reinterpret_cast<uint32_t(*)[SS_NB]>(s_raw);
   K* s_keys = reinterpret_cast<K*>(s_raw);
+  uint16_t* s_dig = reinterpret_cast<uint16_t*>(s_raw + KEY_BYTES);
   __shared__ uint32_t s_dadj[SS_NB];  // segment-relative position of tile key j with id b: s_dadj[b] + j
   __shared__ K s_spl[256];
   __shared__ uint32_t s_vals[PAY ? TILE : 1];
-  __shared__ uint16_t s_dig[TILE];
   __shared__ uint32_t s_scan[NW + 1];
   __shared__ uint32_t s_tile;
 
