@@ -145,12 +145,29 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_count(const typename KeyTrait
         const uint32_t idx = b0 + (uint32_t)i * SS_THREADS + t;
         x[i] = p[idx < cnt ? idx : cnt - 1];
       }
+      // all binary searches first (their LDS reads overlap), then the counts
+      uint32_t bk[IPT];
 #pragma unroll
       for (int i = 0; i < IPT; ++i) {
-        const uint32_t idx = b0 + (uint32_t)i * SS_THREADS + t;
         K y = x[i];
         if constexpr (key_mapped<KK>) y = map_in ? map_key<KK>(y) : y;
-        if (idx < cnt) atomicAdd(&s_cnt[ss_classify<K>(y, s_spl)], 1u);
+        bk[i] = ss_classify<K>(y, s_spl);
+      }
+#pragma unroll
+      for (int i = 0; i < IPT; ++i) {
+        const bool ok = b0 + (uint32_t)i * SS_THREADS + t < cnt;
+        // sorted or run-structured keys put a wave's keys in one bucket,
+        // where 64 atomics on one LDS word serialise.  A wave whose first
+        // and last lanes share a bucket (a scalar test that random keys
+        // almost never pass) adds the lanes of that bucket through its
+        // lowest lane; every other key adds 1.  No branch: each lane's
+        // increment (0, 1 or the run) masks the one atomic.
+        const uint32_t b_first = __builtin_amdgcn_readfirstlane(bk[i]);
+        const bool lead = b_first == __builtin_amdgcn_readlane(bk[i], WAVE - 1);
+        const bool in_run = lead && ok && bk[i] == b_first;
+        const uint64_t run = __ballot(in_run);
+        const uint32_t inc = in_run ? (mbcnt(run) == 0 ? popc64(run) : 0u) : (ok ? 1u : 0u);
+        if (inc) atomicAdd(&s_cnt[bk[i]], inc);
       }
     }
   }

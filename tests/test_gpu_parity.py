@@ -604,3 +604,32 @@ def test_calibrated_preset_decisions():
     assert run_pair(keys, None, cfg_preset=ahs.PRESET_MI355X_CALIBRATED) == ahs.COUNTING
     keys[1] = 7 + 5000
     assert run_pair(keys, None, cfg_preset=ahs.PRESET_MI355X_CALIBRATED) == ahs.QUICK
+
+
+@pytest.mark.parametrize("span_bits,nvals,dt", [(13, 30, np.uint32), (21, 200, np.uint32), (32, 300, np.uint32),
+                                                (27, 100, np.uint64), (61, 13, np.uint64)])
+def test_auto_radix_digits_from_histogram(span_bits, nvals, dt):
+    """AUTO to radix on few values over spans of 2^13 (exact histogram, shift
+    0: every digit summed from the bins), 2^21 (shift 5: digit 0 counted per
+    key, digits 1 and 2 from runs of 8 and 2,048 bins), 2^32, 2^27 and 2^61
+    (u64, shift 45: digits 6 and 7 from the bins): keys, payload and the
+    decision equal the oracle's."""
+    r = np.random.default_rng(span_bits)
+    hi = (1 << span_bits) - 1
+    vals = r.integers(0, hi, nvals, dtype=np.uint64, endpoint=True)
+    vals[0], vals[1] = 0, hi
+    keys = (vals[r.integers(0, nvals, 300_007)] + np.uint64(12345)).astype(dt)  # wraps for 2^32: still radix
+    preset = 0
+    if span_bits == 13:
+        # lower the radix threshold so a span below 2^16 reaches the radix test
+        cfg = ahs.ahs_config_init(0, k_count=100, k_radix=1000)
+        ocfg = O.config(0, k_count=100, k_radix=1000)
+        k = to_dev(keys)
+        ko, vo, ch, f = ahs.ahs_sort(k, to_dev(np.arange(keys.size, dtype=np.uint32)), ahs.AUTO, cfg,
+                                     want_features=True)
+        st, rk, rv, rch, rf = O.sort(keys, np.arange(keys.size, dtype=np.uint32), O.AUTO, ocfg)
+        assert st == O.OK and rch == O.RADIX and ch == ahs.RADIX and f.shift == 0
+        assert np.array_equal(bits(ko.cpu().numpy()), bits(rk)) and np.array_equal(vo.cpu().numpy(), rv)
+        return
+    assert run_pair(keys, np.arange(keys.size, dtype=np.uint32), cfg_preset=preset) == ahs.RADIX
+    assert run_pair(keys, None, cfg_preset=preset) == ahs.RADIX
