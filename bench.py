@@ -377,7 +377,7 @@ def parse():
     ap.add_argument("--cases", action=argparse.BooleanOptionalAction, default=True,
                     help="per-array AUTO vs forced strategies")
     ap.add_argument("--cpu-baseline", action=argparse.BooleanOptionalAction, default=True)
-    ap.add_argument("--cpu-sample-log2", type=int, default=22,
+    ap.add_argument("--cpu-sample-log2", type=int, default=27,
                     help="keys of each array the oracle sorts for the CPU baseline")
     ap.add_argument("--only", default=None, help="comma list of sweep cases to run")
     ap.add_argument("--calib-copy", action="store_true",
