@@ -38,6 +38,10 @@ def say(*a):
 
 def as_ordered_int64(t):
     """Device keys as int64 values whose signed order is the keys' sort order."""
+    if t.dtype == torch.int32:
+        return t.to(torch.int64)
+    if t.dtype == torch.int64:
+        return t
     if t.dtype == torch.uint32:
         return t.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
     if t.dtype == torch.uint64:
@@ -115,6 +119,26 @@ def test_wide_keys_full_size_with_payload(case, selector):
     assert st == O.OK and chosen == rchosen, (chosen, rchosen)
     check_sorted_permutation(k, out, vout)
     say(f"full-size wide {case}: {ahs.STRATEGY_NAMES[chosen]} ok")
+
+
+@pytest.mark.parametrize("case", ["i32_uniform", "i64_uniform", "gauss_k1e6", "taxi_like", "kmer_like"])
+def test_paper_families_full_size_with_payload(case, selector):
+    """The paper's families at the sizes the benchmark's paper sweep runs
+    (2^24 keys, 10^7 for the taxi stand-in, 10^8 u64 for the k-mer one),
+    signed keys included, through AUTO with the selector and a payload."""
+    ctx, cfg = selector
+    keys = gen.paper_sweep(case)
+    n = keys.size
+    say(f"full-size paper family {case}: {n} keys {keys.dtype}")
+    k = torch.from_numpy(keys).to(DEV)
+    v = torch.arange(n, dtype=torch.int32, device=DEV).view(torch.uint32)
+    out, vout, chosen, f = ahs.ahs_sort(k, v, strategy=ahs.AUTO, cfg=cfg, ctx=ctx, want_features=True)
+    torch.cuda.synchronize()
+    rf = check_features_vs_oracle(f, keys)
+    st, rchosen = O.select(rf, O.config(0, use_model=1), O.Model(ahs.SELECTOR_MODEL))
+    assert st == O.OK and chosen == rchosen, (chosen, rchosen)
+    check_sorted_permutation(k, out, vout)
+    say(f"full-size paper family {case}: {ahs.STRATEGY_NAMES[chosen]} ok")
 
 
 def test_batched_full_size_graph():
