@@ -8,22 +8,33 @@ unsorted, sorted, reversed and sorted with n/200 random transpositions
 (general path).  One step sorts all six with AHS AUTO (features, decision,
 the chosen sort); inputs are resident in HBM before the timed region.
 
-Prints one JSON line: whole-job Gkeys/s, the dominant kernel's roofline
-(algorithmic bytes per launch over its average launch time, both measured
-with HIP events on the launch stream), the CPU oracle on a bounded sample,
-and per-array AUTO-vs-forced-strategy timings with %HBM of each path.
+The last stdout line is one compact JSON object (under 4 KB): whole-job
+Gkeys/s, the dominant kernel's roofline (algorithmic bytes per launch over
+its average launch time, both measured with HIP events on the launch
+stream), the CPU oracle on a bounded sample (one pinned core, median of
+runs) and a few summary figures per section.  Every section in full goes to
+--detail-out (and to stderr).
 
-Three further sections, reported beside the headline (not in `value`):
+Sections reported beside the headline (not in `value`):
+* per_case: each sweep array under AUTO and each forced strategy, %HBM of
+  each path.
+* pr1: 10^6 uint32 keys on [0, 1023]: AUTO, forced RADIX and QUICK, keys
+  only and with payload, checked bitwise against the oracle, whose own time
+  is reported.
+* wide: 2^27 u64 uniform, u64 Zipf(1.0) over 4,096 values, f32 and f64
+  Normal(0, 1e3) with duplicates and signed zeros; AUTO against forced
+  RADIX and QUICK, keys only and with payload = index.
 * paper_sweep: the paper's dataset families (uniform, rounded Gaussian as
   signed keys, Zipf(1.5), edge patterns, full-range signed keys, stand-ins
   with the (n, k, H) of its real datasets); AUTO against each forced strategy.
 * batched: 65,536 uint32 segments, sizes log-uniform on [16, 2^20] (about
   6.2e9 keys), distributions mixed per segment; the autotuned, graph-captured
   batched sort against a host loop of per-array AHS AUTO calls.
-* serving: Poisson arrivals at 2,000 requests/s, sizes log-uniform on
-  [2^10, 2^24], key types u32/u64/f32, half with payload, 48 GB admission
+* serving: Poisson arrivals at 2,000 requests/s for 60 s, sizes log-uniform
+  on [2^10, 2^24], key types u32/u64/f32, half with payload, 48 GB admission
   budget; the serving loop against one-at-a-time AHS AUTO on one stream, in
-  real time (latency p50/p99) and as a burst (throughput).
+  real time (latency p50/p99) and as a burst of the trace's first seconds
+  (throughput).
 """
 import argparse
 import json
@@ -199,7 +210,11 @@ def serving_section(args, ahs, gen, torch, np):
         _, kind, off, n, pay = r
         return pools[kind][off:off + n], (pay_pool[off:off + n] if pay else None)
 
+    burst_reqs = [r for r in reqs if r[0] < args.burst_seconds * 1e3]
+
     def served(burst):
+        rs = burst_reqs if burst else reqs
+        m = len(rs)
         srv = ahs.Server(hbm_budget_bytes=int(args.serve_budget_gb * 1e9), slots=args.serve_slots, autotune=True)
         start = srv.now_ms() + 20.0
         i, outstanding, done = 0, 0, 0
@@ -207,9 +222,9 @@ def serving_section(args, ahs, gen, torch, np):
         #            would allocate device memory, which synchronises the device)
         while i < m or outstanding:
             now = srv.now_ms()
-            while i < m and (burst or start + reqs[i][0] <= now):
-                k, v = view(reqs[i])
-                srv.submit(k, v, arrival_ms=start if burst else start + reqs[i][0])
+            while i < m and (burst or start + rs[i][0] <= now):
+                k, v = view(rs[i])
+                srv.submit(k, v, arrival_ms=start if burst else start + rs[i][0])
                 i += 1
                 outstanding += 1
             for r in srv.poll(wait_ms=0.0 if i < m else 50.0):
@@ -232,12 +247,13 @@ def serving_section(args, ahs, gen, torch, np):
             srv.release(r["id"])
         checked = len(held)
         srv.close()
-        return {"p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3), "max_ms": round(st["max_ms"], 3),
-                "gkeys_s": round(st["gkeys_per_s"], 3), "batches": st["batches"],
+        return {"requests": m, "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+                "max_ms": round(st["max_ms"], 3), "gkeys_s": round(st["gkeys_per_s"], 3), "batches": st["batches"],
                 "mean_batch_requests": round(st["mean_batch_requests"], 2),
                 "arena_peak_GB": round(st["arena_peak_bytes"] / 1e9, 3), "spot_checked": checked}
 
     def plain(burst):
+        rs = burst_reqs if burst else reqs
         ctx = ahs.default_context(0)
         ctx.workspace(ahs.ahs_workspace_bytes(1 << 24, ahs.U64, True, ahs.AUTO))
         out_k = torch.empty(1 << 24, dtype=torch.int64, device=dev)
@@ -245,7 +261,7 @@ def serving_section(args, ahs, gen, torch, np):
         torch.cuda.synchronize()
         t0 = time.perf_counter() * 1e3 + 20.0
         lat, last = [], 0.0
-        for r in reqs:
+        for r in rs:
             a = t0 if burst else t0 + r[0]
             while time.perf_counter() * 1e3 < a:
                 pass
@@ -257,13 +273,15 @@ def serving_section(args, ahs, gen, torch, np):
             last = time.perf_counter() * 1e3
             lat.append(last - a)
         del out_k, out_v
-        return {"p50_ms": round(percentile(lat, 50), 3), "p99_ms": round(percentile(lat, 99), 3),
-                "max_ms": round(max(lat), 3), "gkeys_s": round(total_keys / ((last - t0) * 1e-3) / 1e9, 3)}
+        keys_done = sum(r[3] for r in rs)
+        return {"requests": len(rs), "p50_ms": round(percentile(lat, 50), 3), "p99_ms": round(percentile(lat, 99), 3),
+                "max_ms": round(max(lat), 3), "gkeys_s": round(keys_done / ((last - t0) * 1e-3) / 1e9, 3)}
 
     res = {"workload": f"Poisson arrivals 2000/s for {args.serve_seconds}s ({m} requests, {total_keys} keys), "
                        "sizes log-uniform on [2^10, 2^24], u32/u64/f32 (uniform or Zipf(1.0) over 4,096 values; "
                        f"f32 Normal), half with payload; budget {args.serve_budget_gb} GB, {args.serve_slots} slots",
-           "offered_gkeys_s": round(total_keys / args.serve_seconds / 1e9, 3)}
+           "offered_gkeys_s": round(total_keys / args.serve_seconds / 1e9, 3),
+           "burst": f"the first {args.burst_seconds}s of the trace ({len(burst_reqs)} requests) submitted at once"}
     modes = args.serve_modes.split(",")
     for mode, burst in (("realtime", False), ("burst", True)):
         for kind, fn in (("served", served), ("plain", plain)):
@@ -367,6 +385,170 @@ def paper_sweep_section(args, ahs, gen, torch, np):
             "cases": rows}
 
 
+def _timed_sort(ahs, torch, keys, values, strat, cfg, out, out_v, ctx, reps):
+    """Median wall time of `reps` AHS calls (the first, untimed, warms up),
+    with the algorithmic bytes of one call's kernels and the chosen strategy."""
+    times, path_bytes, ch = [], None, None
+    for r in range(reps + 1):
+        ahs.ahs_profile_enable(ctx, True)
+        ahs.ahs_profile_reset(ctx)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        _, _, ch, _ = ahs.ahs_sort(keys, values, strategy=strat, cfg=cfg, out=out, out_values=out_v, ctx=ctx)
+        torch.cuda.synchronize()
+        if r:
+            times.append(time.perf_counter() - a)
+        path_bytes = sum(v[2] for v in ahs.ahs_profile_dump(ctx).values())
+        ahs.ahs_profile_enable(ctx, False)
+    return statistics.median(times), path_bytes, ch
+
+
+def _ordered(torch, x):
+    """Keys as int64 whose signed order is the sort order of the dtype (for
+    the on-device order check of a result)."""
+    if x.dtype == torch.uint32:
+        return x.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+    if x.dtype == torch.float32:
+        b = x.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+        return torch.where(b >= 2 ** 31, (2 ** 32 - 1) - b, b + 2 ** 31)
+    if x.dtype == torch.float64:
+        b = x.view(torch.int64)
+        return torch.where(b < 0, ~b, b ^ (-(2 ** 63))) ^ (-(2 ** 63))
+    if x.dtype == torch.uint64:
+        return x.view(torch.int64) ^ (-(2 ** 63))
+    return x.to(torch.int64)
+
+
+def strategy_table(reps, ahs, torch, keys, with_payload, strategies, ctx):
+    """AUTO and forced strategies on one device array: median ms, Gkeys/s,
+    path %HBM, and whether every strategy produced the same bytes."""
+    n = keys.numel()
+    vals = torch.arange(n, dtype=torch.int32, device=keys.device).view(torch.uint32) if with_payload else None
+    out = torch.empty_like(keys)
+    out_v = torch.empty_like(vals) if with_payload else None
+    row, ref, ref_v = {}, None, None
+    for sname, strat, cfg in strategies:
+        try:
+            med, pb, ch = _timed_sort(ahs, torch, keys, vals, strat, cfg, out, out_v, ctx, reps)
+        except ahs.AhsError as e:
+            ahs.ahs_profile_enable(ctx, False)
+            row[sname] = {"status": e.status}
+            continue
+        if ref is None:
+            ref, ref_v = out.clone(), (out_v.clone() if with_payload else None)
+            x = _ordered(torch, out)
+            row["sorted_ok"] = bool((x[1:] >= x[:-1]).all().item())
+            del x
+            agree = True
+        else:
+            agree = bool(torch.equal(ref.view(torch.uint8), out.view(torch.uint8)))
+            if with_payload:
+                agree = agree and bool(torch.equal(ref_v.view(torch.int32), out_v.view(torch.int32)))
+        row[sname] = {"ms": round(med * 1e3, 4), "Gkeys_s": round(n / med / 1e9, 2),
+                      "chosen": ahs.STRATEGY_NAMES[ch], "path_GB": round(pb / 1e9, 3),
+                      "hbm_frac_path": round(pb / med / 1e9 / HBM_PEAK_GBS, 4), "agrees": agree}
+    forced = {k: row[k]["ms"] for k in ("counting", "radix", "quick") if "ms" in row.get(k, {})}
+    if forced:
+        best = min(forced, key=forced.get)
+        row["best_forced"] = best
+        for a in ("auto", "auto_fsm"):
+            if "ms" in row.get(a, {}):
+                row[f"{a}_over_best"] = round(row[a]["ms"] / forced[best], 4)
+    del vals, out, out_v, ref, ref_v
+    return row
+
+
+def _pin_one_core():
+    """Pins this process to one core for the single-threaded oracle; returns
+    the previous affinity (to restore) and the core."""
+    old = os.sched_getaffinity(0)
+    core = max(old)
+    os.sched_setaffinity(0, {core})
+    return old, core
+
+
+def pr1_section(args, ahs, gen, torch, np):
+    """PR1: 10^6 uint32 keys uniform on [0, 1023] (seed 0): AUTO, forced
+    RADIX and forced QUICK, keys only and with payload = index, each checked
+    bitwise against the CPU oracle; the oracle timed on one pinned core."""
+    import oracle
+    dev = torch.device("cuda:0")
+    ctx = ahs.default_context(0)
+    ctx.set_model(ahs.default_model())
+    keys_h = gen.pr1()
+    keys = torch.from_numpy(keys_h).to(dev)
+    n = keys.numel()
+    cfg = ahs.ahs_config_init(ahs.PRESET_GPU)
+    cfg_m = ahs.ahs_config_init(ahs.PRESET_GPU, use_model=1)
+    strategies = (("auto", ahs.AUTO, cfg_m), ("auto_fsm", ahs.AUTO, cfg), ("counting", ahs.COUNTING, cfg),
+                  ("radix", ahs.RADIX, cfg), ("quick", ahs.QUICK, cfg))
+    res = {"workload": "PR1: 1,000,000 uint32 keys uniform on [0, 1023] (seed 0)", "n": n}
+    vals_h = np.arange(n, dtype=np.uint32)
+    exact = True
+    for pay in (False, True):
+        tab = strategy_table(max(args.reps, 10), ahs, torch, keys, pay, strategies, ctx)
+        # bitwise against the oracle for AUTO, RADIX and QUICK
+        for sname, strat in (("auto_fsm", ahs.AUTO), ("radix", ahs.RADIX), ("quick", ahs.QUICK)):
+            v = torch.from_numpy(vals_h).to(dev) if pay else None
+            ko, vo, ch, _ = ahs.ahs_sort(keys, v, strategy=strat, cfg=cfg, ctx=ctx)
+            st, rk, rv, rch, _ = oracle.sort(keys_h, vals_h if pay else None, strat)
+            ok = st == 0 and np.array_equal(ko.cpu().numpy(), rk) and ch == rch
+            if pay:
+                ok = ok and np.array_equal(vo.cpu().numpy(), rv)
+            tab[sname]["oracle_exact"] = bool(ok)
+            exact = exact and ok
+        res["with_payload" if pay else "keys_only"] = tab
+    old, core = _pin_one_core()
+    try:
+        for sname, strat in (("auto", oracle.AUTO), ("radix", oracle.RADIX), ("quick", oracle.QUICK)):
+            ts = []
+            for _ in range(10):
+                a = time.perf_counter()
+                st, _, _, _, _ = oracle.sort(keys_h, None, strat)
+                ts.append(time.perf_counter() - a)
+            res.setdefault("oracle_ms", {})[sname] = round(statistics.median(ts) * 1e3, 3)
+    finally:
+        os.sched_setaffinity(0, old)
+    res["oracle_core"] = core
+    res["all_oracle_exact"] = exact
+    log(f"[bench] pr1 {json.dumps(res)}")
+    del keys
+    torch.cuda.empty_cache()
+    return res
+
+
+def wide_section(args, ahs, gen, torch, np):
+    """Wide and floating keys at 2^27: u64 uniform, u64 Zipf(1.0) over 4,096
+    values, f32 and f64 Normal(0, 1e3) with duplicates and signed zeros; AUTO
+    against forced RADIX and QUICK, keys only and with payload = index."""
+    dev = torch.device("cuda:0")
+    ctx = ahs.default_context(0)
+    ctx.set_model(ahs.default_model())
+    cfg = ahs.ahs_config_init(ahs.PRESET_GPU)
+    cfg_m = ahs.ahs_config_init(ahs.PRESET_GPU, use_model=1)
+    strategies = (("auto", ahs.AUTO, cfg_m), ("auto_fsm", ahs.AUTO, cfg), ("radix", ahs.RADIX, cfg),
+                  ("quick", ahs.QUICK, cfg))
+    n = 1 << args.wide_log2n
+    rows = []
+    for case in gen.WIDE_CASES:
+        t = time.time()
+        keys = torch.from_numpy(gen.wide_keys(case, n=n)).to(dev)
+        for pay in (False, True):
+            row = {"case": case, "payload": pay, "n": n}
+            row.update(strategy_table(args.reps, ahs, torch, keys, pay, strategies, ctx))
+            rows.append(row)
+            log(f"[bench] wide {case} payload={pay} in {time.time() - t:.1f}s: " + json.dumps(row))
+        del keys
+        torch.cuda.empty_cache()
+    ratios = [r["auto_over_best"] for r in rows if "auto_over_best" in r]
+    return {"workload": f"wide keys, 2^{args.wide_log2n} per array: " + ", ".join(gen.WIDE_CASES) +
+                        "; keys only and with payload = index",
+            "auto_over_best_max": max(ratios), "all_sorted_and_agreeing":
+                all(r["sorted_ok"] and all(r[k].get("agrees", True) for k in ("auto", "auto_fsm", "radix", "quick"))
+                    for r in rows),
+            "cases": rows}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -377,8 +559,16 @@ def parse():
     ap.add_argument("--cases", action=argparse.BooleanOptionalAction, default=True,
                     help="per-array AUTO vs forced strategies")
     ap.add_argument("--cpu-baseline", action=argparse.BooleanOptionalAction, default=True)
-    ap.add_argument("--cpu-sample-log2", type=int, default=27,
+    ap.add_argument("--cpu-sample-log2", type=int, default=26,
                     help="keys of each array the oracle sorts for the CPU baseline")
+    ap.add_argument("--cpu-runs", type=int, default=3, help="oracle runs for the CPU baseline median")
+    ap.add_argument("--pr1", action=argparse.BooleanOptionalAction, default=True,
+                    help="PR1: 10^6 keys on [0, 1023], AUTO vs forced RADIX/QUICK, against the oracle")
+    ap.add_argument("--wide", action=argparse.BooleanOptionalAction, default=True,
+                    help="wide and floating keys: AUTO vs forced strategies, keys only and with payload")
+    ap.add_argument("--wide-log2n", type=int, default=27)
+    ap.add_argument("--detail-out", default=os.path.join("gpurun_out", "bench_detail.json"),
+                    help="file that receives every section in full (the stdout line carries summaries)")
     ap.add_argument("--only", default=None, help="comma list of sweep cases to run")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain elementwise copy of 2^log2n 32-bit words first (counter calibration)")
@@ -392,8 +582,10 @@ def parse():
     ap.add_argument("--seg-loop", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the host loop of per-array calls over the same segments")
     ap.add_argument("--serve", action=argparse.BooleanOptionalAction, default=True)
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="seconds of the Poisson request trace replayed in real time")
+    ap.add_argument("--burst-seconds", type=float, default=10.0,
+                    help="seconds of the same trace submitted at once (throughput runs)")
     ap.add_argument("--serve-budget-gb", type=float, default=48.0)
     ap.add_argument("--serve-slots", type=int, default=4, help="stream slots of the server")
     ap.add_argument("--serve-modes", default="served,plain", help="which serving runs: served, plain or both")
@@ -562,8 +754,10 @@ def main():
                               "path_GB": round(path_bytes / 1e9, 3),
                               "hbm_frac_path": round(path_bytes / med / 1e9 / HBM_PEAK_GBS, 4),
                               "agrees": agree, "kernels": {k: [v[0], round(v[1], 4)] for k, v in p.items()}}
-            best = min((row[k]["ms"] for k in ("counting", "radix", "quick") if "ms" in row.get(k, {})),
-                       default=None)
+            forced = {k: row[k]["ms"] for k in ("counting", "radix", "quick") if "ms" in row.get(k, {})}
+            best = min(forced.values(), default=None)
+            if forced:
+                row["best_forced"] = min(forced, key=forced.get)
             if best and "ms" in row.get("auto", {}):
                 row["auto_over_best"] = round(row["auto"]["ms"] / best, 4)
             if best and "ms" in row.get("auto_fsm", {}):
@@ -578,26 +772,35 @@ def main():
         import oracle
 
         m = min(n, 1 << args.cpu_sample_log2)
-        tot_t, tot_k = 0.0, 0
         omodel = oracle.Model(ahs.SELECTOR_MODEL)
         ocfg = oracle.config(0, use_model=1)
-        for c in cases:
-            sample = np.ascontiguousarray(host[c][:m])
-            a = time.perf_counter()
-            st, _, _, _, _ = oracle.sort(sample, None, oracle.AUTO, ocfg, omodel)
-            tot_t += time.perf_counter() - a
-            tot_k += m
-            if st != 0:
-                log(f"[bench] oracle status {st} on {c}")
-        cpu = {"value": round(tot_k / tot_t / 1e9, 6), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+        samples = [np.ascontiguousarray(host[c][:m]) for c in cases]
+        old_aff, core = _pin_one_core()
+        runs = []
+        try:
+            for _ in range(args.cpu_runs):
+                a = time.perf_counter()
+                for c, sample in zip(cases, samples):
+                    st, _, _, _, _ = oracle.sort(sample, None, oracle.AUTO, ocfg, omodel)
+                    if st != 0:
+                        log(f"[bench] oracle status {st} on {c}")
+                runs.append(time.perf_counter() - a)
+        finally:
+            os.sched_setaffinity(0, old_aff)
+        med = statistics.median(runs)
+        tot_k = m * len(cases)
+        cpu = {"value": round(tot_k / med / 1e9, 6), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
                "sample": f"first 2^{int(np.log2(m))} keys of each of the {len(cases)} arrays, AHS AUTO "
-                         f"(FSM + the same selector model), single-threaded C oracle, {tot_t:.1f} s total",
+                         f"(FSM + the same selector model), single-threaded C oracle pinned to core {core}, "
+                         f"median of {len(runs)} runs of {med:.1f} s",
                **host_info()}
         log(f"[bench] cpu baseline {cpu}")
 
-    # ------------------------------------------------------------ batched and serving sections
+    # ------------------------------------------------------------ other configurations
     del dkeys, out, host
     torch.cuda.empty_cache()
+    pr1 = pr1_section(args, ahs, gen, torch, np) if args.pr1 else None
+    wide = wide_section(args, ahs, gen, torch, np) if args.wide else None
     paper = paper_sweep_section(args, ahs, gen, torch, np) if args.paper_sweep else None
     batched = batched_section(args, ahs, gen, torch, np) if args.batched else None
     serving = serving_section(args, ahs, gen, torch, np) if args.serve else None
@@ -608,12 +811,61 @@ def main():
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"strategy sweep: {len(cases)} arrays x 2^{args.log2n} uint32 ({', '.join(cases)}), "
                                "AHS AUTO per array (FSM + selector trained on MI355X measurements)",
-                   "n_per_array": n, "arrays": cases, "auto_choices": chosen},
-        "roofline": roofline, "ceilings": ceilings, "cpu_baseline": cpu, "step_kernels": step_kernels,
-        "per_case": per_case, "paper_sweep": paper,
-        "batched": batched, "serving": serving,
+                   "n_per_array": n, "auto_choices": chosen},
+        "roofline": roofline, "cpu_baseline": cpu,
     }
-    print(json.dumps(res), flush=True)
+    detail = dict(res, ceilings=ceilings, step_kernels=step_kernels, per_case=per_case, pr1=pr1, wide=wide,
+                  paper_sweep=paper, batched=batched, serving=serving)
+    try:
+        os.makedirs(os.path.dirname(args.detail_out) or ".", exist_ok=True)
+        with open(args.detail_out, "w") as f:
+            json.dump(detail, f, indent=1)
+    except OSError as e:
+        log(f"[bench] cannot write {args.detail_out}: {e}")
+    log("[bench] detail " + json.dumps(detail))
+    res["summary"] = summarise(per_case, pr1, wide, paper, batched, serving, ceilings)
+    line = json.dumps(res, separators=(",", ":"))
+    if len(line) > 3900:  # the stdout line stays short: drop summary parts, largest first
+        for k in sorted(res["summary"], key=lambda k: -len(json.dumps(res["summary"][k]))):
+            del res["summary"][k]
+            line = json.dumps(res, separators=(",", ":"))
+            if len(line) <= 3900:
+                break
+    print(line, flush=True)
+
+
+def summarise(per_case, pr1, wide, paper, batched, serving, ceilings):
+    """A few figures per section for the stdout line (the detail file has all)."""
+    out = {"ceilings": {k: ceilings[k] for k in ("copy_GBps", "read_GBps")}}
+    if per_case:
+        out["sweep"] = {r["case"]: [r.get("auto", {}).get("ms"), r.get("best_forced"), r.get("auto_over_best"),
+                                    max((r[k].get("hbm_frac_path", 0) for k in ("counting", "radix", "quick")
+                                         if k in r and "ms" in r[k]), default=None)]
+                        for r in per_case}
+        out["sweep_cols"] = "auto_ms, best forced, auto/best, best path hbm frac"
+    if pr1:
+        out["pr1"] = {"ms": {k: pr1["keys_only"][k].get("ms") for k in ("auto", "radix", "quick")},
+                      "oracle_ms": pr1["oracle_ms"], "oracle_exact": pr1["all_oracle_exact"]}
+    if wide:
+        out["wide"] = {f"{r['case']}{'+p' if r['payload'] else ''}": [r.get("auto", {}).get("ms"),
+                                                                      r.get("best_forced"), r.get("auto_over_best")]
+                       for r in wide["cases"]}
+        out["wide_ok"] = wide["all_sorted_and_agreeing"]
+    if paper:
+        out["paper_sweep"] = {k: paper[k] for k in ("auto_over_best_geomean", "auto_over_best_max",
+                                                    "all_sorted_and_agreeing")}
+    if batched:
+        out["batched"] = {k: batched.get(k) for k in ("graph_ms", "blocking_ms", "loop_ms", "speedup_graph_vs_loop",
+                                                      "identical_outputs", "graph_status")}
+    if serving:
+        out["serving"] = {k: serving.get(k) for k in ("p99_served_over_plain_realtime",
+                                                      "throughput_served_over_plain_burst")}
+        for k in ("served_realtime", "plain_realtime", "served_burst", "plain_burst"):
+            if k in serving:
+                out["serving"][k] = [serving[k]["p50_ms"], serving[k]["p99_ms"], serving[k]["gkeys_s"]] + \
+                    ([serving[k]["mean_batch_requests"]] if "mean_batch_requests" in serving[k] else [])
+        out["serving_cols"] = "p50_ms, p99_ms, Gkeys/s, mean requests per batch"
+    return out
 
 
 if __name__ == "__main__":

@@ -3,7 +3,6 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-#include <vector>
 
 #include "ahs.h"
 #include "host_internal.hpp"
@@ -12,6 +11,13 @@
 namespace ahs {
 
 static int key_bytes_of(ahs_dtype d) { return (d == AHS_U32 || d == AHS_F32 || d == AHS_I32) ? 4 : 8; }
+
+// Radix digit counts read back to the host (up to 8 digits of 256 bins).
+// A fixed array: the sort path makes no heap allocation.
+struct DigitCounts {
+  int ndig = 0;
+  uint32_t c[8 * 256];
+};
 
 static bool partial_overlap(const void* a, const void* b, size_t bytes) {
   if (a == b || bytes == 0) return false;
@@ -79,7 +85,7 @@ static ahs_status step_hist(SortJob& j, uint32_t* hist_out, int ndig_fused) {
 // the reduce with the entropy, the fused digit counts; then one read of the
 // feature vector and the digit counts.  Returns the plan word.
 static ahs_status step_features_auto(SortJob& j, const ahs_config& c, bool model, bool want_hist,
-                                     std::vector<uint32_t>* dcounts, uint32_t* plan_out) {
+                                     DigitCounts* dcounts, uint32_t* plan_out) {
   DevFeatures* df = at<DevFeatures>(j.ws, j.L.df);
   FeaturePlanCfg pc = {};
   pc.enabled = 1;
@@ -130,16 +136,14 @@ static ahs_status step_features_auto(SortJob& j, const ahs_config& c, bool model
   const uint32_t plan = j.f.reserved;
   j.f.reserved = 0;
   const int ndig = plan_digits(plan);
-  if (ndig > 0) {
-    dcounts->resize(256 * (size_t)ndig);
-    memcpy(dcounts->data(), pin + 256, 4 * 256 * (size_t)ndig);
-  }
+  dcounts->ndig = ndig;
+  if (ndig > 0) memcpy(dcounts->c, pin + 256, 4 * 256 * (size_t)ndig);
   *plan_out = plan;
   return AHS_OK;
 }
 
 // Reads back the feature vector and, if ndig > 0, the digit counts.
-static ahs_status read_features(SortJob& j, int ndig, std::vector<uint32_t>* counts) {
+static ahs_status read_features(SortJob& j, int ndig, DigitCounts* counts) {
   char* pin = static_cast<char*>(j.ctx->pinned);
   AHS_HIP(j, hipMemcpyAsync(pin, at<DevFeatures>(j.ws, j.L.df), sizeof(DevFeatures), hipMemcpyDeviceToHost, j.s),
           "copy features");
@@ -150,8 +154,8 @@ static ahs_status read_features(SortJob& j, int ndig, std::vector<uint32_t>* cou
   AHS_HIP(j, hipStreamSynchronize(j.s), "synchronize");
   memcpy(&j.f, pin, sizeof(DevFeatures));
   if (ndig > 0) {
-    counts->resize(256 * (size_t)ndig);
-    memcpy(counts->data(), pin + 256, 4 * 256 * (size_t)ndig);
+    counts->ndig = ndig;
+    memcpy(counts->c, pin + 256, 4 * 256 * (size_t)ndig);
   }
   return AHS_OK;
 }
@@ -166,11 +170,12 @@ static ahs_status copy_through(SortJob& j) {
 
 // LSD radix, base 256, over (key - min) (Sec. III-G, eq. (4)).  Passes whose
 // digit is the same for every key are skipped: they would not move a key.
-static ahs_status run_radix(SortJob& j, const std::vector<uint32_t>* ready_counts) {
+static ahs_status run_radix(SortJob& j, const DigitCounts* ready_counts) {
   const int ndig = radix_digits(j.f.span);
-  std::vector<uint32_t> counts;
+  DigitCounts local;
+  const uint32_t* counts = local.c;
   if (ready_counts) {
-    counts = *ready_counts;
+    counts = ready_counts->c;
   } else {
     const int nb = digit_hist_blocks(j.n);
     {
@@ -186,17 +191,17 @@ static ahs_status run_radix(SortJob& j, const std::vector<uint32_t>* ready_count
                               j.s),
             "copy digit counts");
     AHS_HIP(j, hipStreamSynchronize(j.s), "synchronize");
-    counts.resize(256 * (size_t)ndig);
-    memcpy(counts.data(), pin, 4 * 256 * (size_t)ndig);
+    local.ndig = ndig;
+    memcpy(local.c, pin, 4 * 256 * (size_t)ndig);
   }
-  std::vector<int> passes;
+  int passes[8];
+  int m = 0;
   for (int p = 0; p < ndig; ++p) {
     bool trivial = false;
     for (int b = 0; b < 256; ++b)
       if (counts[(size_t)p * 256 + b] == (uint32_t)j.n) trivial = true;
-    if (!trivial) passes.push_back(p);
+    if (!trivial) passes[m++] = p;
   }
-  const int m = (int)passes.size();
   if (m == 0) return copy_through(j);
 
   void* tmpk = at<void>(j.ws, j.L.tmpk);
@@ -380,7 +385,7 @@ extern "C" ahs_status ahs_sort(ahs_context* ctx, const void* d_keys_in, void* d_
   }
   const bool need_minmax = flt || requested != AHS_QUICK || want_feats;
   uint32_t plan = 0;
-  std::vector<uint32_t> dcounts;
+  DigitCounts dcounts;
   if (requested == AHS_AUTO) {
     AHS_TRY(step_features_auto(j, c, model_decides, want_feats, &dcounts, &plan));
   } else if (need_minmax) {

@@ -10,6 +10,7 @@ with vals_out ascending inside every run of equal keys.  The batched
 workload at its full 65,536 segments is additionally compared with the
 oracle segment by segment on a sample of segments.
 """
+import functools
 import sys
 import time
 
@@ -193,3 +194,71 @@ def test_batched_full_size_graph():
     assert torch.equal(ob.view(torch.int32), a), "blocking and graph outputs differ"
     assert torch.equal(cb, g.chosen), "blocking and graph decisions differ"
     say("full-size batch: blocking form identical to the graph")
+
+
+@pytest.mark.parametrize("case", ["uniform32", "sorted32", "reverse32", "swapped32"])
+def test_general_path_full_size_forced_quick(case):
+    """The general-path arrays at 2^28 under forced QUICK with payload =
+    index: on uniform keys the sample sort takes three levels, the last one
+    reading the output buffer; the keys-only run must give the same keys."""
+    n = 1 << 28
+    keys = gen.strategy_sweep(case, n=n)
+    say(f"full-size forced quick {case}: 2^28 keys")
+    k = torch.from_numpy(keys).to(DEV)
+    del keys
+    v = torch.arange(n, dtype=torch.int32, device=DEV).view(torch.uint32)
+    out, vout, chosen, _ = ahs.ahs_sort(k, v, strategy=ahs.QUICK)
+    torch.cuda.synchronize()
+    assert chosen == ahs.QUICK
+    check_sorted_permutation(k, out, vout)
+    out2, _, _, _ = ahs.ahs_sort(k, strategy=ahs.QUICK)
+    torch.cuda.synchronize()
+    assert torch.equal(out.view(torch.int32), out2.view(torch.int32)), "keys-only run differs"
+    say(f"full-size forced quick {case}: ok")
+
+
+@functools.lru_cache(maxsize=1)
+def _wide_host(case):
+    return gen.wide_keys(case, n=1 << 27)
+
+
+@pytest.mark.parametrize("strategy,payload", [("auto", False), ("radix", False), ("radix", True),
+                                              ("quick", False), ("quick", True)])
+@pytest.mark.parametrize("case", gen.WIDE_CASES)
+def test_wide_keys_full_size_strategies(case, strategy, payload, selector):
+    """Wide and floating keys at 2^27 under AUTO (keys only; the payload run
+    is above) and forced RADIX and QUICK, keys only and with payload."""
+    ctx, cfg = selector
+    keys = _wide_host(case)
+    n = keys.size
+    say(f"full-size wide {case}: {strategy} payload={payload}")
+    k = torch.from_numpy(keys).to(DEV)
+    v = torch.arange(n, dtype=torch.int32, device=DEV).view(torch.uint32) if payload else None
+    out, vout, chosen, f = ahs.ahs_sort(k, v, strategy=strategy, cfg=cfg, ctx=ctx, want_features=strategy == "auto")
+    torch.cuda.synchronize()
+    if strategy == "auto":
+        rf = check_features_vs_oracle(f, keys)
+        st, rchosen = O.select(rf, O.config(0, use_model=1), O.Model(ahs.SELECTOR_MODEL))
+        assert st == O.OK and chosen == rchosen, (chosen, rchosen)
+    else:
+        assert chosen == ahs.STRATEGY_CODES[strategy]
+    check_sorted_permutation(k, out, vout)
+    say(f"full-size wide {case} {strategy}: ok")
+
+
+@pytest.mark.parametrize("strategy", ["radix", "quick"])
+def test_single_array_2p30_u32(strategy):
+    """One array of 2^30 uniform 32-bit keys with payload = index: the
+    look-back status words of the radix passes and of the sample-sort
+    scatter switch to 64 bits at this size."""
+    n = 1 << 30
+    keys = gen.u32(12, 0, n)
+    say(f"single array 2^30 u32: {strategy}")
+    k = torch.from_numpy(keys).to(DEV)
+    del keys
+    v = torch.arange(n, dtype=torch.int32, device=DEV).view(torch.uint32)
+    out, vout, chosen, _ = ahs.ahs_sort(k, v, strategy=strategy)
+    torch.cuda.synchronize()
+    assert chosen == ahs.STRATEGY_CODES[strategy]
+    check_sorted_permutation(k, out, vout)
+    say(f"single array 2^30 u32 {strategy}: ok")

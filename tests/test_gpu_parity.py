@@ -184,6 +184,16 @@ def test_pr1_auto_radix_parity():
     assert run_pair(keys, None, ahs.RADIX) == ahs.RADIX
 
 
+@pytest.mark.parametrize("payload", [False, True])
+def test_pr1_forced_quick_parity(payload):
+    """PR1 with the strategy forced to QUICK: the sample sort on 1,024
+    distinct values (every bucket an equality bucket after one level),
+    keys and payload bit-exact to the oracle's quicksort."""
+    keys = gen.pr1()
+    vals = np.arange(keys.size, dtype=np.uint32) if payload else None
+    assert run_pair(keys, vals, ahs.QUICK) == ahs.QUICK
+
+
 SIZES = [1, 2, 19, 20, 21, 100, 4095, 4096, 4097, 8191, 8192, 8193, 3 * 8192 + 17, 65537, 300_001]
 
 
