@@ -131,8 +131,11 @@ typedef struct ahs_model ahs_model;
 ahs_status ahs_config_init(ahs_config* cfg, int preset);
 
 /* Creates host-side state bound to HIP device `device`: device properties,
- * a small pinned staging buffer, per-kernel timing, the optional model.  No
- * device memory is allocated. */
+ * a small pinned staging buffer, per-kernel timing, the optional model, and
+ * the device address of the library's fixed ahs_sort_static scratch on that
+ * device (looked up once per device; the HIP runtime places the array when
+ * it loads the library's code there).  No other device memory is
+ * allocated. */
 ahs_status ahs_context_create(int device, ahs_context** out);
 void ahs_context_destroy(ahs_context* ctx);
 
@@ -174,6 +177,26 @@ ahs_status ahs_sort(ahs_context* ctx, const void* d_keys_in, void* d_keys_out,
                     const uint32_t* d_vals_in, uint32_t* d_vals_out, uint64_t n, ahs_dtype dtype,
                     ahs_strategy requested, const ahs_config* cfg, void* d_ws, size_t ws_bytes,
                     void* stream, ahs_strategy* h_chosen, ahs_feature_vector* h_feats);
+
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): ahs_sort
+ * with no workspace argument.  Its scratch is a fixed array of
+ * AHS_STATIC_SCRATCH_BYTES inside the library, one per GPU, allocated when
+ * the library's code is loaded on that GPU and held until the process ends;
+ * its device address is looked up once per device by ahs_context_create.
+ * The call allocates nothing (no hipMalloc, hipFree or host heap).  Inputs,
+ * outputs and every other argument behave as in ahs_sort.  A call whose
+ * ahs_workspace_bytes(n, dtype, with_payload, requested) exceeds
+ * AHS_STATIC_SCRATCH_BYTES returns AHS_E_WORKSPACE before any launch (about
+ * 4.2e6 u32 keys under AUTO, 2.1e6 u64 keys with payload).  All calls on
+ * one GPU share its array, and it keeps the last call's contents: calls that
+ * overlap in time on one GPU (other streams or host threads) race and give
+ * undefined results; serialise them. */
+#define AHS_STATIC_SCRATCH_BYTES (64ull << 20)
+ahs_status ahs_sort_static(ahs_context* ctx, const void* d_keys_in, void* d_keys_out,
+                           const uint32_t* d_vals_in, uint32_t* d_vals_out, uint64_t n, ahs_dtype dtype,
+                           ahs_strategy requested, const ahs_config* cfg, void* stream,
+                           ahs_strategy* h_chosen, ahs_feature_vector* h_feats);
 
 /* Batched segmented sort: nseg independent arrays stored back to back,
  * segment s occupying [d_offsets[s], d_offsets[s+1]) of the key (and

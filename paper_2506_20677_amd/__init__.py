@@ -8,7 +8,7 @@ fallback path.
 
 Calls (same names as the C ABI):
     ahs_config_init, ahs_context_create, ahs_workspace_bytes,
-    ahs_features, ahs_select, ahs_sort, ahs_model_load, ahs_model_predict,
+    ahs_features, ahs_select, ahs_sort, ahs_sort_static, ahs_model_load, ahs_model_predict,
     ahs_profile_enable / ahs_profile_reset / ahs_profile_query / ahs_profile_dump
 """
 from __future__ import annotations
@@ -112,6 +112,8 @@ def lib():
             "ahs_select": (i32, [C.POINTER(FeatureVector), C.POINTER(Config), vp, C.POINTER(C.c_int)]),
             "ahs_sort": (i32, [vp, vp, vp, vp, vp, u64, i32, i32, C.POINTER(Config), vp, sz, vp,
                                C.POINTER(C.c_int), C.POINTER(FeatureVector)]),
+            "ahs_sort_static": (i32, [vp, vp, vp, vp, vp, u64, i32, i32, C.POINTER(Config), vp,
+                                      C.POINTER(C.c_int), C.POINTER(FeatureVector)]),
             "ahs_segmented_workspace_bytes": (sz, [u64, u32, i32, i32]),
             "ahs_sort_segmented": (i32, [vp, vp, vp, vp, vp, vp, u32, u64, i32, i32, C.POINTER(Config), vp, sz,
                                          vp, vp, vp]),
@@ -341,6 +343,39 @@ def ahs_sort(keys: torch.Tensor, values: torch.Tensor | None = None, strategy: i
     if st != OK:
         _raise(st, ctx, f if want_features else None)
     return out, out_values, chosen.value, (f if want_features else None)
+
+
+STATIC_SCRATCH_BYTES = 64 << 20  # AHS_STATIC_SCRATCH_BYTES
+
+
+def ahs_sort_static(keys: torch.Tensor, out: torch.Tensor, values: torch.Tensor | None = None,
+                    out_values: torch.Tensor | None = None, strategy: int | str = AUTO, cfg: Config | None = None,
+                    dtype: int | None = None, ctx: Context | None = None, stream=None, want_features: bool = False):
+    """ahs_sort with the library's fixed per-device scratch instead of a
+    workspace: the call allocates nothing, so the caller passes the outputs.
+    Returns (chosen strategy, FeatureVector or None)."""
+    if isinstance(strategy, str):
+        strategy = STRATEGY_CODES[strategy]
+    code = dtype_code(keys, dtype)
+    _check_keys(keys, code)
+    ctx = ctx or default_context(keys.device.index)
+    n = keys.numel()
+    if out.numel() != n or out.element_size() != keys.element_size() or not out.is_cuda or not out.is_contiguous():
+        raise ValueError("out must be a contiguous device tensor shaped like keys")
+    if (values is None) != (out_values is None):
+        raise ValueError("values and out_values must be given together")
+    for t in (values, out_values):
+        if t is not None and (t.numel() != n or t.element_size() != 4 or not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("payloads must be contiguous device tensors of n 32-bit elements")
+    chosen = C.c_int()
+    f = FeatureVector()
+    vp = (lambda t: C.c_void_p(t.data_ptr()) if t is not None else None)
+    st = lib().ahs_sort_static(ctx.handle, vp(keys), vp(out), vp(values), vp(out_values), n, code, strategy,
+                               C.byref(cfg) if cfg is not None else None, _stream_handle(stream), C.byref(chosen),
+                               C.byref(f) if want_features else None)
+    if st != OK:
+        _raise(st, ctx, f if want_features else None)
+    return chosen.value, (f if want_features else None)
 
 
 SEG_NAN = 0xFD  # per-segment decision code of a segment that holds NaN keys

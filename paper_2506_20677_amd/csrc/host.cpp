@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "host_internal.hpp"
+#include "static_scratch.hpp"
 #include "kernels.hpp"
 
 using namespace ahs;
@@ -108,6 +109,13 @@ extern "C" ahs_status ahs_context_create(int device, ahs_context** out) {
     hipSetDevice(prev);
     delete c;
     return AHS_E_OOM;
+  }
+  // the fixed scratch of ahs_sort_static on this device (its address is
+  // per device; looked up here, with the device current, once per device)
+  if (ahs::static_scratch_address(device, &c->static_scratch) != hipSuccess) {
+    hipSetDevice(prev);
+    delete c;
+    return AHS_E_DEVICE;
   }
   hipSetDevice(prev);
   *out = c;

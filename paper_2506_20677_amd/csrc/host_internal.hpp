@@ -23,6 +23,7 @@ struct ahs_context {
   std::string last_error;
   const ahs_model* model = nullptr;
   void* pinned = nullptr;  // host staging for small device-to-host reads
+  void* static_scratch = nullptr;  // device address of this device's ahs_sort_static scratch
 
   // per-kernel event timing
   struct Rec {

@@ -7,6 +7,7 @@
 #include "ahs.h"
 #include "host_internal.hpp"
 #include "kernels.hpp"
+#include "static_scratch.hpp"
 
 namespace ahs {
 
@@ -445,4 +446,26 @@ extern "C" ahs_status ahs_sort(ahs_context* ctx, const void* d_keys_in, void* d_
   if (h_chosen) *h_chosen = s;
   if (h_feats) memcpy(h_feats, &j.f, sizeof *h_feats);
   return AHS_OK;
+}
+
+// ahs_sort with its workspace in the library's fixed per-device scratch
+// array: no allocation of any kind.  The array is shared by every call on
+// the device (calls that overlap on one GPU race); ahs_sort clears whatever
+// it needs zeroed with its own fill kernels, so stale contents from an
+// earlier call are harmless.
+extern "C" ahs_status ahs_sort_static(ahs_context* ctx, const void* d_keys_in, void* d_keys_out,
+                                      const uint32_t* d_vals_in, uint32_t* d_vals_out, uint64_t n, ahs_dtype dtype,
+                                      ahs_strategy requested, const ahs_config* cfg, void* stream,
+                                      ahs_strategy* h_chosen, ahs_feature_vector* h_feats) {
+  using namespace ahs;
+  AHS_TRY(common_checks(ctx, n, dtype));
+  if ((int)requested < AHS_AUTO || (int)requested > AHS_QUICK)
+    return ctx->fail(AHS_E_INVALID_ARG, "strategy %d cannot be requested", (int)requested);
+  if (!ctx->static_scratch) return ctx->fail(AHS_E_DEVICE, "no static scratch on device %d", ctx->device);
+  const size_t need = ahs_workspace_bytes(n, dtype, d_vals_in != nullptr ? 1 : 0, requested);
+  if (need > STATIC_SCRATCH_BYTES)
+    return ctx->fail(AHS_E_WORKSPACE, "%llu keys need %zu bytes of scratch; the static scratch holds %zu",
+                     (unsigned long long)n, need, STATIC_SCRATCH_BYTES);
+  return ahs_sort(ctx, d_keys_in, d_keys_out, d_vals_in, d_vals_out, n, dtype, requested, cfg, ctx->static_scratch,
+                  STATIC_SCRATCH_BYTES, stream, h_chosen, h_feats);
 }
