@@ -238,7 +238,9 @@ ahs_status ahs_sort_segmented(ahs_context* ctx, const void* d_keys_in, void* d_k
  * required), written by the last kernel: 0 success; bit 0 invalid offsets
  * (nothing else was written); bit 1 sample-sort table overflow; bit 2 a
  * segment larger than max_seg_hint remained unsplit (its output is not
- * sorted).  Host-side argument errors return a status as usual. */
+ * sorted); bit 3 a segment holds more than max_seg_hint keys (the level
+ * count and look-back word width were sized for the hint, so its output
+ * may be wrong).  Host-side argument errors return a status as usual. */
 ahs_status ahs_sort_segmented_async(ahs_context* ctx, const void* d_keys_in, void* d_keys_out,
                                     const uint32_t* d_vals_in, uint32_t* d_vals_out, const uint64_t* d_offsets,
                                     uint32_t nseg, uint64_t n_total, uint64_t max_seg_hint, ahs_dtype dtype,

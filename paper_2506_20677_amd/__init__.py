@@ -206,7 +206,13 @@ def ahs_model_predict(model: Model, f: FeatureVector) -> int:
 
 class Context:
     """Host-side library state bound to one HIP device, plus a cached
-    device workspace allocated through torch."""
+    device workspace per stream allocated through torch.
+
+    A sort returns with its kernels still enqueued on its stream, so each
+    stream gets its own workspace, allocated on that stream: torch's caching
+    allocator then never hands a grown-out buffer to another stream while
+    the old one's kernels may still run.  Like the C context, one Context is
+    driven by one host thread."""
 
     def __init__(self, device: int = 0):
         h = C.c_void_p()
@@ -215,14 +221,20 @@ class Context:
             raise AhsError(st, f"cannot create a context on device {device}")
         self.handle = h
         self.device = device
-        self._ws = None
+        self._ws = {}
         self._model = None
 
-    def workspace(self, nbytes: int) -> torch.Tensor:
-        if self._ws is None or self._ws.numel() < nbytes:
-            self._ws = None
-            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
-        return self._ws
+    def workspace(self, nbytes: int, stream=None) -> torch.Tensor:
+        dev = torch.device("cuda", self.device)
+        s = torch.cuda.current_stream(dev) if stream is None else stream
+        ws = self._ws.get(s.cuda_stream)
+        if ws is None or ws.numel() < nbytes:
+            self._ws.pop(s.cuda_stream, None)
+            del ws
+            with torch.cuda.stream(s):
+                ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
+            self._ws[s.cuda_stream] = ws
+        return ws
 
     def set_model(self, model: Model | None):
         self._model = model
@@ -290,7 +302,7 @@ def ahs_features(keys: torch.Tensor, hist: torch.Tensor | None = None, dtype: in
     if hist is not None and (not hist.is_cuda or hist.numel() < 65536 or hist.element_size() != 4):
         raise ValueError("hist must be a device tensor of at least 65,536 32-bit elements")
     wsb = ahs_workspace_bytes(n, code, False, AUTO)
-    ws = ctx.workspace(wsb)
+    ws = ctx.workspace(wsb, stream)
     f = FeatureVector()
     st = lib().ahs_features(ctx.handle, C.c_void_p(keys.data_ptr()), n, code,
                             C.c_void_p(hist.data_ptr()) if hist is not None else None,
@@ -333,7 +345,7 @@ def ahs_sort(keys: torch.Tensor, values: torch.Tensor | None = None, strategy: i
     elif out_values is not None:
         raise ValueError("out_values given without values")
     wsb = ahs_workspace_bytes(n, code, values is not None, strategy)
-    ws = ctx.workspace(wsb)
+    ws = ctx.workspace(wsb, stream)
     chosen = C.c_int()
     f = FeatureVector()
     vp = (lambda t: C.c_void_p(t.data_ptr()) if t is not None else None)
@@ -385,7 +397,7 @@ def ahs_segmented_workspace_bytes(n_total: int, nseg: int, dtype: int, with_payl
     return lib().ahs_segmented_workspace_bytes(n_total, nseg, dtype, 1 if with_payload else 0)
 
 
-SEG_ERR_OFFSETS, SEG_ERR_OVERFLOW, SEG_ERR_LEVELS = 1, 2, 4  # bits of the enqueue-only status word
+SEG_ERR_OFFSETS, SEG_ERR_OVERFLOW, SEG_ERR_LEVELS, SEG_ERR_HINT = 1, 2, 4, 8  # bits of the enqueue-only status word
 
 
 def _seg_prepare(keys, offsets, values, strategy, out, out_values, dtype, ctx, want_chosen, want_features):
@@ -429,7 +441,7 @@ def ahs_sort_segmented(keys: torch.Tensor, offsets: torch.Tensor, values: torch.
     strategy, code, nseg, n, ctx, out, out_values, chosen, feats = _seg_prepare(
         keys, offsets, values, strategy, out, out_values, dtype, ctx, want_chosen, want_features)
     wsb = ahs_segmented_workspace_bytes(n, nseg, code, values is not None)
-    ws = ctx.workspace(wsb)
+    ws = ctx.workspace(wsb, stream)
     vp = (lambda t: C.c_void_p(t.data_ptr()) if t is not None else None)
     st = lib().ahs_sort_segmented(ctx.handle, vp(keys), vp(out), vp(values), vp(out_values), vp(offsets), nseg, n,
                                   code, strategy, C.byref(cfg) if cfg is not None else None,
@@ -454,7 +466,7 @@ def ahs_sort_segmented_async(keys: torch.Tensor, offsets: torch.Tensor, values: 
         keys, offsets, values, strategy, out, out_values, dtype, ctx, want_chosen, want_features)
     wsb = ahs_segmented_workspace_bytes(n, nseg, code, values is not None)
     if ws is None:
-        ws = ctx.workspace(wsb)
+        ws = ctx.workspace(wsb, stream)
     status = torch.empty(1, dtype=torch.int32, device=keys.device)
     vp = (lambda t: C.c_void_p(t.data_ptr()) if t is not None else None)
     st = lib().ahs_sort_segmented_async(ctx.handle, vp(keys), vp(out), vp(values), vp(out_values), vp(offsets), nseg,

@@ -47,6 +47,9 @@ struct ahs_context {
                                           {{0, 1, 2, 3}, {0, 1, 2, 3}}, {{0, 1, 2, 3}, {0, 1, 2, 3}},
                                           {{0, 1, 2, 3}, {0, 1, 2, 3}}, {{0, 1, 2, 3}, {0, 1, 2, 3}}};
   static_assert(ahs::NUM_KEY_KINDS == 6, "one row of defaults per key kind");
+  // Batched sort: tile variant (0 small, 1 large) of the segmented radix
+  // passes per key type and payload flag; set by the autotuner.
+  int seg_radix_variant[ahs::NUM_KEY_KINDS][2] = {{1, 1}, {1, 1}, {1, 1}, {1, 1}, {1, 1}, {1, 1}};
 
   ~ahs_context();
   ahs_status fail(ahs_status s, const char* fmt, ...);

@@ -11,15 +11,6 @@
 
 namespace ahs {
 
-// Decision engine of Sec. III-A on the device: n, then k = span + 1, then
-// the entropy test against h_ratio * log2(B).
-__device__ __forceinline__ uint8_t seg_fsm(uint64_t n, uint64_t span, uint32_t nbins, double H, const SegConfig& c) {
-  if (n <= c.n_small) return 4;                                             // INSERTION
-  if (span <= c.k_count - 1) return 1;                                      // COUNTING
-  if (span >= c.k_radix && H < c.h_ratio * log2((double)nbins)) return 2;  // RADIX
-  return 3;                                                                 // QUICK
-}
-
 // Mapped-key bounds of the non-NaN values: map(-inf) .. map(+inf).
 template <typename K> struct NanBounds;
 template <> struct NanBounds<uint32_t> {
@@ -29,16 +20,10 @@ template <> struct NanBounds<uint64_t> {
   static constexpr uint64_t lo = 0x000FFFFFFFFFFFFFull, hi = 0xFFF0000000000000ull;
 };
 
-__device__ __forceinline__ void shift_nbins(uint64_t span, uint32_t& shift, uint32_t& nbins) {
-  const int bl = bitlen64(span);
-  shift = bl > 16 ? (uint32_t)(bl - 16) : 0u;
-  nbins = (uint32_t)(span >> shift) + 1u;
-}
-
 // ------------------------------------------------------------------ classify
 __global__ __launch_bounds__(256) void k_seg_classify(const uint64_t* __restrict__ offs, uint32_t nseg,
                                                       uint64_t n_total, uint32_t* __restrict__ queues, uint32_t qcap,
-                                                      SsSeg* __restrict__ large_ss, SsSeg* __restrict__ large,
+                                                      SegLarge* __restrict__ linfo, SsSeg* __restrict__ large,
                                                       uint32_t* __restrict__ large_ids,
                                                       SegCounters* __restrict__ ctr) {
   const uint32_t s = blockIdx.x * 256 + threadIdx.x;
@@ -61,19 +46,22 @@ __global__ __launch_bounds__(256) void k_seg_classify(const uint64_t* __restrict
     g.start = a;
     g.size = (uint32_t)size;
     g.first_tile = 0;
-    large_ss[i] = g;
     large[i] = g;
+    SegLarge L;
+    L.mn = ~0ull;
+    L.mx = 0ull;
+    L.nan = 0u;
+    L.pad = 0u;
+    linfo[i] = L;
     large_ids[i] = s;
     atomicAdd(&ctr->large_keys, (unsigned long long)size);
     atomicMax(&ctr->max_large, (uint32_t)size);
   }
 }
 
-__global__ void k_seg_gate(const SegCounters* __restrict__ ctr, SsCounters* __restrict__ rec0,
-                           SsCounters* __restrict__ rec_chunks) {
+__global__ void k_seg_gate(const SegCounters* __restrict__ ctr, SsCounters* __restrict__ rec_chunks) {
   if (threadIdx.x == 0) {
     const uint32_t nl = ctr->bad ? 0u : ctr->nlarge;
-    rec0->nsegs_next = nl;
     rec_chunks->nsegs_next = nl;
   }
 }
@@ -323,7 +311,8 @@ __global__ __launch_bounds__(SEG_CH_THREADS) void k_seg_chunk(SegArgs a) {
 }
 
 // One workgroup per large segment: features from its ends and its chunks'
-// entropy terms (summed in a fixed order), then the decision.
+// entropy terms (summed in a fixed order).  The decision was taken before
+// the segment was sorted.
 template <int KK>
 __global__ __launch_bounds__(256) void k_seg_large_final(SegArgs a) {
   using K = typename KeyTraits<KK>::K;
@@ -347,10 +336,7 @@ __global__ __launch_bounds__(256) void k_seg_large_final(SegArgs a) {
     DevFeatures f = {};
     f.n = g.size;
     f.nan_count = lo + (g.size - hi);
-    uint8_t chosen;
-    if (f.nan_count) {
-      chosen = SEG_STATUS_NAN;
-    } else {
+    if (!f.nan_count) {
       const K* __restrict__ keys = (const K*)a.kout + g.start;
       K mn = keys[0], mx = keys[g.size - 1];
       if constexpr (key_mapped<KK>) {
@@ -364,17 +350,20 @@ __global__ __launch_bounds__(256) void k_seg_large_final(SegArgs a) {
       f.exact = f.shift == 0;
       f.entropy_bits = H < 0.0 ? 0.0 : H;
       f.entropy_ratio = f.nbins > 1 ? f.entropy_bits / log2((double)f.nbins) : 0.0;
-      chosen = a.requested ? (uint8_t)a.requested : seg_fsm(g.size, f.span, f.nbins, f.entropy_bits, a.cfg);
     }
-    if (a.chosen) a.chosen[s] = chosen;
     if (a.feats) a.feats[s] = f;
   }
 }
 
 __global__ void k_seg_status(const SegCounters* __restrict__ ctr, const SsCounters* __restrict__ levels, int nlevels,
+                             const SegDispatchCounters* __restrict__ dctr, uint64_t max_seg,
                              uint32_t* __restrict__ status) {
   if (threadIdx.x != 0) return;
   uint32_t st = ctr->bad ? SEG_ERR_OFFSETS : 0u;
+  if (dctr && dctr->bad) st |= SEG_ERR_OVERFLOW;
+  // the level count and the look-back word width were chosen for segments of
+  // at most max_seg keys: a larger one is an error even if it was sorted
+  if (!ctr->bad && (uint64_t)ctr->max_large > max_seg) st |= SEG_ERR_HINT;
   for (int l = 0; l < nlevels; ++l)
     if (levels[l].overflow) st |= SEG_ERR_OVERFLOW;
   if (!ctr->bad && ctr->nlarge > 0 && (nlevels == 0 || levels[nlevels - 1].nsegs_next > 0)) st |= SEG_ERR_LEVELS;
@@ -406,14 +395,14 @@ __global__ __launch_bounds__(256) void k_tune_fill(typename KeyTraits<KK>::K* __
 
 // ------------------------------------------------------------------ launchers
 hipError_t launch_seg_classify(const uint64_t* offs, uint32_t nseg, uint64_t n_total, uint32_t* queues, uint32_t qcap,
-                               SsSeg* large_ss, SsSeg* large, uint32_t* large_ids, SegCounters* ctr, hipStream_t s) {
+                               SegLarge* linfo, SsSeg* large, uint32_t* large_ids, SegCounters* ctr, hipStream_t s) {
   const uint32_t nb = (uint32_t)(((uint64_t)nseg + 256) / 256);  // nseg < 2^32: at most 2^24 workgroups of 256
-  k_seg_classify<<<nb, 256, 0, s>>>(offs, nseg, n_total, queues, qcap, large_ss, large, large_ids, ctr);
+  k_seg_classify<<<nb, 256, 0, s>>>(offs, nseg, n_total, queues, qcap, linfo, large, large_ids, ctr);
   return hipGetLastError();
 }
 
-hipError_t launch_seg_gate(const SegCounters* ctr, SsCounters* rec0, SsCounters* rec_chunks, hipStream_t s) {
-  k_seg_gate<<<1, 64, 0, s>>>(ctr, rec0, rec_chunks);
+hipError_t launch_seg_gate(const SegCounters* ctr, SsCounters* rec_chunks, hipStream_t s) {
+  k_seg_gate<<<1, 64, 0, s>>>(ctr, rec_chunks);
   return hipGetLastError();
 }
 
@@ -539,9 +528,9 @@ uint32_t seg_chunk_resident(int kk, uint32_t cu_count) {
   return (uint32_t)per_cu * (cu_count ? cu_count : 1);
 }
 
-hipError_t launch_seg_status(const SegCounters* ctr, const SsCounters* levels, int nlevels, uint32_t* status,
-                             hipStream_t s) {
-  k_seg_status<<<1, 64, 0, s>>>(ctr, levels, nlevels, status);
+hipError_t launch_seg_status(const SegCounters* ctr, const SsCounters* levels, int nlevels,
+                             const SegDispatchCounters* dctr, uint64_t max_seg, uint32_t* status, hipStream_t s) {
+  k_seg_status<<<1, 64, 0, s>>>(ctr, levels, nlevels, dctr, max_seg, status);
   return hipGetLastError();
 }
 

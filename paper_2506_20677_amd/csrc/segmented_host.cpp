@@ -14,11 +14,13 @@ namespace ahs {
 namespace {
 
 struct SegLayout {
-  size_t queues = 0, large = 0, large_ids = 0, bounds = 0, partial = 0, segctr = 0, status = 0, total = 0;
-  uint64_t chunk_cap = 0;
+  size_t queues = 0, large = 0, large_ids = 0, bounds = 0, partial = 0, segctr = 0, status = 0;
+  size_t linfo = 0, hsegs = 0, hlarge = 0, hslot_of = 0, hslots = 0, rsegs = 0, rinfo = 0, rdig = 0, dctr = 0;
+  size_t total = 0;
+  uint64_t chunk_cap = 0, lcap = 0, slot_cap = 0, unit_cap = 0, tile_cap = 0;
 };
 
-SegLayout seg_layout(size_t base, uint64_t n_total, uint32_t nseg) {
+SegLayout seg_layout(size_t base, uint64_t n_total, uint32_t nseg, int key_bytes, int with_payload) {
   SegLayout L;
   size_t o = base;
   auto take = [&](size_t bytes) {
@@ -34,6 +36,20 @@ SegLayout seg_layout(size_t base, uint64_t n_total, uint32_t nseg) {
   L.partial = take(sizeof(double) * L.chunk_cap);
   L.segctr = take(sizeof(SegCounters) + 2 * sizeof(SsCounters));
   L.status = take(256);
+  // large-segment dispatch: a large segment holds more than SS_CAP keys
+  L.lcap = std::min<uint64_t>(nseg, n_total / (SS_CAP + 1)) + 1;
+  L.slot_cap = n_total / (SEG_HU + 1) + 1;
+  L.unit_cap = n_total / SEG_HU + L.lcap;
+  L.tile_cap = n_total / seg_radix_tile(key_bytes, with_payload, 0) + L.lcap;
+  L.linfo = take(sizeof(SegLarge) * ((size_t)nseg + 1));
+  L.hsegs = take(sizeof(SsSeg) * L.lcap);
+  L.hlarge = take(4 * L.lcap);
+  L.hslot_of = take(4 * L.lcap);
+  L.hslots = take(4 * 65536 * (size_t)L.slot_cap);
+  L.rsegs = take(sizeof(SsSeg) * L.lcap);
+  L.rinfo = take(sizeof(SegRadixInfo) * L.lcap);
+  L.rdig = take(4 * 8 * 256 * (size_t)L.lcap);
+  L.dctr = take(sizeof(SegDispatchCounters));
   L.total = o;
   return L;
 }
@@ -47,6 +63,7 @@ struct SegCall {
   SsTables T;
   SegLayout G;
   SegArgs a;
+  SegDispatchArgs d;
   SegCounters* sctr;
   SsCounters* rec0;        // level 0 of the sample sort
   SsCounters* rec_chunks;  // chunks of the large segments
@@ -89,7 +106,7 @@ ahs_status seg_setup(SegCall& C, ahs_context* ctx, const void* d_keys_in, void* 
   j.s = (hipStream_t)stream;
   j.L = plan_layout(n_total, kb, d_vals_in ? 1 : 0, true);
   memset(&j.f, 0, sizeof j.f);
-  C.G = seg_layout(j.L.total, n_total, nseg);
+  C.G = seg_layout(j.L.total, n_total, nseg, kb, d_vals_in ? 1 : 0);
   if (ws_bytes < C.G.total) return ctx->fail(AHS_E_WORKSPACE, "workspace %zu < %zu", ws_bytes, C.G.total);
   AHS_HIP(j, hipSetDevice(ctx->device), "set device");
   C.S = ss_layout(n_total, kb);
@@ -121,6 +138,43 @@ ahs_status seg_setup(SegCall& C, ahs_context* ctx, const void* d_keys_in, void* 
   a.requested = (uint32_t)requested;
   a.chosen = d_chosen;
   a.feats = reinterpret_cast<DevFeatures*>(d_feats);
+
+  SegDispatchArgs& d = C.d;
+  d.kin = d_keys_in;
+  d.kout = d_keys_out;
+  d.ktmp = at<void>(d_ws, j.L.tmpk);
+  d.vin = d_vals_in;
+  d.vout = d_vals_out;
+  d.vtmp = d_vals_in ? at<uint32_t>(d_ws, j.L.tmpv) : nullptr;
+  d.large = a.large;
+  d.large_ids = a.large_ids;
+  d.ctr = C.sctr;
+  d.chunks = C.rec_chunks;
+  d.chunk_cap = a.chunk_cap;
+  d.linfo = at<SegLarge>(d_ws, C.G.linfo);
+  d.qsegs = C.T.segs[0];
+  d.qrec = C.rec0;
+  d.qcap = (uint32_t)std::min<uint64_t>(C.S.seg_cap, 0xFFFFFFFFull);
+  d.hsegs = at<SsSeg>(d_ws, C.G.hsegs);
+  d.hlarge = at<uint32_t>(d_ws, C.G.hlarge);
+  d.hslots = at<uint32_t>(d_ws, C.G.hslots);
+  d.hslot_of = at<uint32_t>(d_ws, C.G.hslot_of);
+  d.slot_cap = (uint32_t)C.G.slot_cap;
+  d.rsegs = at<SsSeg>(d_ws, C.G.rsegs);
+  d.rinfo = at<SegRadixInfo>(d_ws, C.G.rinfo);
+  d.rdig = at<uint32_t>(d_ws, C.G.rdig);
+  d.list_cap = (uint32_t)C.G.lcap;
+  d.tile_cap = (uint32_t)std::min<uint64_t>(C.G.tile_cap, 0xFFFFFFFFull);
+  d.unit_cap = (uint32_t)std::min<uint64_t>(C.G.unit_cap, 0xFFFFFFFFull);
+  d.dctr = at<SegDispatchCounters>(d_ws, C.G.dctr);
+  d.status = C.T.status;  // the radix passes and the sample-sort levels run one after the other
+  d.cfg = a.cfg;
+  d.requested = a.requested;
+  d.in_place = (d_keys_in == d_keys_out || (d_vals_in && d_vals_in == d_vals_out)) ? 1u : 0u;
+  d.chosen = d_chosen;
+  // the radix passes' look-back words live in the sample sort's status table
+  if ((uint64_t)C.G.tile_cap * 256 * 8 > 8ull * SS_NB * C.S.tile_cap)
+    return ctx->fail(AHS_E_DEVICE, "radix status table exceeds the sample sort's");
   return AHS_OK;
 }
 
@@ -132,16 +186,17 @@ ahs_status seg_classify(SegCall& C, uint64_t n_total) {
           launch_fill_u32(reinterpret_cast<uint32_t*>(C.sctr), (sizeof(SegCounters) + 2 * sizeof(SsCounters)) / 4,
                           0u, j.s),
           "fill");
+  static_assert(sizeof(SegDispatchCounters) % 4 == 0, "counters fill as words");
+  AHS_HIP(j, launch_fill_u32(reinterpret_cast<uint32_t*>(C.d.dctr), sizeof(SegDispatchCounters) / 4, 0u, j.s),
+          "fill");
   {
     ProfScope p(j.ctx, "seg_classify", j.s);
     AHS_HIP(j,
-            launch_seg_classify(C.a.offs, C.nseg, n_total, const_cast<uint32_t*>(C.a.queues), C.a.qcap, C.T.segs[0],
+            launch_seg_classify(C.a.offs, C.nseg, n_total, const_cast<uint32_t*>(C.a.queues), C.a.qcap, C.d.linfo,
                                 const_cast<SsSeg*>(C.a.large), const_cast<uint32_t*>(C.a.large_ids), C.sctr, j.s),
             "classify");
   }
-  AHS_HIP(j, launch_seg_gate(C.sctr, C.rec0, C.rec_chunks, j.s), "gate");
-  AHS_HIP(j, launch_ss_tiles(C.T.segs[0], C.rec0, (uint32_t)ss_tile(j.key_bytes), (uint32_t)C.S.seg_cap, j.s),
-          "tiles");
+  AHS_HIP(j, launch_seg_gate(C.sctr, C.rec_chunks, j.s), "gate");
   AHS_HIP(j, launch_ss_tiles(const_cast<SsSeg*>(C.a.large), C.rec_chunks, SEG_CH, C.nseg + 1, j.s), "chunks");
   return AHS_OK;
 }
@@ -163,6 +218,55 @@ ahs_status seg_small_all(SegCall& C, const uint32_t* exact_counts, double small_
   return AHS_OK;
 }
 
+// Large segments: min/max, decisions (entropy where the span calls for it),
+// the radix list's digit passes, then the quick list's sample-sort levels
+// (device-driven: `levels` of them; host-driven when levels < 0), and the
+// features of the sorted segments when the caller asked for them.
+ahs_status seg_large_all(SegCall& C, uint64_t max_seg, int levels) {
+  SortJob& j = C.j;
+  const uint32_t cu = j.ctx->cu_count ? j.ctx->cu_count : 256;
+  const int variant = j.ctx->seg_radix_variant[j.kk][C.pay];
+  {
+    ProfScope p(j.ctx, "seg_dispatch", j.s);
+    AHS_HIP(j, launch_seg_dispatch(j.kk, C.d, cu, j.s), "large-segment decisions");
+  }
+  AHS_HIP(j, launch_ss_tiles(C.T.segs[0], C.rec0, (uint32_t)ss_tile(j.key_bytes), (uint32_t)C.S.seg_cap, j.s),
+          "tiles");
+  {
+    ProfScope p(j.ctx, "seg_radix_digits", j.s);
+    AHS_HIP(j, launch_seg_radix_prepare(j.kk, C.d, seg_radix_tile(j.key_bytes, C.pay, variant), cu, j.s),
+            "radix digit counts");
+  }
+  const int npass = j.key_bytes == 4 ? 5 : SEG_MAX_PASSES;  // digits, plus a repeated first pass in place
+  for (int q = 0; q < npass; ++q) {
+    ProfScope p(j.ctx, "seg_radix_pass", j.s);
+    AHS_HIP(j, launch_seg_radix_pass(j.kk, C.pay, variant, C.d, q, max_seg, cu, j.s), "radix pass");
+  }
+  if (levels > 0) {
+    AHS_TRY(ss_levels_device(j, C.S, C.T, C.rec0, levels, max_seg));
+  } else if (levels < 0) {
+    char* pin = static_cast<char*>(j.ctx->pinned);
+    AHS_HIP(j, hipMemcpyAsync(pin, C.rec0, sizeof(SsCounters), hipMemcpyDeviceToHost, j.s), "copy");
+    AHS_HIP(j, hipMemcpyAsync(pin + 64, C.d.dctr, sizeof(SegDispatchCounters), hipMemcpyDeviceToHost, j.s), "copy");
+    AHS_HIP(j, hipStreamSynchronize(j.s), "synchronize");
+    SsCounters q;
+    SegDispatchCounters dc;
+    memcpy(&q, pin, sizeof q);
+    memcpy(&dc, pin + 64, sizeof dc);
+    if (dc.bad) return j.ctx->fail(AHS_E_DEVICE, "batched sort table overflow");
+    if (q.nsegs_next) AHS_TRY(ss_levels_host(j, C.S, C.T, q.nsegs_next, q.ntiles_next, q.seg_keys_next, max_seg));
+  }
+  if (C.a.feats) {
+    ProfScope p(j.ctx, "seg_large_features", j.s);
+    const uint32_t lmax = (uint32_t)std::min<uint64_t>(C.nseg, j.n / (SS_CAP + 1) + 1);
+    AHS_HIP(j,
+            launch_seg_large(j.kk, C.a, (lmax + 63) / 64, seg_chunk_resident(j.kk, cu),
+                             std::min<uint32_t>(lmax, 2 * cu), j.s),
+            "large-segment features");
+  }
+  return AHS_OK;
+}
+
 ahs_status seg_enqueue_async(SegCall& C, uint64_t n_total, uint64_t max_seg_hint, uint32_t* d_status) {
   SortJob& j = C.j;
   AHS_TRY(seg_classify(C, n_total));
@@ -170,17 +274,8 @@ ahs_status seg_enqueue_async(SegCall& C, uint64_t n_total, uint64_t max_seg_hint
   uint64_t max_seg = max_seg_hint ? std::min<uint64_t>(max_seg_hint, n_total) : n_total;
   if (max_seg > 0xFFFFFFFFull) max_seg = 0xFFFFFFFFull;
   const int levels = C.nseg ? ss_levels_for(max_seg) : 0;
-  if (levels > 0) {
-    AHS_TRY(ss_levels_device(j, C.S, C.T, C.rec0, levels, max_seg));
-    ProfScope p(j.ctx, "seg_large_features", j.s);
-    const uint32_t cu = j.ctx->cu_count ? j.ctx->cu_count : 256;
-    const uint32_t lmax = (uint32_t)std::min<uint64_t>(C.nseg, n_total / (SS_CAP + 1) + 1);
-    AHS_HIP(j,
-            launch_seg_large(j.kk, C.a, (lmax + 63) / 64, seg_chunk_resident(j.kk, cu),
-                             std::min<uint32_t>(lmax, 2 * cu), j.s),
-            "large-segment features");
-  }
-  AHS_HIP(j, launch_seg_status(C.sctr, C.T.ctr, levels, d_status, j.s), "status");
+  if (C.nseg && max_seg > (uint64_t)SS_CAP) AHS_TRY(seg_large_all(C, max_seg, levels));
+  AHS_HIP(j, launch_seg_status(C.sctr, C.T.ctr, levels, C.d.dctr, max_seg, d_status, j.s), "status");
   return AHS_OK;
 }
 
@@ -192,7 +287,7 @@ using namespace ahs;
 extern "C" size_t ahs_segmented_workspace_bytes(uint64_t n_total, uint32_t nseg, ahs_dtype dtype, int with_payload) {
   if ((int)dtype < 0 || (int)dtype > (int)AHS_I64) return 0;
   const Layout L = plan_layout(n_total, key_bytes_of(dtype), with_payload ? 1 : 0, true);
-  return seg_layout(L.total, n_total, nseg).total;
+  return seg_layout(L.total, n_total, nseg, key_bytes_of(dtype), with_payload ? 1 : 0).total;
 }
 
 extern "C" ahs_status ahs_sort_segmented(ahs_context* ctx, const void* d_keys_in, void* d_keys_out,
@@ -207,26 +302,14 @@ extern "C" ahs_status ahs_sort_segmented(ahs_context* ctx, const void* d_keys_in
   SortJob& j = C.j;
   AHS_TRY(seg_classify(C, n_total));
   char* pin = static_cast<char*>(ctx->pinned);
-  AHS_HIP(j, hipMemcpyAsync(pin, C.sctr, sizeof(SegCounters) + sizeof(SsCounters), hipMemcpyDeviceToHost, j.s),
-          "copy");
+  AHS_HIP(j, hipMemcpyAsync(pin, C.sctr, sizeof(SegCounters), hipMemcpyDeviceToHost, j.s), "copy");
   AHS_HIP(j, hipStreamSynchronize(j.s), "synchronize");
   SegCounters sc;
-  SsCounters rc;
   memcpy(&sc, pin, sizeof sc);
-  memcpy(&rc, pin + sizeof sc, sizeof rc);
   if (sc.bad) return ctx->fail(AHS_E_INVALID_ARG, "offsets are not non-decreasing or do not end at n_total");
   const double rec_bytes = 2.0 * j.key_bytes + (C.pay ? 8.0 : 0.0);
   AHS_TRY(seg_small_all(C, sc.nclass, rec_bytes * (double)sc.small_keys));
-  if (sc.nlarge) {
-    AHS_TRY(ss_levels_host(j, C.S, C.T, sc.nlarge, rc.ntiles_next, sc.large_keys, sc.max_large));
-    ProfScope p(ctx, "seg_large_features", j.s, (double)j.key_bytes * (double)sc.large_keys);
-    const uint64_t chunks = sc.large_keys / SEG_CH + sc.nlarge;
-    const uint32_t res = seg_chunk_resident(j.kk, ctx->cu_count);
-    AHS_HIP(j,
-            launch_seg_large(j.kk, C.a, (sc.nlarge + 63) / 64, (uint32_t)std::min<uint64_t>(chunks, res), sc.nlarge,
-                             j.s),
-            "large-segment features");
-  }
+  if (sc.nlarge) AHS_TRY(seg_large_all(C, sc.max_large, -1));
   return AHS_OK;
 }
 

@@ -157,6 +157,37 @@ def test_segmented_radix_decision():
     assert (chosen == ahs.RADIX).all(), chosen
 
 
+def _dispatch_parts():
+    """Large segments of every route: counting ranges (one and two digit
+    passes, a constant segment whose one pass is a copy), low-entropy wide
+    ranges (radix; one of them above 2^20 keys, so its entropy comes from two
+    histogram units, with 16-bit bin wraps from eight values over two million
+    keys), high-entropy wide ranges (sample sort; one over two units), and a
+    span below k_radix (sample sort, no histogram)."""
+    return [
+        gen.u32(61, 0, 300_000, mask=255),
+        gen.u32(61, 1, 20_000, mask=4095),
+        np.full(50_000, 7, np.uint32),
+        gen.zipf_keys(62, 200_000, 64, 1.1, 32),
+        gen.zipf_keys(63, (1 << 21) + 5, 8, 1.1, 32),
+        gen.u32(64, 0, (1 << 20) + 1),
+        gen.u32(65, 0, 30_000, mask=(1 << 20) - 1),
+        gen.u32(66, 0, 9000, mask=(1 << 19) - 1),
+        gen.u32(67, 0, 5000),
+    ]
+
+
+@pytest.mark.parametrize("mode,in_place", [("blocking", False), ("async", True), ("graph", False)])
+def test_segmented_large_dispatch(mode, in_place):
+    parts = _dispatch_parts()
+    sizes = [p.size for p in parts]
+    keys = np.concatenate(parts)
+    chosen = run_segments(keys, offsets_of(sizes), np.arange(keys.size, dtype=np.uint32), mode=mode,
+                          in_place=in_place, hint=max(sizes))
+    assert list(chosen[:5]) == [ahs.COUNTING, ahs.COUNTING, ahs.COUNTING, ahs.RADIX, ahs.RADIX]
+    assert list(chosen[5:8]) == [ahs.QUICK, ahs.QUICK, ahs.QUICK]
+
+
 @pytest.mark.parametrize("strategy", [ahs.COUNTING, ahs.RADIX, ahs.QUICK])
 def test_segmented_forced(strategy):
     keys, offs, _ = gen.segments(nseg=60, seed=24, sizes=mixed_sizes(60, 24, 1 << 15))
@@ -303,7 +334,7 @@ def test_segmented_async_hint_too_small_is_reported():
     keys, offs, _ = gen.segments(nseg=3, seed=43, sizes=np.array(sizes))
     k = to_dev(keys)
     ko, _, _, _, status = ahs.ahs_sort_segmented_async(k, to_dev(offs), max_seg_hint=100)
-    assert int(status.item()) == ahs.SEG_ERR_LEVELS
+    assert int(status.item()) == ahs.SEG_ERR_LEVELS | ahs.SEG_ERR_HINT
     # the small segments are still sorted
     ko = ko.cpu().numpy()
     assert np.array_equal(ko[:100], np.sort(keys[:100]))
