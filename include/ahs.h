@@ -208,9 +208,17 @@ ahs_status ahs_sort_static(ahs_context* ctx, const void* d_keys_in, void* d_keys
  * H lies within rounding of h_ratio * log2(nbins)).  Segments of at most
  * 8,192 keys are queued by size class (up to 1,024 / 2,048 / 4,096 / 8,192
  * keys) and each class is sorted wholly in LDS by one fused kernel that also
- * computes the segment's features and decision; larger segments go through
- * the sample-sort levels (Sec. III-G.1), all of them together, and get their
- * features from their sorted output (features do not depend on key order).
+ * computes the segment's features and decision.  Larger segments get their
+ * min/max and, where the span reaches k_radix, their entropy before they
+ * are sorted, and their decision picks the kernels that sort them, all such
+ * segments together: COUNTING and RADIX segments go through segmented
+ * stable LSD passes over the 8-bit digits of key - min that vary (Sec.
+ * III-F, III-G; a counting sort over at most 2^16 values is the same stable
+ * scatter by the bin index), QUICK segments and segments holding NaN keys
+ * through the sample-sort levels (Sec. III-G.1).  A forced strategy picks
+ * the family the same way.  When d_feats is requested the large segments'
+ * feature vectors are taken from their sorted output (features do not
+ * depend on key order).
  * d_chosen (nullable, nseg bytes) receives each segment's strategy code
  * (AHS_* values; 0xFD marks a segment holding NaN keys, whose output is its
  * keys ordered by the bit map, NaNs at the ends).  d_feats (nullable, nseg
