@@ -570,6 +570,8 @@ def parse():
     ap.add_argument("--detail-out", default=os.path.join("gpurun_out", "bench_detail.json"),
                     help="file that receives every section in full (the stdout line carries summaries)")
     ap.add_argument("--only", default=None, help="comma list of sweep cases to run")
+    ap.add_argument("--force", default="auto", choices=("auto", "counting", "radix", "quick"),
+                    help="strategy of the timed steps (auto: the method; a forced one for kernel profiles)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain elementwise copy of 2^log2n 32-bit words first (counter calibration)")
     ap.add_argument("--headline", action=argparse.BooleanOptionalAction, default=True,
@@ -638,10 +640,13 @@ def main():
     cfg_fsm = ahs.ahs_config_init(ahs.PRESET_GPU)
     torch.cuda.synchronize()
 
+    strat = ahs.STRATEGY_CODES[args.force]
+
     def step():
         chosen = {}
         for c in cases:
-            _, _, ch, _ = ahs.ahs_sort(dkeys[c], strategy=ahs.AUTO, cfg=cfg_auto, out=out, ctx=ctx)
+            _, _, ch, _ = ahs.ahs_sort(dkeys[c], strategy=strat, cfg=cfg_auto if strat == ahs.AUTO else cfg_fsm,
+                                       out=out, ctx=ctx)
             chosen[c] = ahs.STRATEGY_NAMES[ch]
         return chosen
 
@@ -676,7 +681,7 @@ def main():
     dom = max(prof.items(), key=lambda kv: kv[1][1])
     dname, (dl, dms, dbytes) = dom
     achieved = dbytes / (dms / 1e3) / 1e9 if dms > 0 else 0.0
-    tag = f"strategy_sweep_2p{args.log2n}_u32" if not args.only else None
+    tag = f"strategy_sweep_2p{args.log2n}_u32" if not args.only and args.force == "auto" else None
     traffic = measured_traffic(dname, tag) if tag else None
     roofline = {
         "bound": "hbm", "kernel": dname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -810,7 +815,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"strategy sweep: {len(cases)} arrays x 2^{args.log2n} uint32 ({', '.join(cases)}), "
-                               "AHS AUTO per array (FSM + selector trained on MI355X measurements)",
+                               + ("AHS AUTO per array (FSM + selector trained on MI355X measurements)"
+                                  if args.force == "auto" else f"strategy forced to {args.force.upper()}"),
                    "n_per_array": n, "auto_choices": chosen},
         "roofline": roofline, "cpu_baseline": cpu,
     }

@@ -23,16 +23,34 @@ struct BlockSortSmem {
 };
 
 // Loads `size` keys (mapping raw float bit patterns when `raw`) and
-// payloads into LDS.  Ends with a barrier.
+// payloads into LDS.  Every load of the thread is issued before the first
+// LDS store (a load-store loop waits out one memory latency per key).
+// Ends with a barrier.
 template <int KK, bool PAY, typename SM>
 __device__ __forceinline__ void lds_load_mapped(SM& sm, const typename KeyTraits<KK>::K* __restrict__ src,
                                                 const uint32_t* __restrict__ vsrc, uint32_t size, bool raw) {
   using K = typename KeyTraits<KK>::K;
-  for (uint32_t j = threadIdx.x; j < size; j += SM::nt) {
-    K x = src[j];
-    if constexpr (key_mapped<KK>) x = raw ? map_key<KK>(x) : x;
-    sm.keys[j] = x;
-    if constexpr (PAY) sm.vals[j] = vsrc[j];
+  constexpr int IPT = SM::cap / SM::nt;
+  const uint32_t t = threadIdx.x;
+  K x[IPT];
+  uint32_t v[IPT];
+#pragma unroll
+  for (int i = 0; i < IPT; ++i) {
+    const uint32_t j = t + (uint32_t)i * SM::nt;
+    if (j < size) {
+      x[i] = src[j];
+      if constexpr (PAY) v[i] = vsrc[j];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < IPT; ++i) {
+    const uint32_t j = t + (uint32_t)i * SM::nt;
+    if (j < size) {
+      K y = x[i];
+      if constexpr (key_mapped<KK>) y = raw ? map_key<KK>(y) : y;
+      sm.keys[j] = y;
+      if constexpr (PAY) sm.vals[j] = v[i];
+    }
   }
   __syncthreads();
 }

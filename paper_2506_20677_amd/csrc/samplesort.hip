@@ -17,13 +17,31 @@
 
 namespace ahs {
 
+// The 255 splitters of a segment are kept as an implicit perfect search
+// tree: node k (1..255) has children 2k and 2k+1, and in-order traversal
+// gives ascending order.  Node k at depth d holds the splitter of sorted
+// index (2 (k - 2^d) + 1) 2^(7-d) - 1.  A search reads one node per level,
+// and the nodes of a level are consecutive words, so the 64 lanes of a wave
+// read distinct LDS banks (or broadcast) where a search of the sorted array
+// would hit one bank from many lanes.
+__host__ __device__ __forceinline__ uint32_t ss_tree_sorted_index(uint32_t k) {
+  const uint32_t d = 31u - (uint32_t)__builtin_clz(k);
+  return ((2u * (k - (1u << d)) + 1u) << (7u - d)) - 1u;
+}
+
+// Bucket id of x: 2r + (x equals the r-th splitter), where r is the number
+// of splitters below x.  The descent ends at node 256 + r; the splitter
+// equal to x, if any, is the successor of x: the last node it went left at.
 template <typename K>
-__device__ __forceinline__ uint32_t ss_classify(K x, const K* __restrict__ spl) {
-  uint32_t r = 0;
+__device__ __forceinline__ uint32_t ss_classify(K x, const K* __restrict__ tree) {
+  uint32_t k = 1;
 #pragma unroll
-  for (uint32_t step = 128; step >= 1; step >>= 1)
-    if (spl[r + step - 1] < x) r += step;
-  const uint32_t eq = (r < (uint32_t)SS_P && spl[r] == x) ? 1u : 0u;
+  for (int l = 0; l < 8; ++l) k = 2u * k + (tree[k] < x ? 1u : 0u);
+  const uint32_t r = k - 256u;
+  // node of sorted index r: r + 1 = (2m + 1) 2^z puts it at depth 7 - z
+  const uint32_t z = (uint32_t)__builtin_ctz(r + 1u);
+  const uint32_t node = (1u << (7u - z)) + ((r + 1u) >> (z + 1u));
+  const uint32_t eq = (r < (uint32_t)SS_P && tree[node] == x) ? 1u : 0u;
   return 2u * r + eq;
 }
 
@@ -87,7 +105,9 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_sample(const typename KeyTrai
         __syncthreads();
       }
     }
-    for (int i = t; i < SS_P; i += SS_THREADS) spl[(size_t)sidx * 256 + i] = s[(i + 1) * (SS_SAMPLES / 256)];
+    // splitter i (ascending) is sample (i + 1) * SS_SAMPLES / 256; stored in tree order
+    for (int k = t + 1; k < 256; k += SS_THREADS)
+      spl[(size_t)sidx * 256 + k] = s[(ss_tree_sorted_index((uint32_t)k) + 1) * (SS_SAMPLES / 256)];
   }
 }
 
@@ -128,7 +148,7 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_count(const typename KeyTrait
       }
       __syncthreads();
       for (int b = t; b < SS_NB; b += SS_THREADS) s_cnt[b] = 0;
-      for (int i = t; i < SS_P; i += SS_THREADS) s_spl[i] = spl[(size_t)sidx * 256 + i];
+      for (int k = t + 1; k < 256; k += SS_THREADS) s_spl[k] = spl[(size_t)sidx * 256 + k];
       cur = sidx;
       __syncthreads();
     }
@@ -145,13 +165,17 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_count(const typename KeyTrait
         const uint32_t idx = b0 + (uint32_t)i * SS_THREADS + t;
         x[i] = p[idx < cnt ? idx : cnt - 1];
       }
-      // all binary searches first (their LDS reads overlap), then the counts
+      // the tree searches, CS at a time: their LDS reads overlap, while the
+      // registers stay few enough for eight waves per SIMD (the scheduler
+      // would otherwise interleave all IPT searches and halve the occupancy)
+      constexpr int CS = 2;
       uint32_t bk[IPT];
 #pragma unroll
       for (int i = 0; i < IPT; ++i) {
         K y = x[i];
         if constexpr (key_mapped<KK>) y = map_in ? map_key<KK>(y) : y;
         bk[i] = ss_classify<K>(y, s_spl);
+        if (i % CS == CS - 1) __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
       for (int i = 0; i < IPT; ++i) {
@@ -316,7 +340,7 @@ __global__ __launch_bounds__(SS_THREADS, PERSIST ? 4 : 1) void k_ss_scatter(SsSc
     if (tile >= ntiles) break;
     const uint32_t sidx = ss_seg_of_tile(a.segs, nsegs, tile);
     const SsSeg sg = a.segs[sidx];
-    for (int i = t; i < SS_P; i += SS_THREADS) s_spl[i] = ((const K*)a.spl)[(size_t)sidx * 256 + i];
+    for (int k = t + 1; k < 256; k += SS_THREADS) s_spl[k] = ((const K*)a.spl)[(size_t)sidx * 256 + k];
     const uint64_t off = (uint64_t)(tile - sg.first_tile) * TILE;
     const uint64_t rem = (uint64_t)sg.size - off;
     const uint32_t valid = rem < (uint64_t)TILE ? (uint32_t)rem : (uint32_t)TILE;
@@ -346,6 +370,9 @@ __global__ __launch_bounds__(SS_THREADS, PERSIST ? 4 : 1) void k_ss_scatter(SsSc
         k[i] = ~K(0);
         d[i] = SS_NB - 1;
       }
+      // a few tree searches at a time: interleaving all IPT of them would
+      // hold their state in registers beside the tile's keys
+      if (i % 2 == 1) __builtin_amdgcn_sched_barrier(0);
     }
 
     uint32_t r[IPT];
@@ -426,11 +453,29 @@ __device__ __forceinline__ void ss_block_item(const SsBlockArgs& a, BlockSortSme
   const uint64_t base = it.start;
   const uint32_t size = it.size;
   if (it.flags & SS_ITEM_COPY) {
-    for (uint32_t j = t; j < size; j += SS_THREADS) {
-      K x = src[base + j];
-      if constexpr (key_mapped<KK>) x = raw ? x : unmap_key<KK>(x);
-      dst[base + j] = x;
-      if constexpr (PAY) a.vout[base + j] = vsrc[base + j];
+    // groups of CI loads in flight per thread, then their stores
+    constexpr int CI = 16;
+    for (uint32_t j0 = 0; j0 < size; j0 += SS_THREADS * CI) {
+      K x[CI];
+      uint32_t v[CI];
+#pragma unroll
+      for (int i = 0; i < CI; ++i) {
+        const uint32_t j = j0 + t + (uint32_t)i * SS_THREADS;
+        if (j < size) {
+          x[i] = src[base + j];
+          if constexpr (PAY) v[i] = vsrc[base + j];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < CI; ++i) {
+        const uint32_t j = j0 + t + (uint32_t)i * SS_THREADS;
+        if (j < size) {
+          K y = x[i];
+          if constexpr (key_mapped<KK>) y = raw ? y : unmap_key<KK>(y);
+          dst[base + j] = y;
+          if constexpr (PAY) a.vout[base + j] = v[i];
+        }
+      }
     }
     return;
   }
