@@ -19,6 +19,8 @@ struct BlockSortSmem {
   uint32_t scan[NT / WAVE + 1];
   K red[2][NT / WAVE];
   double dred[NT / WAVE];
+  uint32_t gmax[NT / WAVE];
+  uint32_t grp[2][256];  // top-digit groups: start and count
   uint32_t misc[4];
 };
 
@@ -92,10 +94,21 @@ __device__ __forceinline__ void lds_rank_sort(BlockSortSmem<K, PAY, CAP, NT>& sm
 
 // Largest bucket the block sort ranks in one pass (one key per thread).
 constexpr uint32_t LDS_RANK_SORT_MAX = 512;
+// Largest group of equal top digits ranked by comparisons after a top-digit
+// pass (spans over 16 bits).
+#ifndef AHS_GROUP_RANK_MAX
+#define AHS_GROUP_RANK_MAX 64
+#endif
+constexpr uint32_t LDS_GROUP_RANK_MAX = AHS_GROUP_RANK_MAX;
+#ifndef AHS_GROUP_RANK_MIN_BITS
+#define AHS_GROUP_RANK_MIN_BITS 24
+#endif
+constexpr int LDS_GROUP_RANK_MIN_BITS = AHS_GROUP_RANK_MIN_BITS;  // spans of more bits try the group ranks
 
-// Stable LSD sort of sm.keys[0, size) (mapped keys) by 8-bit digits of
-// (key - min), as many passes as the span needs (a rank sort when the keys
-// fit one per thread); payloads move along.
+// Stable sort of sm.keys[0, size) (mapped keys) by 8-bit digits of
+// (key - min): a rank sort when the keys fit one per thread; over 16 bits of
+// span a top-digit pass and ranks inside its groups when they are small;
+// otherwise as many LSD passes as the span needs.  Payloads move along.
 // Returns min and max (mapped).  Ends with a barrier.
 template <typename K, bool PAY, int CAP, int NT>
 __device__ __forceinline__ void lds_sort_loaded(BlockSortSmem<K, PAY, CAP, NT>& sm, uint32_t size, K& out_min,
@@ -128,23 +141,31 @@ __device__ __forceinline__ void lds_sort_loaded(BlockSortSmem<K, PAY, CAP, NT>& 
     return;
   }
 
-  // items of this wave holding at least one key (wave-uniform): a wave whose
-  // items lie past `size` holds only padding, which sorts last and is never
-  // read back, so those items are neither ranked nor placed
-  const uint32_t wbase = (uint32_t)w * WAVE * IPT;
-  const uint32_t nfill = size > wbase ? (size - wbase + WAVE - 1) / WAVE : 0u;
-  const int nv = nfill < (uint32_t)IPT ? (int)nfill : IPT;
-  for (int p = 0; p < npass; ++p) {
+  // the keys are spread over all waves: wave w ranks the `per` items
+  // [w * per * WAVE, (w + 1) * per * WAVE) in (item, lane) order, so ranks
+  // stay stable, and a bucket half the capacity gives every wave half its
+  // items (the serial rank steps of a wave are per item).  Items past
+  // `size` hold only padding, which sorts last and is never read back.
+  const uint32_t per = (size + NT - 1) / NT;
+  const uint32_t wbase = (uint32_t)w * WAVE * per;
+  const uint32_t wend = wbase + WAVE * per < size ? wbase + WAVE * per : size;
+  const int nv = wend > wbase ? (int)((wend - wbase + WAVE - 1) / WAVE) : 0;
+
+  // One stable pass by the 8-bit digit ((key - min) >> shift) & 255.  With
+  // gmax > 0 the pass is abandoned before it moves a key when some digit
+  // holds more than gmax keys (returns false); it then records every digit's
+  // group (start, count) in sm.grp.
+  auto pass = [&](uint32_t shift, uint32_t gmax) -> bool {
     K k[IPT];
     uint32_t v[IPT];
     uint32_t d[IPT];
 #pragma unroll
     for (int i = 0; i < IPT; ++i) {
       const uint32_t idx = wbase + (uint32_t)i * WAVE + lane;
-      if (idx < size) {
+      if (i < nv && idx < size) {
         k[i] = sm.keys[idx];
         if constexpr (PAY) v[i] = sm.vals[idx];
-        d[i] = (uint32_t)(((k[i] - mn) >> (8 * p)) & 255u);
+        d[i] = (uint32_t)(((k[i] - mn) >> shift) & 255u);
       } else {
         k[i] = ~K(0);
         if constexpr (PAY) v[i] = 0;
@@ -171,12 +192,25 @@ __device__ __forceinline__ void lds_sort_loaded(BlockSortSmem<K, PAY, CAP, NT>& 
         cnt += sm.slot[u][t].count;
       }
     }
+    if (gmax) {
+      const uint32_t m = wave_max(t < 256 ? cnt : 0u);
+      if (lane == 0) sm.gmax[w] = m;
+      __syncthreads();
+      uint32_t big = 0;
+#pragma unroll
+      for (int u = 0; u < NW; ++u) big = sm.gmax[u] > big ? sm.gmax[u] : big;
+      if (big > gmax) return false;  // every slot count has been read: the next pass may clear them
+    }
     uint32_t total;
     const uint32_t tstart = block_excl_scan<NT>(t < 256 ? cnt : 0u, sm.scan, total);
     uint32_t(*pos)[256] = reinterpret_cast<uint32_t(*)[256]>(&sm.slot[0][0]);
     if (t < 256) {
 #pragma unroll
       for (int u = 0; u < NW; ++u) pos[u][t] = wpre[u] + tstart;
+      if (gmax) {
+        sm.grp[0][t] = tstart;
+        sm.grp[1][t] = cnt;
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -190,7 +224,67 @@ __device__ __forceinline__ void lds_sort_loaded(BlockSortSmem<K, PAY, CAP, NT>& 
       }
     }
     __syncthreads();
+    return true;
+  };
+
+  const int bits = bitlen64((uint64_t)(mx - mn));
+  if (bits > LDS_GROUP_RANK_MIN_BITS) {
+    // Wide spans: one pass by the top 8 bits, then, if no group of
+    // equal top digits holds more than LDS_GROUP_RANK_MAX keys, each key is
+    // ranked inside its group (the keys before it that are smaller, or equal
+    // at a lower index: stable), instead of ceil(bits / 8) LSD passes.
+    const uint32_t shift = (uint32_t)bits - 8u;
+    if (pass(shift, LDS_GROUP_RANK_MAX)) {
+      // destinations first (u16, over the free slots), then the moves: a
+      // thread holds no per-item rank state, only its keys while they move
+      uint16_t* s_dst = reinterpret_cast<uint16_t*>(&sm.slot[0][0]);
+      static_assert(sizeof(uint16_t) * CAP <= sizeof(sm.slot), "destinations fit over the slots");
+      for (uint32_t j = (uint32_t)t; j < size; j += NT) {
+        const K x = sm.keys[j];
+        const uint32_t dg = (uint32_t)(((x - mn) >> shift) & 255u);
+        const uint32_t gs = sm.grp[0][dg];
+        const uint32_t ge = gs + sm.grp[1][dg] < size ? gs + sm.grp[1][dg] : size;
+        uint32_t rk = 0;
+        uint32_t q = gs;
+        for (; q + 4u <= ge; q += 4u) {  // four reads in flight
+          const K y0 = sm.keys[q], y1 = sm.keys[q + 1], y2 = sm.keys[q + 2], y3 = sm.keys[q + 3];
+          rk += (y0 < x || (y0 == x && q < j)) ? 1u : 0u;
+          rk += (y1 < x || (y1 == x && q + 1u < j)) ? 1u : 0u;
+          rk += (y2 < x || (y2 == x && q + 2u < j)) ? 1u : 0u;
+          rk += (y3 < x || (y3 == x && q + 3u < j)) ? 1u : 0u;
+        }
+        for (; q < ge; ++q) {
+          const K y = sm.keys[q];
+          rk += (y < x || (y == x && q < j)) ? 1u : 0u;
+        }
+        s_dst[j] = (uint16_t)(gs + rk);
+      }
+      __syncthreads();
+      K k[IPT];
+      uint32_t v[IPT];
+#pragma unroll
+      for (int i = 0; i < IPT; ++i) {
+        const uint32_t j = (uint32_t)t + (uint32_t)i * NT;
+        if (j < size) {
+          k[i] = sm.keys[j];
+          if constexpr (PAY) v[i] = sm.vals[j];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < IPT; ++i) {
+        const uint32_t j = (uint32_t)t + (uint32_t)i * NT;
+        if (j < size) {
+          const uint32_t o = s_dst[j];
+          sm.keys[o] = k[i];
+          if constexpr (PAY) sm.vals[o] = v[i];
+        }
+      }
+      __syncthreads();
+      return;
+    }
   }
+  for (int p = 0; p < npass; ++p) pass(8u * (uint32_t)p, 0u);
 }
 
 // Sum over the runs of equal bins (key - kmin) >> shift inside one chunk of
