@@ -7,8 +7,9 @@
 //             sample sort; a forced strategy; COUNTING when the span is below
 //             k_count; QUICK when it is below k_radix; otherwise the segment
 //             joins the hist list, whose entropy decides RADIX or QUICK.
-//   hist      one workgroup per unit of at most SEG_HU keys of a hist-list
-//             segment: 65,536 packed 16-bit LDS bins of (key - min) >> shift,
+//   hist      one workgroup per unit of a hist-list segment (the whole
+//             segment up to SEG_HU keys, else SEG_HU_MULTI keys at a time):
+//             65,536 packed 16-bit LDS bins of (key - min) >> shift,
 //             wraps repaired exactly from the atomics' return values (at most
 //             SEG_HIST_EVENTS corrections per unit), then the FP64 entropy
 //             and the decision; a segment of several units adds its units'
@@ -173,6 +174,31 @@ __global__ __launch_bounds__(SD_THREADS) void k_sd_decide(SegDispatchArgs a) {
   }
 }
 
+// Numbers the histogram units of the hist list (first unit of each
+// segment, total units), one workgroup: a segment takes one unit up to
+// SEG_HU keys, else units of SEG_HU_MULTI keys.
+constexpr int SD_UNITS_THREADS = 1024;
+__global__ __launch_bounds__(SD_UNITS_THREADS) void k_sd_hist_units(SegDispatchArgs a) {
+  __shared__ uint32_t sm[SD_UNITS_THREADS / WAVE + 1];
+  uint32_t nh = a.dctr->hist.nsegs_next;
+  nh = nh < a.list_cap ? nh : a.list_cap;
+  const uint32_t per = (nh + SD_UNITS_THREADS - 1) / SD_UNITS_THREADS;
+  const uint32_t s0 = threadIdx.x * per;
+  auto units = [&](uint32_t size) { return (size + seg_hist_unit_keys(size) - 1) / seg_hist_unit_keys(size); };
+  uint32_t local = 0;
+  for (uint32_t i = 0; i < per; ++i)
+    if (s0 + i < nh) local += units(a.hsegs[s0 + i].size);
+  uint32_t total;
+  uint32_t run = block_excl_scan<SD_UNITS_THREADS>(local, sm, total);
+  for (uint32_t i = 0; i < per; ++i) {
+    if (s0 + i < nh) {
+      a.hsegs[s0 + i].first_tile = run;
+      run += units(a.hsegs[s0 + i].size);
+    }
+  }
+  if (threadIdx.x == 0) a.dctr->hist.ntiles_next = total;
+}
+
 // Clears the global histograms of the multi-unit hist-list segments.
 __global__ __launch_bounds__(SD_THREADS) void k_sd_clear_slots(SegDispatchArgs a) {
   uint32_t ns = a.dctr->nslot;
@@ -236,8 +262,9 @@ __global__ __launch_bounds__(SEG_HIST_THREADS) void k_sd_hist(SegDispatchArgs a)
     const K kmin = (K)L.mn;
     uint32_t shift, nbins;
     shift_nbins(L.mx - L.mn, shift, nbins);
-    const uint64_t u0 = (uint64_t)(u - hg.first_tile) * SEG_HU;
-    const uint32_t cnt = (uint32_t)((uint64_t)hg.size - u0 < SEG_HU ? (uint64_t)hg.size - u0 : SEG_HU);
+    const uint32_t ukeys = seg_hist_unit_keys(hg.size);
+    const uint64_t u0 = (uint64_t)(u - hg.first_tile) * ukeys;
+    const uint32_t cnt = (uint32_t)((uint64_t)hg.size - u0 < ukeys ? (uint64_t)hg.size - u0 : ukeys);
     const bool multi = hg.size > SEG_HU;
     __syncthreads();
 
@@ -620,8 +647,7 @@ hipError_t dispatch_kk(const SegDispatchArgs& a, uint32_t cu, hipStream_t s) {
   const uint32_t grid = 4 * (cu ? cu : 256u);
   k_sd_minmax<KK><<<grid * 4, SD_THREADS, 0, s>>>(a);
   k_sd_decide<KK><<<grid, SD_THREADS, 0, s>>>(a);
-  hipError_t e = launch_ss_tiles(a.hsegs, &a.dctr->hist, SEG_HU, a.list_cap, s);
-  if (e != hipSuccess) return e;
+  k_sd_hist_units<<<1, SD_UNITS_THREADS, 0, s>>>(a);
   k_sd_clear_slots<<<grid, SD_THREADS, 0, s>>>(a);
   k_sd_hist<KK><<<resident_blocks(k_sd_hist<KK>, SEG_HIST_THREADS, cu), SEG_HIST_THREADS, 0, s>>>(a);
   k_sd_hist_final<<<grid, SD_THREADS, 0, s>>>(a);

@@ -59,8 +59,15 @@ struct SegCounters {
 // same stable scatter by the bin index, in one or two digit passes), QUICK
 // segments through the sample-sort levels.  Min/max come from a chunked
 // pass over all large segments; the entropy, needed only where the span
-// reaches k_radix, from one LDS histogram per unit of at most SEG_HU keys.
-constexpr uint32_t SEG_HU = 1u << 20;            // keys per histogram unit
+// reaches k_radix, from LDS histograms: one unit (workgroup) for a segment
+// of at most SEG_HU keys, units of SEG_HU_MULTI keys for a larger one (whose
+// units add into one global histogram per segment), so that one large
+// segment alone still spreads over many CUs.
+constexpr uint32_t SEG_HU = 1u << 20;            // largest single-unit segment
+constexpr uint32_t SEG_HU_MULTI = 1u << 18;      // unit of a larger segment
+__host__ __device__ __forceinline__ uint32_t seg_hist_unit_keys(uint32_t size) {
+  return size <= SEG_HU ? SEG_HU : SEG_HU_MULTI;
+}
 constexpr int SEG_HIST_THREADS = 1024;
 constexpr int SEG_HIST_EVENTS = 2 * (SEG_HU / 65536);  // bin corrections a unit can need
 constexpr int SEG_MAX_PASSES = 9;                // 8 digits, plus a repeated first pass (in place)

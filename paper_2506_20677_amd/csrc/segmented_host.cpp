@@ -39,7 +39,7 @@ SegLayout seg_layout(size_t base, uint64_t n_total, uint32_t nseg, int key_bytes
   // large-segment dispatch: a large segment holds more than SS_CAP keys
   L.lcap = std::min<uint64_t>(nseg, n_total / (SS_CAP + 1)) + 1;
   L.slot_cap = n_total / (SEG_HU + 1) + 1;
-  L.unit_cap = n_total / SEG_HU + L.lcap;
+  L.unit_cap = n_total / SEG_HU_MULTI + L.lcap;
   L.tile_cap = n_total / seg_radix_tile(key_bytes, with_payload, 0) + L.lcap;
   L.linfo = take(sizeof(SegLarge) * ((size_t)nseg + 1));
   L.hsegs = take(sizeof(SsSeg) * L.lcap);

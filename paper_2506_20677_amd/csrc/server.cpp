@@ -4,8 +4,9 @@
 // requests of one key class into a batch (continuous batching: a batch is
 // formed whenever a stream slot is free, from whatever is pending), sorts
 // each batch with the enqueue-only segmented sort on the slot's stream (a
-// lone large request with the single-array AUTO path), and reports
-// per-request completion with event-timed latency.  Several slots
+// batch of one request straight from the caller's buffers), so the host
+// thread never waits on the device, and reports per-request completion
+// with event-timed latency.  Several slots
 // keep batches overlapping on the device.  The caller drives progress from
 // one host thread (submit / poll / release).
 #include <chrono>
@@ -103,12 +104,6 @@ struct ahs_server {
 
 namespace {
 
-// A batch of one request above this many keys is sorted by the single-array
-// AUTO path (features, host decision, then the strategy's kernels), straight
-// from the caller's buffer: alone in a batch, a large request gains nothing
-// from the batched sort, whose large segments always take the sample sort.
-constexpr uint64_t SERVE_SINGLE_MIN = 8192;
-
 ahs_status launch_batch(ahs_server* S, int si, const BatchPlan& plan, uint64_t arena_off, const BatchMem& m) {
   ahs_context* ctx = S->ctx;
   Slot& sl = S->slots[si];
@@ -125,48 +120,28 @@ ahs_status launch_batch(ahs_server* S, int si, const BatchPlan& plan, uint64_t a
   const uint64_t kb = (uint64_t)key_bytes(plan.dtype);
   char* h_chosen = sl.pinned + S->pinned_bytes - a256(S->cfg.max_batch_requests) - 256;
   char* h_status = sl.pinned + S->pinned_bytes - 256;
-  if (nseg == 1) {
-    Request& r = S->core.reqs.at(plan.ids[0]);
-    if (r.n > SERVE_SINGLE_MIN &&
-        ahs_workspace_bytes(r.n, (ahs_dtype)plan.dtype, plan.pay, AHS_AUTO) <= m.ws_bytes) {
-      if (r.ready && ctx->check(hipStreamWaitEvent(sl.s, (hipEvent_t)r.ready, 0), "wait input") != AHS_OK)
-        return AHS_E_DEVICE;
-      ahs_strategy chosen = AHS_AUTO;
-      // blocks for the feature read only; the sort itself stays enqueued
-      const ahs_status st = ahs_sort(ctx, r.kin, b + m.kout, plan.pay ? r.vin : nullptr,
-                                     plan.pay ? reinterpret_cast<uint32_t*>(b + m.vout) : nullptr, r.n,
-                                     (ahs_dtype)plan.dtype, AHS_AUTO, &S->cfg.cfg, b + m.ws, m.ws_bytes, sl.s,
-                                     &chosen, nullptr);
-      if (st == AHS_OK) {
-        h_chosen[0] = (char)chosen;
-        const uint32_t ok = 0;
-        memcpy(h_status, &ok, 4);
-        if (!B.done && ctx->check(hipEventCreate(&B.done), "event") != AHS_OK) return AHS_E_DEVICE;
-        if (ctx->check(hipEventRecord(B.done, sl.s), "record") != AHS_OK) return AHS_E_DEVICE;
-        sl.batch = bid;
-        S->batches_run += 1;
-        S->requests_batched += 1;
-        S->peak_used = std::max(S->peak_used, S->arena.used());
-        return AHS_OK;
-      }
-      // NaN keys (refused by the single-array path before writing anything)
-      // take the batched path below, which reports them per segment
-      if (st != AHS_E_NAN) return st;
-    }
-  }
   // host staging: offsets and copy descriptors
   uint64_t* h_offs = reinterpret_cast<uint64_t*>(sl.pinned);
   CopyDesc* h_desc = reinterpret_cast<CopyDesc*>(sl.pinned + a256(8 * ((uint64_t)S->cfg.max_batch_requests + 1)));
   uint32_t ndesc = 0;
   uint64_t max_bytes = 0;
   h_offs[0] = 0;
+  // a batch of one request is sorted straight from the caller's buffers;
+  // several are gathered into the batch's contiguous block first
+  const void* kin = b + m.kin;
+  const uint32_t* vin = plan.pay ? reinterpret_cast<const uint32_t*>(b + m.vin) : nullptr;
+  if (nseg == 1) {
+    const Request& r = S->core.reqs.at(plan.ids[0]);
+    kin = r.kin;
+    vin = plan.pay ? r.vin : nullptr;
+  }
   for (uint32_t i = 0; i < nseg; ++i) {
     Request& r = S->core.reqs.at(plan.ids[i]);
     h_offs[i + 1] = h_offs[i] + r.n;
     if (r.ready) {
       if (ctx->check(hipStreamWaitEvent(sl.s, (hipEvent_t)r.ready, 0), "wait input") != AHS_OK) return AHS_E_DEVICE;
     }
-    if (r.n) {
+    if (r.n && nseg > 1) {
       h_desc[ndesc++] = CopyDesc{r.kin, b + m.kin + kb * r.offset, kb * r.n};
       if (plan.pay) h_desc[ndesc++] = CopyDesc{r.vin, b + m.vin + 4 * r.offset, 4 * r.n};
       max_bytes = std::max<uint64_t>(max_bytes, kb * r.n);
@@ -184,7 +159,7 @@ ahs_status launch_batch(ahs_server* S, int si, const BatchPlan& plan, uint64_t a
       return AHS_E_DEVICE;
   }
   ahs_status st = ahs_sort_segmented_async(
-      ctx, b + m.kin, b + m.kout, plan.pay ? reinterpret_cast<uint32_t*>(b + m.vin) : nullptr,
+      ctx, kin, b + m.kout, vin,
       plan.pay ? reinterpret_cast<uint32_t*>(b + m.vout) : nullptr, reinterpret_cast<uint64_t*>(b + m.offs), nseg,
       plan.keys, plan.max_n, (ahs_dtype)plan.dtype, AHS_AUTO, &S->cfg.cfg, b + m.ws, m.ws_bytes, sl.s,
       reinterpret_cast<uint8_t*>(b + m.chosen), nullptr, reinterpret_cast<uint32_t*>(b + m.status));

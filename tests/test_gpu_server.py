@@ -208,9 +208,9 @@ def test_server_signed_requests():
 
 
 def test_server_lone_large_request_with_nan_matches_batched_sort():
-    """A lone large request is sorted by the single-array path, which refuses
-    NaN keys; such a request falls back to the batched sort and is reported
-    like a batched segment (status OK, decision code SEG_NAN, keys in bit-map
+    """A lone large request holding NaN keys (sorted straight from the
+    caller's buffers by the enqueue-only batched sort) is reported like a
+    batched segment (status OK, decision code SEG_NAN, keys in bit-map
     order), identical to ahs_sort_segmented of it alone."""
     r = np.random.default_rng(66)
     keys = r.normal(0, 1e3, 20_000).astype(np.float32)
