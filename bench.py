@@ -118,7 +118,8 @@ def batched_section(args, ahs, gen, torch, np):
     torch.cuda.synchronize()
     ctx = ahs.default_context(0)
     caps, tune_ms = ahs.ahs_segmented_autotune(ahs.U32, False, ctx)
-    log(f"[bench] autotuned size-class variants {caps}")
+    radix_tile = ahs.ahs_segmented_get_radix_tile(ahs.U32, False, ctx)
+    log(f"[bench] autotuned size-class variants {caps}, radix tile {radix_tile} keys")
     # blocking call (one host read per sample-sort level)
     out_b, _, chosen_b, _ = ahs.ahs_sort_segmented(keys, offs, ctx=ctx)
     torch.cuda.synchronize()
@@ -143,7 +144,8 @@ def batched_section(args, ahs, gen, torch, np):
     torch.cuda.empty_cache()
     if not args.seg_loop:
         res = {"workload": f"{args.seg_count} uint32 segments, sizes log-uniform on [16, 2^20] (seed 8), {n} keys",
-               "keys": n, "autotuned_caps": caps, "graph_ms": round(graph_s * 1e3, 3),
+               "keys": n, "autotuned_caps": caps, "autotuned_radix_tile": radix_tile,
+               "graph_ms": round(graph_s * 1e3, 3),
                "graph_gkeys_s": round(n / graph_s / 1e9, 3), "blocking_ms": round(blocking_s * 1e3, 3),
                "blocking_gkeys_s": round(n / blocking_s / 1e9, 3), "graph_status": status,
                "identical_outputs": same_graph, "decisions_equal_graph_blocking": same_chosen}
@@ -171,7 +173,8 @@ def batched_section(args, ahs, gen, torch, np):
     res = {
         "workload": f"{args.seg_count} uint32 segments, sizes log-uniform on [16, 2^20] (seed 8), "
                     f"{n} keys; per-segment kinds {kinds_count}",
-        "keys": n, "autotuned_caps": caps, "autotune_kernel_ms": [round(x, 4) for x in tune_ms],
+        "keys": n, "autotuned_caps": caps, "autotuned_radix_tile": radix_tile,
+        "autotune_kernel_ms": [round(x, 4) for x in tune_ms],
         "graph_ms": round(graph_s * 1e3, 3), "graph_gkeys_s": round(n / graph_s / 1e9, 3),
         "blocking_ms": round(blocking_s * 1e3, 3), "blocking_gkeys_s": round(n / blocking_s / 1e9, 3),
         "loop_ms": round(loop_s * 1e3, 3), "loop_gkeys_s": round(n / loop_s / 1e9, 3),

@@ -283,6 +283,16 @@ void ahs_graph_destroy(ahs_graph* graph);
  * synchronises the stream. */
 ahs_status ahs_segmented_autotune(ahs_context* ctx, ahs_dtype dtype, int with_payload, void* stream, int* h_caps,
                                   double* h_ms);
+/* Tile of the segmented LSD radix passes that sort the large COUNTING and
+ * RADIX segments of a batch (Sec. III-F, III-G), in keys per tile: 512
+ * threads times the items per thread of one of two shapes per key size and
+ * payload flag (u32: 8,192 or 12,288; u32 with payload and u64: 6,144 or
+ * 9,216; u64 with payload: 4,096 or 6,144).  ahs_segmented_autotune also
+ * times both on a synthetic batch of large segments sorted with RADIX
+ * forced and keeps the faster.  Results do not depend on the choice.
+ * Setting a size that is not one of the two is AHS_E_INVALID_ARG. */
+ahs_status ahs_segmented_get_radix_tile(ahs_context* ctx, ahs_dtype dtype, int with_payload, uint32_t* h_keys_per_tile);
+ahs_status ahs_segmented_set_radix_tile(ahs_context* ctx, ahs_dtype dtype, int with_payload, uint32_t keys_per_tile);
 ahs_status ahs_segmented_get_variants(ahs_context* ctx, ahs_dtype dtype, int with_payload, int* h_caps);
 ahs_status ahs_segmented_set_variants(ahs_context* ctx, ahs_dtype dtype, int with_payload, const int* h_caps);
 

@@ -126,6 +126,8 @@ def lib():
             "ahs_segmented_autotune": (i32, [vp, i32, i32, vp, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
             "ahs_segmented_get_variants": (i32, [vp, i32, i32, C.POINTER(C.c_int)]),
             "ahs_segmented_set_variants": (i32, [vp, i32, i32, C.POINTER(C.c_int)]),
+            "ahs_segmented_get_radix_tile": (i32, [vp, i32, i32, C.POINTER(C.c_uint32)]),
+            "ahs_segmented_set_radix_tile": (i32, [vp, i32, i32, u32]),
             "ahs_server_config_init": (None, [C.POINTER(ServerConfig)]),
             "ahs_server_create": (i32, [i32, C.POINTER(ServerConfig), C.POINTER(vp)]),
             "ahs_server_now_ms": (C.c_double, [vp]),
@@ -539,6 +541,24 @@ def ahs_segmented_set_variants(dtype: int, caps, with_payload: bool = False, ctx
     ctx = ctx or default_context()
     arr = (C.c_int * 4)(*caps)
     st = lib().ahs_segmented_set_variants(ctx.handle, dtype, 1 if with_payload else 0, arr)
+    if st != OK:
+        _raise(st, ctx)
+
+
+def ahs_segmented_get_radix_tile(dtype: int, with_payload: bool = False, ctx: Context | None = None) -> int:
+    """Keys per tile of the batched sort's segmented radix passes."""
+    ctx = ctx or default_context()
+    out = C.c_uint32()
+    st = lib().ahs_segmented_get_radix_tile(ctx.handle, dtype, 1 if with_payload else 0, C.byref(out))
+    if st != OK:
+        _raise(st, ctx)
+    return out.value
+
+
+def ahs_segmented_set_radix_tile(dtype: int, keys_per_tile: int, with_payload: bool = False,
+                                 ctx: Context | None = None):
+    ctx = ctx or default_context()
+    st = lib().ahs_segmented_set_radix_tile(ctx.handle, dtype, 1 if with_payload else 0, keys_per_tile)
     if st != OK:
         _raise(st, ctx)
 

@@ -494,10 +494,68 @@ extern "C" ahs_status ahs_segmented_autotune(ahs_context* ctx, ahs_dtype dtype, 
       if (h_ms) h_ms[cls] = best_ms;
     }
   }
+  // the radix passes of large segments: both tile shapes on one synthetic
+  // batch of large segments sorted with RADIX forced (about 2^22 keys in
+  // segments of 2^14 .. 2^19 keys)
+  if (st == AHS_OK) {
+    h_offs.assign(1, 0);
+    for (uint32_t i = 0; h_offs.back() < KEYS; ++i)
+      h_offs.push_back(h_offs.back() + std::min<uint64_t>(16384u << (i % 6), KEYS - h_offs.back()));
+    const uint32_t nseg = (uint32_t)h_offs.size() - 1;
+    const uint64_t n = h_offs.back();
+    st = ctx->check(hipMemcpyAsync(offs, h_offs.data(), 8 * h_offs.size(), hipMemcpyHostToDevice, s), "copy");
+    int best = -1;
+    float best_ms = 0.f;
+    for (int v = 0; v < 2 && st == AHS_OK; ++v) {
+      ctx->seg_radix_variant[dtype][pay] = v;
+      float ms_min = 1e30f;
+      for (int rep = 0; rep < 4 && st == AHS_OK; ++rep) {  // first run warms up
+        SegCall C;
+        st = seg_setup(C, ctx, kin, kout, pay ? (const uint32_t*)vin : nullptr, pay ? (uint32_t*)vout : nullptr,
+                       (const uint64_t*)offs, nseg, n, dtype, AHS_RADIX, nullptr, ws, wsb, stream, nullptr, nullptr);
+        if (st == AHS_OK) st = seg_classify(C, n);
+        if (st != AHS_OK) break;
+        (void)hipEventRecord(e0, s);
+        st = seg_large_all(C, 16384u << 5, 0);
+        (void)hipEventRecord(e1, s);
+        if (st != AHS_OK) break;
+        st = ctx->check(hipEventSynchronize(e1), "tune sync");
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) ms_min = std::min(ms_min, ms);
+      }
+      if (st == AHS_OK && (best < 0 || ms_min < best_ms)) {
+        best = v;
+        best_ms = ms_min;
+      }
+    }
+    if (st == AHS_OK) ctx->seg_radix_variant[dtype][pay] = best;
+  }
   ctx->profiling = was_profiling;
   if (st == AHS_OK) st = ctx->check(hipStreamSynchronize(s), "synchronize");
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   release();
   return st;
+}
+
+extern "C" ahs_status ahs_segmented_get_radix_tile(ahs_context* ctx, ahs_dtype dtype, int with_payload,
+                                                   uint32_t* h_keys_per_tile) {
+  if (!ctx || !h_keys_per_tile || (int)dtype < 0 || (int)dtype > (int)AHS_I64) return AHS_E_INVALID_ARG;
+  const int pay = with_payload ? 1 : 0;
+  *h_keys_per_tile = seg_radix_tile(key_bytes_of(dtype), pay, ctx->seg_radix_variant[dtype][pay]);
+  return AHS_OK;
+}
+
+extern "C" ahs_status ahs_segmented_set_radix_tile(ahs_context* ctx, ahs_dtype dtype, int with_payload,
+                                                   uint32_t keys_per_tile) {
+  if (!ctx || (int)dtype < 0 || (int)dtype > (int)AHS_I64) return AHS_E_INVALID_ARG;
+  const int pay = with_payload ? 1 : 0;
+  for (int v = 0; v < 2; ++v) {
+    if (seg_radix_tile(key_bytes_of(dtype), pay, v) == keys_per_tile) {
+      ctx->seg_radix_variant[dtype][pay] = v;
+      return AHS_OK;
+    }
+  }
+  return ctx->fail(AHS_E_INVALID_ARG, "no radix tile of %u keys for this key type", keys_per_tile);
 }

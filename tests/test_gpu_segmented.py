@@ -388,6 +388,40 @@ def test_autotune_choices_valid(dt, pay):
     assert ahs.ahs_segmented_get_variants(dt, pay) == caps
 
 
+RADIX_TILES = {(ahs.U32, False): (8192, 12288), (ahs.U32, True): (6144, 9216), (ahs.U64, False): (6144, 9216),
+               (ahs.U64, True): (4096, 6144)}
+
+
+@pytest.mark.parametrize("dt,pay", list(RADIX_TILES))
+def test_radix_tile_choices_give_identical_results(dt, pay):
+    """Both tile shapes of the segmented radix passes give the same keys,
+    payloads and decisions (oracle-checked), and the autotuner keeps one of
+    them."""
+    sizes = [9000, 70_000, 300_000, 20, 12_345, 150_001]
+    n = sum(sizes)
+    if dt == ahs.U32:
+        keys = np.concatenate([gen.zipf_keys(70 + i, s, 64, 1.1, 32) for i, s in enumerate(sizes)])
+    else:
+        keys = np.concatenate([gen.zipf_keys(70 + i, s, 4096, 1.0, 64) for i, s in enumerate(sizes)])
+    vals = np.arange(n, dtype=np.uint32) if pay else None
+    saved = ahs.ahs_segmented_get_radix_tile(dt, pay)
+    outs = []
+    try:
+        for tile in RADIX_TILES[(dt, pay)]:
+            ahs.ahs_segmented_set_radix_tile(dt, tile, pay)
+            assert ahs.ahs_segmented_get_radix_tile(dt, pay) == tile
+            chosen = run_segments(keys, offsets_of(sizes), vals, mode="async", hint=max(sizes))
+            assert chosen[1] == ahs.RADIX and chosen[2] == ahs.RADIX
+            outs.append(chosen)
+    finally:
+        ahs.ahs_segmented_set_radix_tile(dt, saved, pay)
+    assert np.array_equal(outs[0], outs[1])
+    ahs.ahs_segmented_autotune(dt, pay)
+    assert ahs.ahs_segmented_get_radix_tile(dt, pay) in RADIX_TILES[(dt, pay)]
+    with pytest.raises(ahs.AhsError):
+        ahs.ahs_segmented_set_radix_tile(dt, 1000, pay)
+
+
 def test_every_variant_gives_identical_results():
     keys, offs, _ = gen.segments(nseg=200, seed=46, sizes=mixed_sizes(200, 46, 1 << 13))
     vals = np.arange(keys.size, dtype=np.uint32)
