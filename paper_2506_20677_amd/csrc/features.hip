@@ -11,21 +11,50 @@
 namespace ahs {
 
 // ------------------------------------------------------------------ min/max
-template <int KK>
+// MOD: also counts each non-NaN key by its mapped value modulo
+// HIST_SMALL_MAX_BINS (a speculative histogram: exact, up to a rotation by
+// min, whenever the span is below HIST_SMALL_MAX_BINS) into
+// mod_part[block][.]; NaN keys go to a spare counter.
+template <int KK, bool MOD>
 __global__ __launch_bounds__(MINMAX_THREADS) void k_minmax(const typename KeyTraits<KK>::K* __restrict__ keys,
-                                                           uint64_t n, MinMaxPartial* __restrict__ part) {
+                                                           uint64_t n, MinMaxPartial* __restrict__ part,
+                                                           uint32_t* __restrict__ mod_part) {
   using K = typename KeyTraits<KK>::K;
+  constexpr int V = 16 / sizeof(K);
+  constexpr uint32_t M = HIST_SMALL_MAX_BINS;
+  static_assert((M & (M - 1)) == 0, "modulo by masking");
+  __shared__ uint32_t h[MOD ? M + 1 : 1];
+  if constexpr (MOD) {
+    for (uint32_t b = threadIdx.x; b <= M; b += MINMAX_THREADS) h[b] = 0;
+    __syncthreads();
+  }
   K mn = ~K(0), mx = K(0);
   uint32_t nan = 0;
   const uint64_t tid = (uint64_t)blockIdx.x * MINMAX_THREADS + threadIdx.x;
-  for_each_key<K, 4>(keys, n, tid, (uint64_t)gridDim.x * MINMAX_THREADS, [&](K b) {
-    if constexpr (KeyTraits<KK>::FLT) {
-      if (fnan(b)) { ++nan; return; }
+  for_each_group<K, 4>(keys, n, tid, (uint64_t)gridDim.x * MINMAX_THREADS, [&](const K (&kb)[V], int m) {
+    uint32_t bins[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      bins[i] = M;
+      if (i < m) {
+        const K b = kb[i];
+        if (KeyTraits<KK>::FLT && fnan(b)) {
+          ++nan;
+        } else {
+          const K x = map_key<KK>(b);
+          mn = x < mn ? x : mn;
+          mx = x > mx ? x : mx;
+          bins[i] = (uint32_t)x & (M - 1u);
+        }
+      }
     }
-    const K m = map_key<KK>(b);
-    mn = m < mn ? m : mn;
-    mx = m > mx ? m : mx;
+    if constexpr (MOD) lds_count_group<V>(h, bins, m);
   });
+  if constexpr (MOD) {
+    __syncthreads();
+    uint32_t* out = mod_part + (size_t)blockIdx.x * M;
+    for (uint32_t b = threadIdx.x; b < M; b += MINMAX_THREADS) out[b] = h[b];
+  }
   mn = wave_min(mn);
   mx = wave_max(mx);
   nan = wave_sum(nan);
@@ -90,27 +119,41 @@ __global__ __launch_bounds__(256) void k_minmax_final(const MinMaxPartial* __res
       const int ndig = radix ? (bl + 7) / 8 > 1 ? (bl + 7) / 8 : 1 : 0;
       uint32_t plan = PLAN_ON | (need ? 0u : PLAN_SKIP) | ((uint32_t)ndig << 4);
       if (f.nbins > (uint32_t)HIST_SMALL_MAX_BINS || ndig > 0) plan |= PLAN_LARGE;
+      // the min/max pass's modulo counts are the exact histogram when every
+      // key - min lies below the modulus (shift 0, at most that many bins)
+      if (pc.fused && need && !(plan & PLAN_LARGE) && f.span < (uint64_t)HIST_SMALL_MAX_BINS) plan |= PLAN_FUSED;
       f.reserved = plan;
     }
     *df = f;
   }
 }
 
+template <int KK>
+static void minmax_kk(const void* keys, uint64_t n, MinMaxPartial* partials, int nblocks, uint32_t* mod,
+                      hipStream_t s) {
+  using K = typename KeyTraits<KK>::K;
+  if (mod)
+    k_minmax<KK, true><<<nblocks, MINMAX_THREADS, 0, s>>>((const K*)keys, n, partials, mod);
+  else
+    k_minmax<KK, false><<<nblocks, MINMAX_THREADS, 0, s>>>((const K*)keys, n, partials, nullptr);
+}
+
 hipError_t launch_minmax(int kk, const void* keys, uint64_t n, MinMaxPartial* partials, int nblocks,
-                         DevFeatures* df, hipStream_t s, const FeaturePlanCfg* plan_cfg) {
+                         DevFeatures* df, hipStream_t s, const FeaturePlanCfg* plan_cfg, uint32_t* mod_partials) {
   switch (kk) {
-    case KK_U32: k_minmax<KK_U32><<<nblocks, MINMAX_THREADS, 0, s>>>((const uint32_t*)keys, n, partials); break;
-    case KK_U64: k_minmax<KK_U64><<<nblocks, MINMAX_THREADS, 0, s>>>((const uint64_t*)keys, n, partials); break;
-    case KK_F32: k_minmax<KK_F32><<<nblocks, MINMAX_THREADS, 0, s>>>((const uint32_t*)keys, n, partials); break;
-    case KK_I32: k_minmax<KK_I32><<<nblocks, MINMAX_THREADS, 0, s>>>((const uint32_t*)keys, n, partials); break;
-    case KK_F64: k_minmax<KK_F64><<<nblocks, MINMAX_THREADS, 0, s>>>((const uint64_t*)keys, n, partials); break;
-    case KK_I64: k_minmax<KK_I64><<<nblocks, MINMAX_THREADS, 0, s>>>((const uint64_t*)keys, n, partials); break;
+    case KK_U32: minmax_kk<KK_U32>(keys, n, partials, nblocks, mod_partials, s); break;
+    case KK_U64: minmax_kk<KK_U64>(keys, n, partials, nblocks, mod_partials, s); break;
+    case KK_F32: minmax_kk<KK_F32>(keys, n, partials, nblocks, mod_partials, s); break;
+    case KK_I32: minmax_kk<KK_I32>(keys, n, partials, nblocks, mod_partials, s); break;
+    case KK_F64: minmax_kk<KK_F64>(keys, n, partials, nblocks, mod_partials, s); break;
+    case KK_I64: minmax_kk<KK_I64>(keys, n, partials, nblocks, mod_partials, s); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   FeaturePlanCfg pc = {};
   if (plan_cfg) pc = *plan_cfg;
+  pc.fused = (plan_cfg && mod_partials) ? 1u : 0u;
   k_minmax_final<<<1, 256, 0, s>>>(partials, nblocks, n, df, pc);
   return hipGetLastError();
 }
@@ -127,7 +170,7 @@ __global__ __launch_bounds__(HIST_SMALL_THREADS) void k_hist_small(const typenam
   using K = typename KeyTraits<KK>::K;
   __shared__ uint32_t h[HIST_SMALL_MAX_BINS];
   if (plan) {
-    if (plan->reserved & (PLAN_SKIP | PLAN_LARGE)) return;
+    if (plan->reserved & (PLAN_SKIP | PLAN_LARGE | PLAN_FUSED)) return;
     kmin = (K)plan->min_key;
     shift = plan->shift;
     nbins = plan->nbins;
@@ -311,7 +354,7 @@ __global__ __launch_bounds__(HRED_THREADS) void k_hist_reduce(const uint32_t* __
                                                               uint32_t* __restrict__ hist_out, uint64_t n,
                                                               double* __restrict__ hpart,
                                                               const DevFeatures* __restrict__ plan,
-                                                              int ngroups_large) {
+                                                              int ngroups_large, int ngroups_fused) {
   __shared__ uint32_t s0[HRED_SLICES][HRED_ITEMS], s1[HRED_SLICES][HRED_ITEMS];
   const int it = threadIdx.x % HRED_ITEMS, sl = threadIdx.x / HRED_ITEMS;
   if (plan) {
@@ -323,7 +366,11 @@ __global__ __launch_bounds__(HRED_THREADS) void k_hist_reduce(const uint32_t* __
     large = (p & PLAN_LARGE) ? 1 : 0;
     nbins = plan->nbins;
     if (large) ngroups = ngroups_large;
+    if (p & PLAN_FUSED) ngroups = ngroups_fused;
   }
+  // fused: block g's count of key - min == b sits at its modulo slot (b + min) mod M
+  const bool fused = plan && (plan->reserved & PLAN_FUSED);
+  const uint32_t rot = fused ? (uint32_t)plan->min_key & (uint32_t)(HIST_SMALL_MAX_BINS - 1) : 0u;
   const uint32_t item = blockIdx.x * HRED_ITEMS + it;
   const uint32_t nitems = large ? (nbins + 1u) / 2u : nbins;
   uint32_t c0 = 0, c1 = 0;
@@ -334,6 +381,9 @@ __global__ __launch_bounds__(HRED_THREADS) void k_hist_reduce(const uint32_t* __
         c0 += w & 0xFFFFu;
         c1 += w >> 16;
       }
+    } else if (fused) {
+      const uint32_t slot = (item + rot) & (uint32_t)(HIST_SMALL_MAX_BINS - 1);
+      for (int g = sl; g < ngroups; g += HRED_SLICES) c0 += partials[(size_t)g * HIST_SMALL_MAX_BINS + slot];
     } else {
       for (int g = sl; g < ngroups; g += HRED_SLICES) c0 += partials[(size_t)g * nbins + item];
     }
@@ -375,14 +425,15 @@ __global__ __launch_bounds__(HRED_THREADS) void k_hist_reduce(const uint32_t* __
 
 hipError_t launch_hist_reduce(const uint32_t* partials, int ngroups, uint32_t nbins, int large,
                               const uint32_t* corr, uint32_t* hist_out, uint64_t n, double* hpart,
-                              int* nparts_out, hipStream_t s, const DevFeatures* plan, int ngroups_large) {
+                              int* nparts_out, hipStream_t s, const DevFeatures* plan, int ngroups_large,
+                              int ngroups_fused) {
   const uint32_t items = large ? (nbins + 1u) / 2u : nbins;
   // with a plan the bins are known on the device only: cover the largest
   // histogram; blocks past the last bin contribute a zero partial
   const int nb = plan ? HRED_MAX_BLOCKS : (int)((items + HRED_ITEMS - 1) / HRED_ITEMS);
   *nparts_out = nb;
   k_hist_reduce<<<nb, HRED_THREADS, 0, s>>>(partials, ngroups, nbins, large, corr, hist_out, n, hpart, plan,
-                                            ngroups_large);
+                                            ngroups_large, ngroups_fused);
   return hipGetLastError();
 }
 

@@ -72,6 +72,15 @@ void ahs_context::prof_end(hipStream_t s) {
   (void)hipEventRecord(pending.back().b, s);
 }
 
+void ahs_context::prof_set_last_bytes(const char* name, double bytes) {
+  for (auto it = pending.rbegin(); it != pending.rend(); ++it) {
+    if (it->name == name) {
+      it->bytes = bytes;
+      return;
+    }
+  }
+}
+
 void ahs_context::prof_collect() {
   for (auto& r : pending) {
     (void)hipEventSynchronize(r.b);

@@ -57,6 +57,9 @@ struct ahs_context {
   hipEvent_t take_event();
   void prof_begin(const char* name, hipStream_t s, double bytes);
   void prof_end(hipStream_t s);
+  // Sets the algorithmic bytes of the latest pending launch record named
+  // `name` (launches whose work the device decides, known after a read-back).
+  void prof_set_last_bytes(const char* name, double bytes);
   void prof_collect();
 };
 

@@ -94,6 +94,7 @@ inline size_t status_word_bytes(uint64_t n) { return n < STATUS32_MAX_N ? 4 : 8;
 constexpr uint32_t PLAN_ON = 1u << 31;
 constexpr uint32_t PLAN_LARGE = 1u;  // the 65,536-bin packed histogram (else the exact small one)
 constexpr uint32_t PLAN_SKIP = 2u;   // no histogram needed
+constexpr uint32_t PLAN_FUSED = 4u;  // the exact histogram is the min/max pass's modulo counts, rotated by min
 inline __host__ __device__ int plan_digits(uint32_t plan) { return (int)((plan >> 4) & 15u); }
 // Of those digits, the ones the fused histogram counts per key: digit p
 // (bits 8p .. 8p+7 of key - min) with 8p >= shift is (bin >> (8p - shift))
@@ -105,12 +106,18 @@ inline __host__ __device__ int plan_fused_digits(uint32_t plan, uint32_t shift) 
 }
 struct FeaturePlanCfg {
   uint64_t kcount_minus1, k_radix, n_small;
-  uint32_t enabled, model, want_hist, pad;
+  uint32_t enabled, model, want_hist;
+  uint32_t fused;  // the min/max pass also counted every key by its mapped value modulo HIST_SMALL_MAX_BINS
 };
 constexpr int HRED_MAX_BLOCKS = 1024;  // reduce blocks covering 65,536 bins
 
+// With mod_partials (AUTO only) every block also counts its non-NaN keys
+// by mapped value modulo HIST_SMALL_MAX_BINS into mod_partials[block][.]:
+// when the span turns out below HIST_SMALL_MAX_BINS that is the exact
+// histogram of key - min rotated by min, and the plan marks it PLAN_FUSED.
 hipError_t launch_minmax(int kk, const void* keys, uint64_t n, MinMaxPartial* partials, int nblocks,
-                         DevFeatures* df, hipStream_t s, const FeaturePlanCfg* plan_cfg = nullptr);
+                         DevFeatures* df, hipStream_t s, const FeaturePlanCfg* plan_cfg = nullptr,
+                         uint32_t* mod_partials = nullptr);
 hipError_t launch_hist_small(int kk, const void* keys, uint64_t n, uint64_t kmin, uint32_t shift,
                              uint32_t nbins, uint32_t* partials, int nblocks, hipStream_t s,
                              const DevFeatures* plan = nullptr);
@@ -122,7 +129,7 @@ hipError_t launch_hist_large(int kk, const void* keys, uint64_t n, uint64_t kmin
 hipError_t launch_hist_reduce(const uint32_t* partials, int ngroups, uint32_t nbins, int large,
                               const uint32_t* corr, uint32_t* hist_out, uint64_t n, double* hpart,
                               int* nparts_out, hipStream_t s, const DevFeatures* plan = nullptr,
-                              int ngroups_large = 0);
+                              int ngroups_large = 0, int ngroups_fused = 0);
 hipError_t launch_entropy_final(const double* hpart, int nparts, DevFeatures* df, hipStream_t s);
 
 // ---------------------------------------------------------------- counting

@@ -95,13 +95,16 @@ static ahs_status step_features_auto(SortJob& j, const ahs_config& c, bool model
   pc.n_small = c.n_small;
   pc.model = model ? 1u : 0u;
   pc.want_hist = want_hist ? 1u : 0u;
+  uint32_t* parts = at<uint32_t>(j.ws, j.L.hist_parts);
   {
+    // the exact histogram is counted speculatively in the same read (modulo
+    // counts in the histogram partials), used when the span turns out small
     ProfScope p(j.ctx, "minmax", j.s, (double)j.key_bytes * j.n);
     AHS_HIP(j,
-            launch_minmax(j.kk, j.kin, j.n, at<MinMaxPartial>(j.ws, j.L.mm), minmax_blocks(j.n), df, j.s, &pc),
+            launch_minmax(j.kk, j.kin, j.n, at<MinMaxPartial>(j.ws, j.L.mm), minmax_blocks(j.n), df, j.s, &pc,
+                          parts),
             "minmax launch");
   }
-  uint32_t* parts = at<uint32_t>(j.ws, j.L.hist_parts);
   uint32_t* corr = at<uint32_t>(j.ws, j.L.corr);
   const int gs = hist_small_blocks(j.n), gl = hist_large_blocks(j.n);
   AHS_HIP(j, launch_fill_u32(corr, 65536, 0u, j.s), "fill");
@@ -116,7 +119,7 @@ static ahs_status step_features_auto(SortJob& j, const ahs_config& c, bool model
     int nparts = 0;
     AHS_HIP(j,
             launch_hist_reduce(parts, gs, 0, 0, corr, at<uint32_t>(j.ws, j.L.hist), j.n, at<double>(j.ws, j.L.hpart),
-                               &nparts, j.s, df, gl),
+                               &nparts, j.s, df, gl, minmax_blocks(j.n)),
             "histogram reduce");
     AHS_HIP(j, launch_entropy_final(at<double>(j.ws, j.L.hpart), nparts, df, j.s), "entropy");
   }
@@ -136,6 +139,9 @@ static ahs_status step_features_auto(SortJob& j, const ahs_config& c, bool model
   memcpy(&j.f, pin, sizeof(DevFeatures));
   const uint32_t plan = j.f.reserved;
   j.f.reserved = 0;
+  // the histogram kernels read the keys only when the plan needed a
+  // histogram that the min/max pass did not already count
+  if (plan & (PLAN_SKIP | PLAN_FUSED)) j.ctx->prof_set_last_bytes("feature_hist", 0.0);
   const int ndig = plan_digits(plan);
   dcounts->ndig = ndig;
   if (ndig > 0) memcpy(dcounts->c, pin + 256, 4 * 256 * (size_t)ndig);
