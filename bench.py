@@ -68,11 +68,29 @@ def host_info():
     return {"cpu_model": model, "nproc": os.cpu_count()}
 
 
-def source_sha():
+# The sources each timed kernel family is compiled from: a committed
+# counter summary describes a kernel only while these are unchanged.
+KERNEL_SOURCES = {
+    "onesweep_pass": ["radix.hip", "onesweep.hpp", "common.hpp", "kernels.hpp"],
+    "minmax": ["features.hip", "histcommon.hpp", "common.hpp", "kernels.hpp"],
+    "feature_hist": ["features.hip", "histcommon.hpp", "common.hpp", "kernels.hpp"],
+    "counting_expand": ["counting.hip", "common.hpp", "kernels.hpp"],
+    "ss_block_sort": ["samplesort.hip", "blocksort.hpp", "onesweep.hpp", "samplesort.hpp", "common.hpp", "kernels.hpp"],
+    "ss_scatter": ["samplesort.hip", "onesweep.hpp", "samplesort.hpp", "common.hpp", "kernels.hpp"],
+    "ss_count": ["samplesort.hip", "samplesort.hpp", "common.hpp", "kernels.hpp"],
+}
+
+
+def source_sha(kernel=None):
+    """Hash of the kernel family's sources (all library sources when the
+    family is unknown)."""
     import glob
     import hashlib
+    csrc = os.path.join(ROOT, "paper_2506_20677_amd", "csrc")
+    files = [os.path.join(csrc, f) for f in KERNEL_SOURCES[kernel]] if kernel in KERNEL_SOURCES else \
+        sorted(glob.glob(os.path.join(csrc, "*")))
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2506_20677_amd", "csrc", "*"))):
+    for f in files:
         h.update(os.path.basename(f).encode())
         h.update(open(f, "rb").read())
     return h.hexdigest()[:16]
@@ -80,8 +98,8 @@ def source_sha():
 
 def measured_traffic(kernel, tag):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary of this workload, or None when the kernel sources changed since
-    the counters were taken."""
+    summary of this workload, or None when the kernel's sources changed
+    since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"traffic_{tag}.json")
     try:
         with open(path) as f:
@@ -89,7 +107,7 @@ def measured_traffic(kernel, tag):
     except OSError:
         return None
     k = t.get("kernels", {}).get(kernel)
-    if t.get("source_sha") != source_sha() or not k or k["fetch_bytes_per_launch"] is None:
+    if not k or k.get("source_sha") != source_sha(kernel) or k["fetch_bytes_per_launch"] is None:
         return None
     return k["fetch_bytes_per_launch"] + (k["write_bytes_per_launch"] or 0)
 

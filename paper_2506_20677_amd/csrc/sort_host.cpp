@@ -13,6 +13,10 @@ namespace ahs {
 
 static int key_bytes_of(ahs_dtype d) { return (d == AHS_U32 || d == AHS_F32 || d == AHS_I32) ? 4 : 8; }
 
+// Smallest input whose AUTO min/max pass also counts the exact histogram
+// (its grid then has at least 256 workgroups).
+constexpr uint64_t FUSED_HIST_MIN_N = 1ull << 27;
+
 // Radix digit counts read back to the host (up to 8 digits of 256 bins).
 // A fixed array: the sort path makes no heap allocation.
 struct DigitCounts {
@@ -97,12 +101,15 @@ static ahs_status step_features_auto(SortJob& j, const ahs_config& c, bool model
   pc.want_hist = want_hist ? 1u : 0u;
   uint32_t* parts = at<uint32_t>(j.ws, j.L.hist_parts);
   {
-    // the exact histogram is counted speculatively in the same read (modulo
-    // counts in the histogram partials), used when the span turns out small
+    // from FUSED_HIST_MIN_N keys on, the exact histogram is counted
+    // speculatively in the same read (modulo counts in the histogram
+    // partials), used when the span turns out small.  Below it the min/max
+    // grid is too small to carry the LDS counting at full speed, and the
+    // second read costs less than the counting would.
     ProfScope p(j.ctx, "minmax", j.s, (double)j.key_bytes * j.n);
     AHS_HIP(j,
             launch_minmax(j.kk, j.kin, j.n, at<MinMaxPartial>(j.ws, j.L.mm), minmax_blocks(j.n), df, j.s, &pc,
-                          parts),
+                          j.n >= FUSED_HIST_MIN_N ? parts : nullptr),
             "minmax launch");
   }
   uint32_t* corr = at<uint32_t>(j.ws, j.L.corr);
