@@ -105,9 +105,19 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_sample(const typename KeyTrai
         __syncthreads();
       }
     }
-    // splitter i (ascending) is sample (i + 1) * SS_SAMPLES / 256; stored in tree order
-    for (int k = t + 1; k < 256; k += SS_THREADS)
-      spl[(size_t)sidx * 256 + k] = s[(ss_tree_sorted_index((uint32_t)k) + 1) * (SS_SAMPLES / 256)];
+    // q distinct splitter positions, q = size / SS_TARGET clamped to [1, 255]:
+    // a segment splits into about q + 1 ranges of SS_TARGET keys (a small
+    // segment into a few block-sort buckets instead of 511 tiny ones).
+    // Splitter i (ascending) is sample (floor(i q / 255) + 1) SS_SAMPLES /
+    // (q + 1); repeated splitters only leave buckets empty.  With q = 255
+    // splitter i is sample (i + 1) SS_SAMPLES / 256.  Stored in tree order.
+    uint32_t q = sg.size / (uint32_t)SS_TARGET;
+    q = q < 1u ? 1u : (q > (uint32_t)SS_P ? (uint32_t)SS_P : q);
+    for (int k = t + 1; k < 256; k += SS_THREADS) {
+      const uint32_t i = ss_tree_sorted_index((uint32_t)k);
+      const uint32_t pos = (uint32_t)(((uint64_t)(i * q / (uint32_t)SS_P) + 1u) * SS_SAMPLES / (q + 1u));
+      spl[(size_t)sidx * 256 + k] = s[pos];
+    }
   }
 }
 
