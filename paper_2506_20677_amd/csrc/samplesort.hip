@@ -67,56 +67,69 @@ __global__ void k_ss_init(SsSeg* segs, SsItem* items, uint64_t n) {
 }
 
 // ------------------------------------------------------------------ sample + splitters
-// One block per segment (grid stride): SS_SAMPLES keys at pseudo-random
-// positions, sorted in LDS by a bitonic network; splitter i is sample
-// (i + 1) * 32.  Also clears the segment's bucket counts.
+// One block per segment (grid stride).  A segment of `size` keys gets
+// q = size / SS_TARGET splitters (clamped to [1, SS_P]): about q + 1 ranges
+// of SS_TARGET keys, so a medium segment splits into a few block-sort
+// buckets instead of 511 tiny ones.  The sample holds about 32 keys per
+// range, ns = 32 (q + 1) rounded up to a power of two in [512, SS_SAMPLES],
+// drawn at pseudo-random positions and sorted by the in-LDS block sort.
+// Splitter i (ascending) is sample (floor(i q / 255) + 1) ns / (q + 1):
+// q distinct positions, each repeated; repeated splitters only leave
+// buckets empty.  With q = 255, splitter i is sample (i + 1) ns / 256.
+// Splitters are stored in tree order.  Also clears the bucket counts.
+__host__ __device__ __forceinline__ uint32_t ss_splitters(uint32_t size) {
+  const uint32_t q = size / (uint32_t)SS_TARGET;
+  return q < 1u ? 1u : (q > (uint32_t)SS_P ? (uint32_t)SS_P : q);
+}
+__host__ __device__ __forceinline__ uint32_t ss_sample_size(uint32_t q) {
+  uint32_t ns = (uint32_t)SS_THREADS;
+  while (ns < 32u * (q + 1u) && ns < (uint32_t)SS_SAMPLES) ns <<= 1;
+  return ns;
+}
+
 template <int KK>
 __global__ __launch_bounds__(SS_THREADS) void k_ss_sample(const typename KeyTraits<KK>::K* __restrict__ src,
                                                           int map_in, const SsSeg* __restrict__ segs, SsLevelIn lv,
                                                           typename KeyTraits<KK>::K* __restrict__ spl,
                                                           uint32_t* __restrict__ counts, uint64_t seed) {
   using K = typename KeyTraits<KK>::K;
-  __shared__ K s[SS_SAMPLES];
-  const int t = threadIdx.x;
+  using Smem = BlockSortSmem<K, false, SS_SAMPLES, SS_THREADS>;
+  constexpr int IPT = SS_SAMPLES / SS_THREADS;
+  __shared__ Smem sm;
+  const uint32_t t = threadIdx.x;
   const uint32_t nsegs = lv.segs_n();
   for (uint32_t sidx = blockIdx.x; sidx < nsegs; sidx += gridDim.x) {
     __syncthreads();  // the previous segment's splitters have been read
     const SsSeg sg = segs[sidx];
-    for (int b = t; b < SS_NB; b += SS_THREADS) counts[(size_t)sidx * SS_NB + b] = 0u;
+    for (uint32_t b = t; b < (uint32_t)SS_NB; b += SS_THREADS) counts[(size_t)sidx * SS_NB + b] = 0u;
+    const uint32_t q = ss_splitters(sg.size);
+    const uint32_t ns = ss_sample_size(q);
     const uint64_t base = ss_mix(seed ^ (sg.start * 0x9E3779B97F4A7C15ull));
-    for (int j = t; j < SS_SAMPLES; j += SS_THREADS) {
-      const uint64_t h = ss_mix(base + (uint64_t)(j + 1) * 0x9E3779B97F4A7C15ull);
-      const uint64_t pos = sg.start + (((h >> 32) * (uint64_t)sg.size) >> 32);
-      K x = src[pos];
-      if constexpr (key_mapped<KK>) x = map_in ? map_key<KK>(x) : x;
-      s[j] = x;
-    }
-    __syncthreads();
-    for (int k = 2; k <= SS_SAMPLES; k <<= 1) {
-      for (int jj = k >> 1; jj > 0; jj >>= 1) {
-        for (int i = t; i < SS_SAMPLES; i += SS_THREADS) {
-          const int ixj = i ^ jj;
-          if (ixj > i) {
-            const K a = s[i], b = s[ixj];
-            const bool up = (i & k) == 0;
-            if ((a > b) == up) { s[i] = b; s[ixj] = a; }
-          }
-        }
-        __syncthreads();
+    K x[IPT];
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {  // every gather in flight before the first LDS store
+      const uint32_t j = t + (uint32_t)i * SS_THREADS;
+      if (j < ns) {
+        const uint64_t h = ss_mix(base + (uint64_t)(j + 1) * 0x9E3779B97F4A7C15ull);
+        x[i] = src[sg.start + (((h >> 32) * (uint64_t)sg.size) >> 32)];
       }
     }
-    // q distinct splitter positions, q = size / SS_TARGET clamped to [1, 255]:
-    // a segment splits into about q + 1 ranges of SS_TARGET keys (a small
-    // segment into a few block-sort buckets instead of 511 tiny ones).
-    // Splitter i (ascending) is sample (floor(i q / 255) + 1) SS_SAMPLES /
-    // (q + 1); repeated splitters only leave buckets empty.  With q = 255
-    // splitter i is sample (i + 1) SS_SAMPLES / 256.  Stored in tree order.
-    uint32_t q = sg.size / (uint32_t)SS_TARGET;
-    q = q < 1u ? 1u : (q > (uint32_t)SS_P ? (uint32_t)SS_P : q);
-    for (int k = t + 1; k < 256; k += SS_THREADS) {
-      const uint32_t i = ss_tree_sorted_index((uint32_t)k);
-      const uint32_t pos = (uint32_t)(((uint64_t)(i * q / (uint32_t)SS_P) + 1u) * SS_SAMPLES / (q + 1u));
-      spl[(size_t)sidx * 256 + k] = s[pos];
+#pragma unroll
+    for (int i = 0; i < IPT; ++i) {
+      const uint32_t j = t + (uint32_t)i * SS_THREADS;
+      if (j < ns) {
+        K y = x[i];
+        if constexpr (key_mapped<KK>) y = map_in ? map_key<KK>(y) : y;
+        sm.keys[j] = y;
+      }
+    }
+    __syncthreads();
+    K mn, mx;
+    lds_sort_loaded(sm, ns, mn, mx);
+    for (uint32_t k = t + 1; k < 256u; k += SS_THREADS) {
+      const uint32_t i = ss_tree_sorted_index(k);
+      const uint32_t pos = (i * q / (uint32_t)SS_P + 1u) * ns / (q + 1u);
+      spl[(size_t)sidx * 256 + k] = sm.keys[pos];
     }
   }
 }

@@ -11,7 +11,7 @@ namespace ahs {
 
 constexpr int SS_P = 255;             // splitters per segment
 constexpr int SS_NB = 512;            // bucket-id space (2 * SS_P + 1 used)
-constexpr int SS_SAMPLES = 8192;      // sample keys per segment
+constexpr int SS_SAMPLES = 8192;      // most sample keys per segment
 constexpr int SS_CAP = 8192;          // largest bucket finished in LDS
 constexpr int SS_TARGET = 4096;       // bucket size a level aims at (splitters per segment: size / SS_TARGET, <= 255)
 constexpr int SS_THREADS = 512;
