@@ -226,48 +226,29 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_count(const typename KeyTrait
 
 // ------------------------------------------------------------------ plan
 // One block per segment (grid stride): bucket start positions (exclusive
-// scan of the counts from the segment start) and the fate of every bucket:
-// equal-key buckets are final (copied out unless already in place), buckets
-// of at most SS_CAP keys become block-sort items, larger ones next-level
-// segments.
-__device__ __forceinline__ void ss_plan_bucket(const SsSeg& sg, uint32_t b, uint32_t c, uint32_t ex, uint32_t dst_buf,
-                                               int copy_in_place, SsSeg* __restrict__ next,
-                                               SsItem* __restrict__ items, SsCounters* __restrict__ ctr,
-                                               uint32_t item_cap, uint32_t seg_cap) {
-  const uint64_t pos = sg.start + ex;
-  if (c == 0) return;
-  if (b & 1) {
-    if (dst_buf == SS_BUF_OUT && !copy_in_place) return;
-    const uint32_t nchunks = (c + SS_CAP - 1) / SS_CAP;
-    atomicAdd(&ctr->item_keys, (unsigned long long)c);
-    const uint32_t at = atomicAdd(&ctr->nitems, nchunks);
-    for (uint32_t q = 0; q < nchunks; ++q) {
-      if (at + q >= item_cap) { atomicOr(&ctr->overflow, 1u); break; }
-      SsItem it;
-      it.start = pos + (uint64_t)q * SS_CAP;
-      it.size = (c - q * SS_CAP) < SS_CAP ? (c - q * SS_CAP) : SS_CAP;
-      it.flags = SS_ITEM_COPY | (dst_buf << 8);
-      items[at + q] = it;
-    }
-  } else if (c <= SS_CAP) {
-    atomicAdd(&ctr->item_keys, (unsigned long long)c);
-    const uint32_t at = atomicAdd(&ctr->nitems, 1u);
-    if (at >= item_cap) { atomicOr(&ctr->overflow, 1u); return; }
-    SsItem it;
-    it.start = pos;
-    it.size = c;
-    it.flags = dst_buf << 8;
-    items[at] = it;
-  } else {
-    atomicAdd(&ctr->seg_keys_next, (unsigned long long)c);
-    const uint32_t at = atomicAdd(&ctr->nsegs_next, 1u);
-    if (at >= seg_cap) { atomicOr(&ctr->overflow, 2u); return; }
-    SsSeg ns;
-    ns.start = pos;
-    ns.size = c;
-    ns.first_tile = 0;
-    next[at] = ns;
+// scan of the counts from the segment start) and the fate of every bucket.
+// A bucket of more than SS_CAP / 2 keys stands alone: an equal-key bucket
+// is final (copied out unless already in place), an open bucket becomes a
+// block-sort item when it has at most SS_CAP keys, else a next-level
+// segment.  Smaller buckets of both kinds merge into runs; a run starts at
+// a small bucket that follows a standalone one or whose start crosses a
+// multiple of SS_CAP / 2, so every run holds fewer than SS_CAP keys.  The
+// buckets are ordered ranges, so sorting a run sorts each bucket: a run
+// with keys of an open bucket is one block-sort item, a run of equal-key
+// buckets only is already sorted and is copied (or left in place).  Merging
+// replaces the many tiny items of small segments and of single-key equal
+// buckets by items near SS_CAP / 2 keys.  Items and next-level segments
+// are numbered with one counter update per segment.
+__device__ __forceinline__ bool ss_mask_any(const uint64_t* __restrict__ m, uint32_t lo, uint32_t hi) {
+  // any bit of the 512-bit mask m in [lo, hi), lo < hi
+  for (uint32_t u = lo / WAVE; u * WAVE < hi; ++u) {
+    uint64_t x = m[u];
+    if (u == lo / WAVE) x &= ~0ull << (lo % WAVE);
+    const uint32_t top = hi - u * WAVE;
+    if (top < (uint32_t)WAVE) x &= (1ull << top) - 1ull;
+    if (x) return true;
   }
+  return false;
 }
 
 __global__ __launch_bounds__(SS_NB) void k_ss_plan(const SsSeg* __restrict__ segs, SsLevelIn lv,
@@ -275,16 +256,116 @@ __global__ __launch_bounds__(SS_NB) void k_ss_plan(const SsSeg* __restrict__ seg
                                                    uint32_t dst_buf, int copy_in_place, SsSeg* __restrict__ next,
                                                    SsItem* __restrict__ items, SsCounters* __restrict__ ctr,
                                                    uint32_t item_cap, uint32_t seg_cap) {
-  __shared__ uint32_t sm[SS_NB / WAVE + 1];
+  constexpr int NW = SS_NB / WAVE;
+  constexpr uint32_t W = SS_CAP / 2;
+  __shared__ uint32_t sm[NW + 1];
+  __shared__ uint64_t sm64[NW + 1];
+  __shared__ uint32_t s_ex[SS_NB + 1];
+  __shared__ uint64_t s_bound[NW], s_open[NW];
+  __shared__ unsigned long long s_keys[NW];
+  __shared__ uint32_t s_base[2];
   const uint32_t nsegs = lv.segs_n();
-  const int b = threadIdx.x;
+  const uint32_t b = threadIdx.x;
+  const int w = (int)b / WAVE, lane = lane_id();
+  const bool eq_final = dst_buf == SS_BUF_OUT && !copy_in_place;  // equal-key buckets already in place
   for (uint32_t sidx = blockIdx.x; sidx < nsegs; sidx += gridDim.x) {
     const SsSeg sg = segs[sidx];
     const uint32_t c = counts[(size_t)sidx * SS_NB + b];
     uint32_t total;
     const uint32_t ex = block_excl_scan<SS_NB>(c, sm, total);  // ends with a barrier
     offs[(size_t)sidx * SS_NB + b] = ex;  // relative to the segment start
-    ss_plan_bucket(sg, (uint32_t)b, c, ex, dst_buf, copy_in_place, next, items, ctr, item_cap, seg_cap);
+    s_ex[b] = ex;
+    if (b == 0) s_ex[SS_NB] = total;
+    __syncthreads();
+    const bool small = c <= W;
+    bool start = false;
+    if (small) {
+      if (b == 0) {
+        start = true;
+      } else {
+        const uint32_t pex = s_ex[b - 1];
+        start = ex - pex > W || ex / W != pex / W;
+      }
+    }
+    const uint64_t bm = __ballot(start || !small);
+    const uint64_t om = __ballot((b & 1u) == 0u && c > 0u);
+    if (lane == 0) { s_bound[w] = bm; s_open[w] = om; }
+    __syncthreads();
+    // this bucket's items and segments, and its item / segment keys
+    uint32_t n_it = 0, n_sg = 0, len = 0, flags = dst_buf << 8;
+    uint64_t k_it = 0, k_sg = 0;
+    if (start) {
+      uint32_t e = SS_NB;  // first boundary after b
+      const uint64_t above = lane == WAVE - 1 ? 0ull : bm & (~0ull << (lane + 1));
+      if (above) {
+        e = (uint32_t)w * WAVE + (uint32_t)__builtin_ctzll(above);
+      } else {
+        for (int u = w + 1; u < NW; ++u)
+          if (s_bound[u]) { e = (uint32_t)u * WAVE + (uint32_t)__builtin_ctzll(s_bound[u]); break; }
+      }
+      len = s_ex[e] - ex;
+      if (len > 0) {
+        if (ss_mask_any(s_open, b, e)) {
+          n_it = 1;
+        } else if (!eq_final) {
+          n_it = 1;
+          flags |= SS_ITEM_COPY;
+        }
+      }
+    } else if (!small) {
+      len = c;
+      if (b & 1u) {
+        if (!eq_final) n_it = (c + SS_CAP - 1) / SS_CAP;
+        flags |= SS_ITEM_COPY;
+      } else if (c <= (uint32_t)SS_CAP) {
+        n_it = 1;
+      } else {
+        n_sg = 1;
+      }
+    }
+    if (n_it) k_it = len;
+    if (n_sg) k_sg = len;
+    // a segment has fewer than 2^32 keys: item and segment keys pack into
+    // one 64-bit sum without carries
+    const unsigned long long kw = wave_sum((unsigned long long)(k_it | (k_sg << 32)));
+    if (lane == 0) s_keys[w] = kw;
+    uint64_t tot_pack;
+    const uint64_t o_pack = block_excl_scan<SS_NB>((uint64_t)n_it | ((uint64_t)n_sg << 32), sm64, tot_pack);
+    if (b == 0) {
+      unsigned long long ks = 0;
+#pragma unroll
+      for (int u = 0; u < NW; ++u) ks += s_keys[u];
+      const uint32_t tot_it = (uint32_t)tot_pack, tot_sg = (uint32_t)(tot_pack >> 32);
+      s_base[0] = tot_it ? atomicAdd(&ctr->nitems, tot_it) : 0u;
+      s_base[1] = tot_sg ? atomicAdd(&ctr->nsegs_next, tot_sg) : 0u;
+      if (ks & 0xFFFFFFFFull) atomicAdd(&ctr->item_keys, ks & 0xFFFFFFFFull);
+      if (ks >> 32) atomicAdd(&ctr->seg_keys_next, ks >> 32);
+    }
+    __syncthreads();
+    const uint64_t pos = sg.start + ex;
+    if (n_it) {
+      const uint32_t at = s_base[0] + (uint32_t)o_pack;
+      for (uint32_t q = 0; q < n_it; ++q) {
+        if (at + q >= item_cap) { atomicOr(&ctr->overflow, 1u); break; }
+        SsItem it;
+        it.start = pos + (uint64_t)q * SS_CAP;
+        it.size = (len - q * SS_CAP) < (uint32_t)SS_CAP ? (len - q * SS_CAP) : (uint32_t)SS_CAP;
+        it.flags = flags;
+        items[at + q] = it;
+      }
+    }
+    if (n_sg) {
+      const uint32_t at = s_base[1] + (uint32_t)(o_pack >> 32);
+      if (at >= seg_cap) {
+        atomicOr(&ctr->overflow, 2u);
+      } else {
+        SsSeg ns;
+        ns.start = pos;
+        ns.size = len;
+        ns.first_tile = 0;
+        next[at] = ns;
+      }
+    }
   }
 }
 

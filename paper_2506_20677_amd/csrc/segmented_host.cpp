@@ -429,7 +429,11 @@ extern "C" ahs_status ahs_segmented_autotune(ahs_context* ctx, ahs_dtype dtype, 
   // the class's size range
   constexpr uint64_t KEYS = 1u << 22;
   constexpr uint32_t MAXSEG = KEYS / 512 + 1;  // smallest class lower bound is 1 key
-  const uint64_t nmax = KEYS + SEG_CLASS_CAP[SEG_NCLASS - 1];
+  // the radix tile is timed on a batch large enough to keep every CU busy
+  // for many tiles: on a small batch the smaller tile wins by its shorter
+  // tail although it is slower per key on large batches
+  constexpr uint64_t RKEYS = 1u << 26;
+  const uint64_t nmax = RKEYS;
   const size_t wsb = ahs_segmented_workspace_bytes(nmax, MAXSEG * 8, dtype, pay);
   void *kin = nullptr, *kout = nullptr, *vin = nullptr, *vout = nullptr, *ws = nullptr, *offs = nullptr;
   auto release = [&]() {
@@ -495,12 +499,12 @@ extern "C" ahs_status ahs_segmented_autotune(ahs_context* ctx, ahs_dtype dtype, 
     }
   }
   // the radix passes of large segments: both tile shapes on one synthetic
-  // batch of large segments sorted with RADIX forced (about 2^22 keys in
+  // batch of large segments sorted with RADIX forced (2^26 keys in
   // segments of 2^14 .. 2^19 keys)
   if (st == AHS_OK) {
     h_offs.assign(1, 0);
-    for (uint32_t i = 0; h_offs.back() < KEYS; ++i)
-      h_offs.push_back(h_offs.back() + std::min<uint64_t>(16384u << (i % 6), KEYS - h_offs.back()));
+    for (uint32_t i = 0; h_offs.back() < RKEYS; ++i)
+      h_offs.push_back(h_offs.back() + std::min<uint64_t>(16384u << (i % 6), RKEYS - h_offs.back()));
     const uint32_t nseg = (uint32_t)h_offs.size() - 1;
     const uint64_t n = h_offs.back();
     st = ctx->check(hipMemcpyAsync(offs, h_offs.data(), 8 * h_offs.size(), hipMemcpyHostToDevice, s), "copy");
