@@ -1,7 +1,6 @@
 // In-LDS stable sort of up to CAP keys by one workgroup of NT threads, and
 // the run statistics of a sorted key array (for features computed after
-// sorting).  NT >= 256 (one thread per digit) and CAP / NT <= 16 (the run
-// scratch of CAP words reuses the rank slots).
+// sorting).  NT >= 256 (one thread per digit) and CAP / NT <= 16.
 #pragma once
 
 #include "onesweep.hpp"
@@ -13,7 +12,13 @@ template <typename K, bool PAY, int CAP = SS_CAP, int NT = SS_THREADS>
 struct BlockSortSmem {
   static_assert(NT >= 256 && CAP % NT == 0 && CAP / NT <= 16, "block sort shape");
   static constexpr int cap = CAP, nt = NT, nw = NT / WAVE;
-  RankSlot slot[NT / WAVE][256];  // rank slots, then each pass's position table
+  // rank state of each wave, then each pass's position table, the u16
+  // destinations of the group ranks or the run starts of lds_run_entropy
+  static constexpr size_t RANK_BYTES = sizeof(RankLds<256>) * (NT / WAVE);
+  static constexpr size_t SCRATCH_BYTES = RANK_BYTES > sizeof(uint32_t) * CAP ? RANK_BYTES : sizeof(uint32_t) * CAP;
+  __align__(16) unsigned char scratch[SCRATCH_BYTES];
+  __device__ RankLds<256>* rank() { return reinterpret_cast<RankLds<256>*>(scratch); }
+  __device__ uint32_t (*pos())[256] { return reinterpret_cast<uint32_t(*)[256]>(scratch); }
   K keys[CAP];
   uint32_t vals[PAY ? CAP : 1];
   uint32_t scan[NT / WAVE + 1];
@@ -61,7 +66,7 @@ __device__ __forceinline__ void lds_load_mapped(SM& sm, const typename KeyTraits
 // and counts the keys that sort before it, smaller keys and equal keys at
 // lower indices (keys of lower waves: <=; of higher waves: <; of its own
 // wave: by lane).  One pass of size^2 / NT broadcast reads and compares: for
-// small buckets this beats the LSD passes, whose slot clearing, scans and
+// small buckets this beats the LSD passes, whose state clearing, scans and
 // barriers cost about the same at any size.  Ends with a barrier.
 template <typename K, bool PAY, int CAP, int NT>
 __device__ __forceinline__ void lds_rank_sort(BlockSortSmem<K, PAY, CAP, NT>& sm, uint32_t size) {
@@ -172,24 +177,21 @@ __device__ __forceinline__ void lds_sort_loaded(BlockSortSmem<K, PAY, CAP, NT>& 
         d[i] = 255u;
       }
     }
-    // the previous pass's position table overlays the slots: clear them whole
-    for (int i = t; i < NW * 256; i += NT) {
-      (&sm.slot[0][0])[i].mask = 0ull;
-      (&sm.slot[0][0])[i].count = 0u;
-    }
+    // the previous pass's position table overlays the rank state: clear it whole
+    rank_clear<256, NT>(sm.rank(), NW);
     __syncthreads();
     uint32_t r[IPT];
-    rank_wave_items<IPT>(d, r, sm.slot[w], nv);
+    rank_wave_items<IPT>(d, r, sm.rank()[w], nv);
     __syncthreads();
     // per-wave exclusive prefixes of digit t in registers; after the scan's
-    // first barrier (every slot count read) a dense per-(wave, digit) table
-    // of tile positions overlays the slots: one LDS read per key
+    // first barrier (every count read) a dense per-(wave, digit) table of
+    // tile positions overlays the rank state: one LDS read per key
     uint32_t cnt = 0, wpre[NW];
     if (t < 256) {
 #pragma unroll
       for (int u = 0; u < NW; ++u) {
         wpre[u] = cnt;
-        cnt += sm.slot[u][t].count;
+        cnt += sm.rank()[u].count[t];
       }
     }
     if (gmax) {
@@ -199,11 +201,12 @@ __device__ __forceinline__ void lds_sort_loaded(BlockSortSmem<K, PAY, CAP, NT>& 
       uint32_t big = 0;
 #pragma unroll
       for (int u = 0; u < NW; ++u) big = sm.gmax[u] > big ? sm.gmax[u] : big;
-      if (big > gmax) return false;  // every slot count has been read: the next pass may clear them
+      if (big > gmax) return false;  // every count has been read: the next pass may clear them
     }
     uint32_t total;
     const uint32_t tstart = block_excl_scan<NT>(t < 256 ? cnt : 0u, sm.scan, total);
-    uint32_t(*pos)[256] = reinterpret_cast<uint32_t(*)[256]>(&sm.slot[0][0]);
+    uint32_t(*pos)[256] = sm.pos();
+    static_assert(sizeof(uint32_t) * NW * 256 <= BlockSortSmem<K, PAY, CAP, NT>::SCRATCH_BYTES, "position table fits");
     if (t < 256) {
 #pragma unroll
       for (int u = 0; u < NW; ++u) pos[u][t] = wpre[u] + tstart;
@@ -235,10 +238,10 @@ __device__ __forceinline__ void lds_sort_loaded(BlockSortSmem<K, PAY, CAP, NT>& 
     // at a lower index: stable), instead of ceil(bits / 8) LSD passes.
     const uint32_t shift = (uint32_t)bits - 8u;
     if (pass(shift, LDS_GROUP_RANK_MAX)) {
-      // destinations first (u16, over the free slots), then the moves: a
+      // destinations first (u16, in the free scratch), then the moves: a
       // thread holds no per-item rank state, only its keys while they move
-      uint16_t* s_dst = reinterpret_cast<uint16_t*>(&sm.slot[0][0]);
-      static_assert(sizeof(uint16_t) * CAP <= sizeof(sm.slot), "destinations fit over the slots");
+      uint16_t* s_dst = reinterpret_cast<uint16_t*>(sm.scratch);
+      static_assert(sizeof(uint16_t) * CAP <= sizeof(sm.scratch), "destinations fit in the scratch");
       for (uint32_t j = (uint32_t)t; j < size; j += NT) {
         const K x = sm.keys[j];
         const uint32_t dg = (uint32_t)(((x - mn) >> shift) & 255u);
@@ -294,7 +297,7 @@ __device__ __forceinline__ void lds_sort_loaded(BlockSortSmem<K, PAY, CAP, NT>& 
 // and after the chunk (has_prev / has_next false at the segment ends).
 // carry_start is the segment position where the run open at the chunk's
 // start began; it is updated to the start of the run open at the chunk's end.
-// Returns the block's FP64 sum (valid in every thread).  Uses sm.slot as
+// Returns the block's FP64 sum (valid in every thread).  Uses sm.scratch as
 // scratch for run starts (CAP u32 entries fit in it).
 template <typename K, bool PAY, int CAP, int NT>
 __device__ __forceinline__ double lds_run_entropy(BlockSortSmem<K, PAY, CAP, NT>& sm, uint32_t cnt, uint64_t pos0,
@@ -302,7 +305,7 @@ __device__ __forceinline__ double lds_run_entropy(BlockSortSmem<K, PAY, CAP, NT>
                                                   uint32_t shift, uint64_t n, uint64_t& carry_start) {
   constexpr int CH = CAP / NT;  // consecutive positions per thread
   const int t = threadIdx.x;
-  uint32_t* s_start = reinterpret_cast<uint32_t*>(&sm.slot[0][0]);  // run starts (chunk-relative)
+  uint32_t* s_start = reinterpret_cast<uint32_t*>(sm.scratch);  // run starts (chunk-relative)
   const uint32_t j0 = (uint32_t)t * CH;
   auto binof = [&](K x) { return (uint64_t)((x - kmin) >> shift); };
   // run starts in my positions

@@ -4,9 +4,9 @@
 //
 // A tile of OS_THREADS * IPT keys is ranked stably by an 8-bit digit:
 //   1. wave-level peer discovery without ballot chains: every lane ORs its
-//      lane bit into an LDS mask slot indexed by its digit (ds_or_b64, order
-//      irrelevant) and reads the slot back, which yields exactly the lanes
-//      sharing its digit; the group leader (highest lane) clears the slot.
+//      lane bit into an LDS mask word indexed by its digit (ds_or_b64, order
+//      irrelevant) and reads the word back, which yields exactly the lanes
+//      sharing its digit; the group leader (highest lane) clears the word.
 //      A wave whose 64 keys share one digit takes a ballot fast path.
 //   2. each wave keeps running per-digit counts over its IPT items, so the
 //      rank of a key inside its wave is (earlier items) + (lower lanes);
@@ -23,21 +23,37 @@
 
 namespace ahs {
 
-// One LDS slot per (wave, digit): the peer mask of the item being ranked
-// and the wave's running count of the digit, read back with one 16-byte
-// load.
-struct __align__(16) RankSlot {
-  uint64_t mask;
-  uint32_t count;
-  uint32_t pad;
+// Rank state of one wave over ND digits: the peer mask of the item being
+// ranked and the wave's running count of each digit, kept in two arrays.
+// Their 8- and 4-byte strides spread a wave's 64 random digits over more
+// LDS banks than one 16-byte slot per digit did (that layout cost about a
+// third more time in the ranking of a 2^28-key pass).
+template <int ND>
+struct RankLds {
+  uint64_t mask[ND];
+  uint32_t count[ND];
 };
+typedef __attribute__((address_space(3))) uint64_t lds_u64;
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
+// Zeroes the rank state of `nw` waves (the whole workgroup of NT threads
+// takes part; no barrier).
+template <int ND, int NT>
+__device__ __forceinline__ void rank_clear(RankLds<ND>* st, int nw) {
+  static_assert(sizeof(RankLds<ND>) % 16 == 0, "rank state clears as 16-byte words");
+  u32x4* p = reinterpret_cast<u32x4*>(st);
+  const int nvec = nw * (int)(sizeof(RankLds<ND>) / 16);
+  const u32x4 z = {0u, 0u, 0u, 0u};
+  for (int i = (int)threadIdx.x; i < nvec; i += NT) p[i] = z;
+}
 
 // Ranks items [0, nitems) of the wave (nitems wave-uniform; later items
-// are left unranked and must not be used).
-template <int IPT>
-__device__ __forceinline__ void rank_wave_items(const uint32_t (&d)[IPT], uint32_t (&r)[IPT],
-                                                RankSlot* __restrict__ slots /* [ND] of this wave */,
+// are left unranked and must not be used).  `st` lives in LDS.
+template <int IPT, int ND>
+__device__ __forceinline__ void rank_wave_items(const uint32_t (&d)[IPT], uint32_t (&r)[IPT], RankLds<ND>& st,
                                                 int nitems = IPT) {
+  lds_u64* mask = (lds_u64*)st.mask;
+  lds_u32* count = (lds_u32*)st.count;
   const int lane = lane_id();
   const uint64_t mybit = 1ull << lane;
 #pragma unroll
@@ -47,23 +63,22 @@ __device__ __forceinline__ void rank_wave_items(const uint32_t (&d)[IPT], uint32
       const uint32_t d0 = __builtin_amdgcn_readfirstlane(di);
       if (__ballot(di == d0) == ~0ull) {
         // the whole wave shares one digit
-        const uint32_t base = slots[d0].count;
+        const uint32_t base = count[d0];
         __builtin_amdgcn_wave_barrier();
         r[i] = base + (uint32_t)lane;
-        if (lane == WAVE - 1) slots[d0].count = base + WAVE;
+        if (lane == WAVE - 1) count[d0] = base + WAVE;
       } else {
-        __hip_atomic_fetch_or(&slots[di].mask, mybit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_or(&mask[di], mybit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         __builtin_amdgcn_wave_barrier();
-        const u32x4 sv = *reinterpret_cast<const volatile u32x4*>(&slots[di]);
+        const uint64_t peers = *(const volatile lds_u64*)&mask[di];
+        const uint32_t base = *(const volatile lds_u32*)&count[di];
         __builtin_amdgcn_wave_barrier();
-        const uint64_t peers = (uint64_t)sv.x | ((uint64_t)sv.y << 32);
-        const uint32_t base = sv.z;
         const uint32_t lt = mbcnt(peers);
         const uint32_t cnt = popc64(peers);
         r[i] = base + lt;
         if (lt == cnt - 1) {
-          const u32x4 nv = {0u, 0u, base + cnt, 0u};
-          *reinterpret_cast<volatile u32x4*>(&slots[di]) = nv;
+          *(volatile lds_u64*)&mask[di] = 0ull;
+          *(volatile lds_u32*)&count[di] = base + cnt;
         }
       }
     }

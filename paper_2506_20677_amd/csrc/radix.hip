@@ -13,15 +13,15 @@ __global__ __launch_bounds__(OS_THREADS) void k_onesweep(OnesweepArgs a) {
   using K = typename KeyTraits<KK>::K;
   constexpr int TILE = OS_THREADS * IPT;
   constexpr int NW = OS_WAVES;
-  // One LDS region holds in turn the rank slots, the dense per-(wave,
-  // digit) position table (written once every slot count has been read,
-  // after the scan's first barrier) and the staged keys (once every key's
-  // tile position is in a register).
-  constexpr size_t SLOT_BYTES = sizeof(RankSlot) * NW * 256;
+  // One LDS region holds in turn the rank state, the dense per-(wave,
+  // digit) position table (written once every count has been read, after
+  // the scan's first barrier) and the staged keys (once every key's tile
+  // position is in a register).
+  constexpr size_t SLOT_BYTES = sizeof(RankLds<256>) * NW;
   constexpr size_t KEY_BYTES = sizeof(K) * TILE;
   static_assert(sizeof(uint32_t) * NW * 256 <= SLOT_BYTES, "position table fits over the slots");
   __shared__ __align__(16) unsigned char s_raw[SLOT_BYTES > KEY_BYTES ? SLOT_BYTES : KEY_BYTES];
-  RankSlot(*s_slot)[256] = reinterpret_cast<RankSlot(*)[256]>(s_raw);
+  RankLds<256>* s_rank = reinterpret_cast<RankLds<256>*>(s_raw);
   uint32_t(*s_pos)[256] = reinterpret_cast<uint32_t(*)[256]>(s_raw);
   K* s_keys = reinterpret_cast<K*>(s_raw);
   __shared__ uint32_t s_tstart[256];
@@ -31,10 +31,7 @@ __global__ __launch_bounds__(OS_THREADS) void k_onesweep(OnesweepArgs a) {
   __shared__ uint32_t s_tile;
 
   const int t = threadIdx.x, w = t / WAVE, lane = lane_id();
-  for (int i = t; i < NW * 256; i += OS_THREADS) {
-    (&s_slot[0][0])[i].mask = 0ull;
-    (&s_slot[0][0])[i].count = 0u;
-  }
+  rank_clear<256, OS_THREADS>(s_rank, NW);
   if (t == 0) s_tile = add_agent(a.tile_counter, 1u);
   const uint32_t doff = t < 256 ? a.digit_offsets[t] : 0u;  // in flight early
   __syncthreads();
@@ -69,7 +66,7 @@ __global__ __launch_bounds__(OS_THREADS) void k_onesweep(OnesweepArgs a) {
     uint32_t d[IPT];
 #pragma unroll
     for (int i = 0; i < IPT; ++i) d[i] = digit(k[i]);
-    rank_wave_items<IPT>(d, r, s_slot[w]);
+    rank_wave_items<IPT>(d, r, s_rank[w]);
   }
   __syncthreads();
 
@@ -80,7 +77,7 @@ __global__ __launch_bounds__(OS_THREADS) void k_onesweep(OnesweepArgs a) {
 #pragma unroll
     for (int u = 0; u < NW; ++u) {
       wpre[u] = cnt;
-      cnt += s_slot[u][t].count;
+      cnt += s_rank[u].count[t];
     }
   }
   const uint64_t valid64 = a.n - tbase < (uint64_t)TILE ? a.n - tbase : (uint64_t)TILE;

@@ -408,18 +408,18 @@ __global__ __launch_bounds__(SS_THREADS, PERSIST ? 4 : 1) void k_ss_scatter(SsSc
   using K = typename KeyTraits<KK>::K;
   constexpr int TILE = SS_THREADS * IPT;
   constexpr int NW = SS_THREADS / WAVE;
-  // One LDS region holds in turn the rank slots, the dense per-(wave,
-  // bucket) position table (written once every slot count has been read,
-  // after the scan's first barrier) and the staged keys with their bucket
-  // ids (once every key's tile position is in a register).  Sharing it keeps
-  // a u32 tile near 75 KiB, so two tiles fit in a CU's LDS.
-  constexpr size_t SLOT_BYTES = sizeof(RankSlot) * NW * SS_NB;
+  // One LDS region holds in turn the rank state, the dense per-(wave,
+  // bucket) position table (written once every count has been read, after
+  // the scan's first barrier) and the staged keys with their bucket ids
+  // (once every key's tile position is in a register).  Sharing it keeps a
+  // u32 tile near 75 KiB, so two tiles fit in a CU's LDS.
+  constexpr size_t SLOT_BYTES = sizeof(RankLds<SS_NB>) * NW;
   constexpr size_t KEY_BYTES = sizeof(K) * TILE;
   constexpr size_t STAGE_BYTES = KEY_BYTES + sizeof(uint16_t) * TILE;
   static_assert(sizeof(uint32_t) * NW * SS_NB <= SLOT_BYTES, "position table fits over the slots");
   static_assert(KEY_BYTES % 16 == 0, "bucket ids start aligned after the keys");
   __shared__ __align__(16) unsigned char s_raw[SLOT_BYTES > STAGE_BYTES ? SLOT_BYTES : STAGE_BYTES];
-  RankSlot(*s_slot)[SS_NB] = reinterpret_cast<RankSlot(*)[SS_NB]>(s_raw);
+  RankLds<SS_NB>* s_rank = reinterpret_cast<RankLds<SS_NB>*>(s_raw);
   uint32_t(*s_pos)[SS_NB] = reinterpret_cast<uint32_t(*)[SS_NB]>(s_raw);
   K* s_keys = reinterpret_cast<K*>(s_raw);
   uint16_t* s_dig = reinterpret_cast<uint16_t*>(s_raw + KEY_BYTES);
@@ -429,15 +429,16 @@ __global__ __launch_bounds__(SS_THREADS, PERSIST ? 4 : 1) void k_ss_scatter(SsSc
   __shared__ uint32_t s_scan[NW + 1];
   __shared__ uint32_t s_tile;
 
-  const int t = threadIdx.x, w = t / WAVE, lane = lane_id();
   const uint32_t ntiles = a.lv.tiles_n(), nsegs = a.lv.segs_n();
   for (int iter = 0;; ++iter) {
     if (!PERSIST && iter > 0) break;  // one tile per workgroup: no loop to keep registers live across
+    // thread and lane ids made opaque per tile: otherwise the compiler hoists
+    // the per-item offsets out of the tile loop and holds (spills) them
+    uint32_t tv = threadIdx.x;
+    asm volatile("" : "+v"(tv));
+    const int t = (int)tv, w = t / WAVE, lane = t & (WAVE - 1);
     __syncthreads();  // the previous tile's LDS contents have been consumed
-    for (int i = t; i < NW * SS_NB; i += SS_THREADS) {
-      (&s_slot[0][0])[i].mask = 0ull;
-      (&s_slot[0][0])[i].count = 0u;
-    }
+    rank_clear<SS_NB, SS_THREADS>(s_rank, NW);
     if (t == 0) s_tile = add_agent(a.tile_counter, 1u);
     __syncthreads();
     const uint32_t tile = s_tile;
@@ -480,7 +481,9 @@ __global__ __launch_bounds__(SS_THREADS, PERSIST ? 4 : 1) void k_ss_scatter(SsSc
     }
 
     uint32_t r[IPT];
-    rank_wave_items<IPT>(d, r, s_slot[w]);
+    __builtin_amdgcn_sched_barrier(0);
+    rank_wave_items<IPT>(d, r, s_rank[w]);
+    __builtin_amdgcn_sched_barrier(0);
     __syncthreads();
 
     // per-wave exclusive prefixes of bucket t (one bucket per thread)
@@ -489,7 +492,7 @@ __global__ __launch_bounds__(SS_THREADS, PERSIST ? 4 : 1) void k_ss_scatter(SsSc
 #pragma unroll
     for (int u = 0; u < NW; ++u) {
       wpre[u] = cnt;
-      cnt += s_slot[u][t].count;
+      cnt += s_rank[u].count[t];
     }
     if (t == SS_NB - 1) cnt -= (uint32_t)TILE - valid;  // padding: last id, sorted last
     uint32_t total;

@@ -482,11 +482,11 @@ __global__ __launch_bounds__(SEG_RD_THREADS, 4) void k_sd_rpass(SegDispatchArgs 
   constexpr int NT = SEG_RD_THREADS;
   constexpr int NW = NT / WAVE;
   constexpr int TILE = NT * IPT;
-  constexpr size_t SLOT_BYTES = sizeof(RankSlot) * NW * 256;
+  constexpr size_t SLOT_BYTES = sizeof(RankLds<256>) * NW;
   constexpr size_t KEY_BYTES = sizeof(K) * TILE;
   static_assert(sizeof(uint32_t) * NW * 256 <= SLOT_BYTES, "position table fits over the slots");
   __shared__ __align__(16) unsigned char s_raw[SLOT_BYTES > KEY_BYTES ? SLOT_BYTES : KEY_BYTES];
-  RankSlot(*s_slot)[256] = reinterpret_cast<RankSlot(*)[256]>(s_raw);
+  RankLds<256>* s_rank = reinterpret_cast<RankLds<256>*>(s_raw);
   uint32_t(*s_pos)[256] = reinterpret_cast<uint32_t(*)[256]>(s_raw);
   K* s_keys = reinterpret_cast<K*>(s_raw);
   __shared__ uint32_t s_dadj[256];
@@ -502,10 +502,7 @@ __global__ __launch_bounds__(SEG_RD_THREADS, 4) void k_sd_rpass(SegDispatchArgs 
   const int t = threadIdx.x, w = t / WAVE;
   for (;;) {
     __syncthreads();  // the previous tile's LDS contents are consumed
-    for (int i = t; i < NW * 256; i += NT) {
-      (&s_slot[0][0])[i].mask = 0ull;
-      (&s_slot[0][0])[i].count = 0u;
-    }
+    rank_clear<256, NT>(s_rank, NW);
     if (t == 0) s_tile = add_agent(&a.dctr->tile_ctr[1 + q], 1u);
     __syncthreads();
     const uint32_t tile = s_tile;
@@ -562,7 +559,7 @@ __global__ __launch_bounds__(SEG_RD_THREADS, 4) void k_sd_rpass(SegDispatchArgs 
       uint32_t d[IPT];
 #pragma unroll
       for (int i = 0; i < IPT; ++i) d[i] = digit(k[i]);
-      rank_wave_items<IPT>(d, r, s_slot[w]);
+      rank_wave_items<IPT>(d, r, s_rank[w]);
     }
     __syncthreads();
 
@@ -571,7 +568,7 @@ __global__ __launch_bounds__(SEG_RD_THREADS, 4) void k_sd_rpass(SegDispatchArgs 
 #pragma unroll
       for (int u = 0; u < NW; ++u) {
         wpre[u] = cnt;
-        cnt += s_slot[u][t].count;
+        cnt += s_rank[u].count[t];
       }
       if (t == 255) cnt -= (uint32_t)TILE - valid;
     }
