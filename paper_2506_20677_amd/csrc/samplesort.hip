@@ -11,37 +11,109 @@
 //   r = #{i : s_i < x};  id = 2r + (r < 255 && x == s_r)
 // so ids ascend with the key and duplicate splitters only leave buckets
 // empty.
+#include <type_traits>
+
 #include "blocksort.hpp"
 #include "onesweep.hpp"
 #include "samplesort.hpp"
 
 namespace ahs {
 
-// The 255 splitters of a segment are kept as an implicit perfect search
-// tree: node k (1..255) has children 2k and 2k+1, and in-order traversal
-// gives ascending order.  Node k at depth d holds the splitter of sorted
-// index (2 (k - 2^d) + 1) 2^(7-d) - 1.  A search reads one node per level,
-// and the nodes of a level are consecutive words, so the 64 lanes of a wave
-// read distinct LDS banks (or broadcast) where a search of the sorted array
-// would hit one bank from many lanes.
+// Bucket classification.  A key's bucket id is 2r + (x equals the r-th
+// splitter), r = #{s_i < x} over the sorted splitters s_0 <= ... <= s_254.
+//
+// Cell table (most segments).  The range [s_0, s_254] is cut into C cells
+// (1,024 for 32-bit keys, 512 for 64-bit) of 2^shift values from s_0 (the
+// smallest shift that covers it).  cnt[c] = #{i : cell(s_i) < c}, c = 0..C,
+// is a non-decreasing step
+// function, so the splitters inside cell c are exactly those of index
+// [cnt[c], cnt[c + 1]); a key x in cell c has r = cnt[c] + #{i in [cnt[c],
+// cnt[c + 1]) : s_i < x}, a search over the few splitters of its own cell
+// (none or one for most keys) in place of eight steps over all 255.  A key
+// at or below s_0 has r = 0, a key past the last cell r = 255.
+//
+// Search tree (segments whose splitters crowd into cells: more than
+// SS_CELL_MAX in one, as skewed or duplicate-heavy keys give).  The 255
+// splitters as an implicit perfect search tree: node k (1..255) has children
+// 2k and 2k + 1, in-order traversal gives ascending order, and node k at
+// depth d holds the splitter of sorted index (2 (k - 2^d) + 1) 2^(7-d) - 1.
+// A search reads one node per level, and the nodes of a level are
+// consecutive words, so the 64 lanes of a wave read distinct LDS banks (or
+// broadcast) where a binary search of the sorted array would hit one bank
+// from many lanes.
+//
+// The sample kernel writes both layouts, the cell table and the choice into
+// the segment's splitter record (ss_spl_rec_bytes); the count and scatter
+// kernels load the layout the record names.
+constexpr uint32_t SS_CELL_MAX = 16;
+constexpr uint32_t SS_TREE = 0x80000000u;  // layout flag in the record's shift word
+
 __host__ __device__ __forceinline__ uint32_t ss_tree_sorted_index(uint32_t k) {
   const uint32_t d = 31u - (uint32_t)__builtin_clz(k);
   return ((2u * (k - (1u << d)) + 1u) << (7u - d)) - 1u;
 }
 
-// Bucket id of x: 2r + (x equals the r-th splitter), where r is the number
-// of splitters below x.  The descent ends at node 256 + r; the splitter
-// equal to x, if any, is the successor of x: the last node it went left at.
 template <typename K>
-__device__ __forceinline__ uint32_t ss_classify(K x, const K* __restrict__ tree) {
-  uint32_t k = 1;
+struct SsCells {
+  K spl[256];                      // sorted splitters (0..254), or the tree (nodes 1..255)
+  uint32_t cntw[ss_cell_words((int)sizeof(K))];  // cell table: cnt[c] as bytes
+  __device__ const uint8_t* cnt() const { return reinterpret_cast<const uint8_t*>(cntw); }
+};
+
+// Loads the layout a segment's record names into LDS (every thread takes
+// part; the caller places a barrier before the first use) and returns the
+// record's word (shift | SS_TREE).
+template <typename K, int NT>
+__device__ __forceinline__ uint32_t ss_cells_load(SsCells<K>& c, const void* spl, uint32_t sidx) {
+  const uint32_t su = __builtin_amdgcn_readfirstlane(sidx);  // a scalar load of the word
+  const unsigned char* rec = static_cast<const unsigned char*>(spl) + (size_t)su * ss_spl_rec_bytes((int)sizeof(K));
+  const uint32_t* rw = reinterpret_cast<const uint32_t*>(rec + sizeof(K) * 512);
+  const uint32_t word = rw[ss_cell_words((int)sizeof(K))];
+  if (word & SS_TREE) {
+    const K* rt = reinterpret_cast<const K*>(rec) + 256;
+    for (int k = (int)threadIdx.x; k < 256; k += NT) c.spl[k] = rt[k];
+  } else {
+    const K* rs = reinterpret_cast<const K*>(rec);
+    for (int k = (int)threadIdx.x; k < SS_P; k += NT) c.spl[k] = rs[k];
+    for (int k = (int)threadIdx.x; k < (int)ss_cell_words((int)sizeof(K)); k += NT) c.cntw[k] = rw[k];
+  }
+  return word;
+}
+
+// Bucket id of x in the layout TREE names (the caller branches once per
+// tile on the record's word).  base = s_0 and shift: the cell layout's.
+template <bool TREE, typename K>
+__device__ __forceinline__ uint32_t ss_classify(K x, const SsCells<K>& c, K base, uint32_t shift) {
+  if constexpr (TREE) {
+    const K* tree = c.spl;
+    uint32_t k = 1;
 #pragma unroll
-  for (int l = 0; l < 8; ++l) k = 2u * k + (tree[k] < x ? 1u : 0u);
-  const uint32_t r = k - 256u;
-  // node of sorted index r: r + 1 = (2m + 1) 2^z puts it at depth 7 - z
-  const uint32_t z = (uint32_t)__builtin_ctz(r + 1u);
-  const uint32_t node = (1u << (7u - z)) + ((r + 1u) >> (z + 1u));
-  const uint32_t eq = (r < (uint32_t)SS_P && tree[node] == x) ? 1u : 0u;
+    for (int l = 0; l < 8; ++l) k = 2u * k + (tree[k] < x ? 1u : 0u);
+    const uint32_t r = k - 256u;
+    // node of sorted index r: r + 1 = (2m + 1) 2^z puts it at depth 7 - z
+    const uint32_t z = (uint32_t)__builtin_ctz(r + 1u);
+    const uint32_t node = (1u << (7u - z)) + ((r + 1u) >> (z + 1u));
+    const uint32_t eq = (r < (uint32_t)SS_P && tree[node] == x) ? 1u : 0u;
+    return 2u * r + eq;
+  }
+  uint32_t r;
+  if (x <= base) {
+    r = 0;
+  } else {
+    const K cell = (x - base) >> shift;
+    if (cell >= (K)(1u << ss_cells_log2((int)sizeof(K)))) {
+      r = (uint32_t)SS_P;
+    } else {
+      const uint8_t* cnt = c.cnt();
+      uint32_t lo = cnt[(uint32_t)cell], hi = cnt[(uint32_t)cell + 1u];
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (c.spl[mid] < x) lo = mid + 1u; else hi = mid;
+      }
+      r = lo;
+    }
+  }
+  const uint32_t eq = (r < (uint32_t)SS_P && c.spl[r] == x) ? 1u : 0u;
   return 2u * r + eq;
 }
 
@@ -76,7 +148,9 @@ __global__ void k_ss_init(SsSeg* segs, SsItem* items, uint64_t n) {
 // Splitter i (ascending) is sample (floor(i q / 255) + 1) ns / (q + 1):
 // q distinct positions, each repeated; repeated splitters only leave
 // buckets empty.  With q = 255, splitter i is sample (i + 1) ns / 256.
-// Splitters are stored in tree order.  Also clears the bucket counts.
+// Splitters are stored in both layouts of the bucket classification, with
+// the cell table and the choice between them.  Also clears the bucket
+// counts.
 __host__ __device__ __forceinline__ uint32_t ss_splitters(uint32_t size) {
   const uint32_t q = size / (uint32_t)SS_TARGET;
   return q < 1u ? 1u : (q > (uint32_t)SS_P ? (uint32_t)SS_P : q);
@@ -90,12 +164,13 @@ __host__ __device__ __forceinline__ uint32_t ss_sample_size(uint32_t q) {
 template <int KK>
 __global__ __launch_bounds__(SS_THREADS) void k_ss_sample(const typename KeyTraits<KK>::K* __restrict__ src,
                                                           int map_in, const SsSeg* __restrict__ segs, SsLevelIn lv,
-                                                          typename KeyTraits<KK>::K* __restrict__ spl,
+                                                          void* __restrict__ spl_rec,
                                                           uint32_t* __restrict__ counts, uint64_t seed) {
   using K = typename KeyTraits<KK>::K;
   using Smem = BlockSortSmem<K, false, SS_SAMPLES, SS_THREADS>;
   constexpr int IPT = SS_SAMPLES / SS_THREADS;
   __shared__ Smem sm;
+  __shared__ uint32_t s_occ[SS_THREADS / WAVE];
   const uint32_t t = threadIdx.x;
   const uint32_t nsegs = lv.segs_n();
   for (uint32_t sidx = blockIdx.x; sidx < nsegs; sidx += gridDim.x) {
@@ -126,10 +201,41 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_sample(const typename KeyTrai
     __syncthreads();
     K mn, mx;
     lds_sort_loaded(sm, ns, mn, mx);
-    for (uint32_t k = t + 1; k < 256u; k += SS_THREADS) {
-      const uint32_t i = ss_tree_sorted_index(k);
-      const uint32_t pos = (i * q / (uint32_t)SS_P + 1u) * ns / (q + 1u);
-      spl[(size_t)sidx * 256 + k] = sm.keys[pos];
+    unsigned char* rec = static_cast<unsigned char*>(spl_rec) + (size_t)sidx * ss_spl_rec_bytes((int)sizeof(K));
+    K* rs = reinterpret_cast<K*>(rec);
+    auto splitter = [&](uint32_t i) { return sm.keys[(i * q / (uint32_t)SS_P + 1u) * ns / (q + 1u)]; };
+    for (uint32_t i = t; i < (uint32_t)SS_P; i += SS_THREADS) rs[i] = splitter(i);
+    for (uint32_t k = t + 1; k < 256u; k += SS_THREADS) rs[256 + k] = splitter(ss_tree_sorted_index(k));
+    // cell table: cnt[c] = first splitter whose cell is >= c
+    const K sbase = splitter(0);
+    const int bl = bitlen64((uint64_t)(splitter((uint32_t)SS_P - 1u) - sbase));
+    constexpr uint32_t CL = ss_cells_log2((int)sizeof(K)), NC = 1u << CL;
+    const uint32_t shift = bl > (int)CL ? (uint32_t)bl - CL : 0u;
+    auto first_at = [&](uint32_t cc) {
+      uint32_t lo = 0, hi = (uint32_t)SS_P;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (((splitter(mid) - sbase) >> shift) < (K)cc) lo = mid + 1u; else hi = mid;
+      }
+      return lo;
+    };
+    uint8_t* cnt = rec + sizeof(K) * 512;
+    uint32_t occ = 0;  // most splitters in one cell
+    for (uint32_t cc = t; cc <= NC; cc += SS_THREADS) {
+      const uint32_t lo = first_at(cc);
+      cnt[cc] = (uint8_t)lo;
+      if (cc < NC) {
+        const uint32_t o = first_at(cc + 1u) - lo;
+        occ = o > occ ? o : occ;
+      }
+    }
+    occ = wave_max(occ);
+    if (lane_id() == 0) s_occ[t / WAVE] = occ;
+    __syncthreads();
+    if (t == 0) {
+      uint32_t m = 0;
+      for (int u = 0; u < SS_THREADS / WAVE; ++u) m = s_occ[u] > m ? s_occ[u] : m;
+      reinterpret_cast<uint32_t*>(cnt)[ss_cell_words((int)sizeof(K))] = shift | (m > SS_CELL_MAX ? SS_TREE : 0u);
     }
   }
 }
@@ -150,12 +256,14 @@ template <int KK>
 __global__ __launch_bounds__(SS_THREADS) void k_ss_count(const typename KeyTraits<KK>::K* __restrict__ src, int map_in,
                                                          const SsSeg* __restrict__ segs, SsLevelIn lv,
                                                          uint32_t tile_keys,
-                                                         const typename KeyTraits<KK>::K* __restrict__ spl,
+                                                         const void* __restrict__ spl,
                                                          uint32_t* __restrict__ counts) {
   using K = typename KeyTraits<KK>::K;
-  __shared__ K s_spl[256];
+  __shared__ SsCells<K> s_cells;
   __shared__ uint32_t s_cnt[SS_NB];
   const int t = threadIdx.x;
+  K base = 0;
+  uint32_t shift = 0;
   const uint32_t nsegs = lv.segs_n(), ntiles = lv.tiles_n();
   const uint32_t per = (ntiles + gridDim.x - 1) / gridDim.x;
   const uint32_t t0 = blockIdx.x * per;
@@ -171,16 +279,17 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_count(const typename KeyTrait
       }
       __syncthreads();
       for (int b = t; b < SS_NB; b += SS_THREADS) s_cnt[b] = 0;
-      for (int k = t + 1; k < 256; k += SS_THREADS) s_spl[k] = spl[(size_t)sidx * 256 + k];
+      shift = ss_cells_load<K, SS_THREADS>(s_cells, spl, sidx);
       cur = sidx;
       __syncthreads();
+      base = s_cells.spl[0];
     }
     const SsSeg sg = segs[sidx];
     const uint64_t off = (uint64_t)(tile - sg.first_tile) * tile_keys;
     const uint64_t rem = (uint64_t)sg.size - off;
     const uint32_t cnt = rem < tile_keys ? (uint32_t)rem : tile_keys;
     const K* p = src + sg.start + off;
-    constexpr int IPT = 16;
+    constexpr int IPT = sizeof(K) == 4 ? 16 : 8;  // 64-bit keys: registers for eight waves per SIMD
     for (uint32_t b0 = 0; b0 < cnt; b0 += SS_THREADS * IPT) {
       K x[IPT];
 #pragma unroll
@@ -188,18 +297,22 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_count(const typename KeyTrait
         const uint32_t idx = b0 + (uint32_t)i * SS_THREADS + t;
         x[i] = p[idx < cnt ? idx : cnt - 1];
       }
-      // the tree searches, CS at a time: their LDS reads overlap, while the
+      // the searches, CS at a time: their LDS reads overlap, while the
       // registers stay few enough for eight waves per SIMD (the scheduler
       // would otherwise interleave all IPT searches and halve the occupancy)
       constexpr int CS = 2;
       uint32_t bk[IPT];
+      auto classify_all = [&](auto tree) {
 #pragma unroll
-      for (int i = 0; i < IPT; ++i) {
-        K y = x[i];
-        if constexpr (key_mapped<KK>) y = map_in ? map_key<KK>(y) : y;
-        bk[i] = ss_classify<K>(y, s_spl);
-        if (i % CS == CS - 1) __builtin_amdgcn_sched_barrier(0);
-      }
+        for (int i = 0; i < IPT; ++i) {
+          K y = x[i];
+          if constexpr (key_mapped<KK>) y = map_in ? map_key<KK>(y) : y;
+          bk[i] = ss_classify<decltype(tree)::value, K>(y, s_cells, base, shift & ~SS_TREE);
+          if (i % CS == CS - 1) __builtin_amdgcn_sched_barrier(0);
+        }
+      };
+      if (shift & SS_TREE) classify_all(std::true_type{});
+      else classify_all(std::false_type{});
 #pragma unroll
       for (int i = 0; i < IPT; ++i) {
         const bool ok = b0 + (uint32_t)i * SS_THREADS + t < cnt;
@@ -424,7 +537,7 @@ __global__ __launch_bounds__(SS_THREADS, PERSIST ? 4 : 1) void k_ss_scatter(SsSc
   K* s_keys = reinterpret_cast<K*>(s_raw);
   uint16_t* s_dig = reinterpret_cast<uint16_t*>(s_raw + KEY_BYTES);
   __shared__ uint32_t s_dadj[SS_NB];  // segment-relative position of tile key j with id b: s_dadj[b] + j
-  __shared__ K s_spl[256];
+  __shared__ SsCells<K> s_cells;
   __shared__ uint32_t s_vals[PAY ? TILE : 1];
   __shared__ uint32_t s_scan[NW + 1];
   __shared__ uint32_t s_tile;
@@ -445,7 +558,6 @@ __global__ __launch_bounds__(SS_THREADS, PERSIST ? 4 : 1) void k_ss_scatter(SsSc
     if (tile >= ntiles) break;
     const uint32_t sidx = ss_seg_of_tile(a.segs, nsegs, tile);
     const SsSeg sg = a.segs[sidx];
-    for (int k = t + 1; k < 256; k += SS_THREADS) s_spl[k] = ((const K*)a.spl)[(size_t)sidx * 256 + k];
     const uint64_t off = (uint64_t)(tile - sg.first_tile) * TILE;
     const uint64_t rem = (uint64_t)sg.size - off;
     const uint32_t valid = rem < (uint64_t)TILE ? (uint32_t)rem : (uint32_t)TILE;
@@ -462,23 +574,31 @@ __global__ __launch_bounds__(SS_THREADS, PERSIST ? 4 : 1) void k_ss_scatter(SsSc
       k[i] = src[idx < valid ? idx : valid - 1];
       if constexpr (PAY) v[i] = vsrc[idx < valid ? idx : valid - 1];
     }
-    __syncthreads();  // splitters in LDS
+    // the segment's record after the key loads: its scalar word and its
+    // loads overlap theirs
+    const uint32_t shift = ss_cells_load<K, SS_THREADS>(s_cells, a.spl, sidx);
+    __syncthreads();  // splitters and cell table in LDS
+    const K base = s_cells.spl[0];
+    auto classify_all = [&](auto tree) {
 #pragma unroll
-    for (int i = 0; i < IPT; ++i) {
-      const uint32_t idx = wbase + (uint32_t)i * WAVE + lane;
-      K x = k[i];
-      if constexpr (key_mapped<KK>) x = a.map_in ? map_key<KK>(x) : x;
-      if (idx < valid) {
-        k[i] = x;
-        d[i] = ss_classify<K>(x, s_spl);
-      } else {
-        k[i] = ~K(0);
-        d[i] = SS_NB - 1;
+      for (int i = 0; i < IPT; ++i) {
+        const uint32_t idx = wbase + (uint32_t)i * WAVE + lane;
+        K x = k[i];
+        if constexpr (key_mapped<KK>) x = a.map_in ? map_key<KK>(x) : x;
+        if (idx < valid) {
+          k[i] = x;
+          d[i] = ss_classify<decltype(tree)::value, K>(x, s_cells, base, shift & ~SS_TREE);
+        } else {
+          k[i] = ~K(0);
+          d[i] = SS_NB - 1;
+        }
+        // a few searches at a time: interleaving all IPT of them would hold
+        // their state in registers beside the tile's keys
+        if (i % 2 == 1) __builtin_amdgcn_sched_barrier(0);
       }
-      // a few tree searches at a time: interleaving all IPT of them would
-      // hold their state in registers beside the tile's keys
-      if (i % 2 == 1) __builtin_amdgcn_sched_barrier(0);
-    }
+    };
+    if (shift & SS_TREE) classify_all(std::true_type{});
+    else classify_all(std::false_type{});
 
     uint32_t r[IPT];
     __builtin_amdgcn_sched_barrier(0);
@@ -626,12 +746,12 @@ hipError_t launch_ss_sample(int kk, const void* src, int map_in, const SsSeg* se
   if (nblocks <= 0) return hipSuccess;
   if ((uint32_t)nblocks > MAX_GRID_BLOCKS) nblocks = (int)MAX_GRID_BLOCKS;  // the kernel strides over segments
   switch (kk) {
-    case KK_U32: k_ss_sample<KK_U32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, lv, (uint32_t*)spl, counts, seed); break;
-    case KK_U64: k_ss_sample<KK_U64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, lv, (uint64_t*)spl, counts, seed); break;
-    case KK_F32: k_ss_sample<KK_F32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, lv, (uint32_t*)spl, counts, seed); break;
-    case KK_I32: k_ss_sample<KK_I32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, lv, (uint32_t*)spl, counts, seed); break;
-    case KK_F64: k_ss_sample<KK_F64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, lv, (uint64_t*)spl, counts, seed); break;
-    case KK_I64: k_ss_sample<KK_I64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, lv, (uint64_t*)spl, counts, seed); break;
+    case KK_U32: k_ss_sample<KK_U32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, lv, spl, counts, seed); break;
+    case KK_U64: k_ss_sample<KK_U64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, lv, spl, counts, seed); break;
+    case KK_F32: k_ss_sample<KK_F32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, lv, spl, counts, seed); break;
+    case KK_I32: k_ss_sample<KK_I32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, lv, spl, counts, seed); break;
+    case KK_F64: k_ss_sample<KK_F64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, lv, spl, counts, seed); break;
+    case KK_I64: k_ss_sample<KK_I64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, lv, spl, counts, seed); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -652,12 +772,12 @@ hipError_t launch_ss_count(int kk, const void* src, int map_in, const SsSeg* seg
   if (nblocks <= 0) return hipSuccess;
   const uint32_t tk = (uint32_t)ss_tile(key_bytes_of(kk));
   switch (kk) {
-    case KK_U32: k_ss_count<KK_U32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, lv, tk, (const uint32_t*)spl, counts); break;
-    case KK_U64: k_ss_count<KK_U64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, lv, tk, (const uint64_t*)spl, counts); break;
-    case KK_F32: k_ss_count<KK_F32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, lv, tk, (const uint32_t*)spl, counts); break;
-    case KK_I32: k_ss_count<KK_I32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, lv, tk, (const uint32_t*)spl, counts); break;
-    case KK_F64: k_ss_count<KK_F64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, lv, tk, (const uint64_t*)spl, counts); break;
-    case KK_I64: k_ss_count<KK_I64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, lv, tk, (const uint64_t*)spl, counts); break;
+    case KK_U32: k_ss_count<KK_U32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, lv, tk, spl, counts); break;
+    case KK_U64: k_ss_count<KK_U64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, lv, tk, spl, counts); break;
+    case KK_F32: k_ss_count<KK_F32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, lv, tk, spl, counts); break;
+    case KK_I32: k_ss_count<KK_I32><<<nblocks, SS_THREADS, 0, s>>>((const uint32_t*)src, map_in, segs, lv, tk, spl, counts); break;
+    case KK_F64: k_ss_count<KK_F64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, lv, tk, spl, counts); break;
+    case KK_I64: k_ss_count<KK_I64><<<nblocks, SS_THREADS, 0, s>>>((const uint64_t*)src, map_in, segs, lv, tk, spl, counts); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -15,6 +15,16 @@ constexpr int SS_SAMPLES = 8192;      // most sample keys per segment
 constexpr int SS_CAP = 8192;          // largest bucket finished in LDS
 constexpr int SS_TARGET = 4096;       // bucket size a level aims at (splitters per segment: size / SS_TARGET, <= 255)
 constexpr int SS_THREADS = 512;
+// Per-segment splitter record: the 255 splitters in ascending order and in
+// search-tree order (256 slots each), the cell table of the bucket
+// classification (cells + 1 counts as bytes, padded to words) and the word
+// holding the cell shift and the layout flag.  64-bit keys take half the
+// cells, which keeps three 64-bit scatter tiles per CU in LDS.
+__host__ __device__ constexpr uint32_t ss_cells_log2(int key_bytes) { return key_bytes == 4 ? 10u : 9u; }
+__host__ __device__ constexpr uint32_t ss_cell_words(int key_bytes) { return ((1u << ss_cells_log2(key_bytes)) + 4u) / 4u; }
+__host__ __device__ constexpr size_t ss_spl_rec_bytes(int key_bytes) {
+  return ((size_t)key_bytes * 512 + 4 * ss_cell_words(key_bytes) + 4 + 15) / 16 * 16;
+}
 constexpr int SS_MAX_LEVELS = 48;
 // u32 scatter tiles of 24 keys per thread measured 6 % faster than 16 on
 // 2^28 keys; u64 keeps 8 (12 and 16 were slower).

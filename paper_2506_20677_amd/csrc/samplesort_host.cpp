@@ -26,7 +26,7 @@ SsLayout ss_layout(uint64_t n, int key_bytes) {
   };
   L.segA = take(sizeof(SsSeg) * L.seg_cap);
   L.segB = take(sizeof(SsSeg) * L.seg_cap);
-  L.spl = take((size_t)key_bytes * 256 * L.seg_cap);
+  L.spl = take(ss_spl_rec_bytes(key_bytes) * L.seg_cap);
   L.counts = take(4 * (size_t)SS_NB * L.seg_cap);
   L.offs = take(4 * (size_t)SS_NB * L.seg_cap);
   L.items = take(sizeof(SsItem) * L.item_cap);
