@@ -11,10 +11,14 @@ distinct values drawn with Zipf ranks, 4..64 equally likely values spread
 over the whole range, sorted and reversed uniform keys; u64 keys uniform
 over 2^64 / 2^48 / 2^32 / 2^16 values, Zipf over 4,096 values and 4..256
 equally likely values spread over [0, 2^40), [0, 2^60) or the whole range
-(both ends present, so the span is exact); f32 and f64 Normal(0, 1e3); n from 2^10
-to 2^28.  Keys are drawn on the
-device from a seeded torch generator (the labels are measurements, not
-parity data).
+(both ends present, so the span is exact); u32 keys uniform inside 2 to 64
+clusters of 2^16 to 2^23 consecutive values spread over the whole range
+(mostly distinct keys whose binned entropy is as low as that of a few
+repeated values); u32 Zipf(1.1) and Zipf(1.5) ranks over [0, 2^20) or
+[0, 2^26) (the key is the rank: a narrow span with low entropy); f32 and f64 Normal(0, 1e3); n from 2^10 to 2^28.  Keys are
+drawn on the device from a seeded torch generator (the labels are
+measurements, not parity data).  --dists times only the named families and
+--merge replaces their rows in an existing label file, keeping the others.
 """
 import argparse
 import csv
@@ -40,6 +44,13 @@ def workloads(max_log2n):
             out.append(("u32", lg, f"zipf{s}", m))
         for m in (4, 16, 64):
             out.append(("u32", lg, "fewvals32", m))
+        # (clusters, log2 width): 2 x 2^23 and 16 x 2^20 fill 256 of the 65,536
+        # bins (H = 8), 64 x 2^16 about 64 bins
+        for c, w in ((2, 23), (16, 20), (64, 16)):
+            out.append(("u32", lg, f"clustered{w}", c))
+        for s in (1.1, 1.5):
+            for k in (1 << 20, 1 << 26):
+                out.append(("u32", lg, f"zipfrank{s}", k))
         out.append(("u32", lg, "sorted", 1 << 32))
         out.append(("u32", lg, "reverse", 1 << 32))
         # 64-bit and float keys at the same sizes (2^28 u64 keys = 2 GiB)
@@ -73,6 +84,23 @@ def make_keys(dtype, lg, dist, param, g, dev):
             vals = torch.randint(0, 1 << bits, (param,), generator=g, device=dev, dtype=torch.int64)
             vals[0], vals[1] = 0, (1 << bits) - 1
         x = vals[torch.randint(0, param, (n,), generator=g, device=dev, dtype=torch.int64)]
+    elif dist.startswith("clustered"):
+        # param clusters of 2^w consecutive values, the first at 0 and the
+        # last ending at 2^32 - 1, each key uniform inside a uniform cluster
+        w = int(dist[9:])
+        base = torch.randint(0, (1 << 32) - (1 << w) + 1, (param,), generator=g, device=dev, dtype=torch.int64)
+        base[0], base[1] = 0, (1 << 32) - (1 << w)
+        x = base[torch.randint(0, param, (n,), generator=g, device=dev, dtype=torch.int64)]
+        x += torch.randint(0, 1 << w, (n,), generator=g, device=dev, dtype=torch.int64)
+        x[0], x[-1] = 0, (1 << 32) - 1
+    elif dist.startswith("zipfrank"):
+        # the rank itself (0 = most frequent), so the span is at most param - 1
+        s = float(dist[8:])
+        w = torch.arange(1, param + 1, device=dev, dtype=torch.float64) ** (-s)
+        cdf = torch.cumsum(w, 0)
+        cdf /= cdf[-1].clone()
+        u = torch.rand(n, generator=g, device=dev, dtype=torch.float64)
+        x = torch.searchsorted(cdf, u).clamp_(max=param - 1)
     elif dist.startswith("zipf"):
         s = float(dist[4:])
         vals = torch.randint(0, 1 << 32 if dtype == "u32" else (1 << 62), (param,), generator=g, device=dev,
@@ -110,6 +138,8 @@ def main():
     ap.add_argument("--out", default=os.path.join(HERE, "mi355x_labels.csv"))
     ap.add_argument("--max-log2n", type=int, default=28)
     ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--dists", default="", help="comma-separated families to time (default: all)")
+    ap.add_argument("--merge", action="store_true", help="replace only these families' rows in --out")
     args = ap.parse_args()
     dev = torch.device("cuda:0")
     g = torch.Generator(device=dev)
@@ -119,6 +149,11 @@ def main():
     cfg = ahs.ahs_config_init(ahs.PRESET_GPU)
     rows = []
     wl = workloads(args.max_log2n)
+    only = [d for d in args.dists.split(",") if d]
+    if only:
+        wl = [w for w in wl if w[2] in only]
+    if not wl:
+        raise SystemExit("no workload matches --dists")
     for i, (dtype, lg, dist, param) in enumerate(wl):
         keys = make_keys(dtype, lg, dist, param, g, dev)
         out = torch.empty_like(keys)
@@ -138,6 +173,11 @@ def main():
               f"({', '.join(f'{k} {v * 1e3:.3f}' for k, v in t.items())} ms), fsm {ahs.STRATEGY_NAMES[fsm]}",
               flush=True)
         del keys, out
+    if args.merge and os.path.exists(args.out):
+        fams = {r["dist"] for r in rows}
+        with open(args.out, newline="") as fh:
+            kept = [r for r in csv.DictReader(fh) if r["dist"] not in fams]
+        rows = kept + rows
     with open(args.out, "w", newline="") as fh:
         w = csv.DictWriter(fh, fieldnames=list(rows[0]))
         w.writeheader()

@@ -11,7 +11,11 @@ scikit-learn's GradientBoostingClassifier (multinomial deviance); the export
 keeps its arithmetic: class score = initial raw score + learning rate x the
 leaf values of the class's trees, and the largest score wins.  scikit-learn
 sends x <= t to the left child, the library x < t, so thresholds are moved
-to the next double above.  The written model is then re-evaluated with the
+to the next double above.  The trees are fitted over log2 n, log2 k and H,
+so that a split between two measured sizes or spans falls at their
+geometric mean (an input halfway between 2^24 and 2^26 keys in log scale
+follows the nearer one); the export turns a log threshold t back into 2^t,
+which leaves every training row on the same side.  The written model is then re-evaluated with the
 library's own evaluator (ahs_model_predict, a host function), which must
 reproduce scikit-learn's class on every training row.
 """
@@ -40,6 +44,14 @@ def load(path):
     return rows, np.array(X), np.array(y), np.array(w), np.array(times)
 
 
+def fit_space(X):
+    """Columns the trees are fitted over: log2 n, log2 k, H."""
+    Z = np.array(X, dtype=np.float64)
+    Z[:, 0] = np.log2(Z[:, 0])
+    Z[:, 1] = np.log2(Z[:, 1])
+    return Z
+
+
 def export(clf, path):
     lr = clf.learning_rate
     base = clf._raw_predict_init(np.zeros((1, 3)))[0]
@@ -53,7 +65,10 @@ def export(clf, path):
                 if t.children_left[i] == -1:
                     nodes.append(f"{i} leaf {float(t.value[i][0][0]) * lr!r}")
                 else:
-                    thr = float(np.nextafter(t.threshold[i], np.inf))
+                    thr = float(t.threshold[i])
+                    if int(t.feature[i]) in (0, 1):  # log2 n, log2 k
+                        thr = float(2.0 ** thr)
+                    thr = float(np.nextafter(thr, np.inf))
                     nodes.append(f"{i} split {int(t.feature[i])} {thr!r} {int(t.children_left[i])} "
                                  f"{int(t.children_right[i])}")
             trees.append((cls, nodes))
@@ -77,6 +92,7 @@ def cross_validate(X, y, w, times):
     from sklearn.ensemble import GradientBoostingClassifier
     from sklearn.model_selection import KFold
 
+    X = fit_space(X)
     folds = list(KFold(n_splits=5, shuffle=True, random_state=0).split(X))
     print("stages depth | held-out accuracy | mean time over best | worst")
     for depth in (1, 2, 3):
@@ -112,8 +128,8 @@ def main():
         return
     clf = GradientBoostingClassifier(n_estimators=args.trees, max_depth=args.depth, learning_rate=0.3,
                                      random_state=0)
-    clf.fit(X, y, sample_weight=w)
-    pred = clf.predict(X)
+    clf.fit(fit_space(X), y, sample_weight=w)
+    pred = clf.predict(fit_space(X))
     export(clf, args.out)
 
     # the written file, evaluated by the library, must agree with scikit-learn
