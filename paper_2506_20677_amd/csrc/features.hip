@@ -237,9 +237,29 @@ __global__ __launch_bounds__(HIST_LARGE_THREADS) void k_hist_large(const typenam
   static_assert(sizeof(h) + sizeof(dh) <= 160 * 1024, "LDS");
   if (plan) {
     const uint32_t p = plan->reserved;
-    if ((p & PLAN_SKIP) || !(p & PLAN_LARGE)) return;
+    if (p & PLAN_SKIP) return;
     kmin = (K)plan->min_key;
     shift = plan->shift;
+    if (!(p & PLAN_LARGE)) {
+      // the exact histogram of at most HIST_SMALL_MAX_BINS bins, unless the
+      // min/max pass already counted it: plain counters in the first words
+      // of the LDS array, one row of nbins per workgroup
+      if (p & PLAN_FUSED) return;
+      const uint32_t nbins = plan->nbins;
+      for (uint32_t b = threadIdx.x; b < nbins; b += HIST_LARGE_THREADS) h[b] = 0;
+      __syncthreads();
+      const uint64_t tid = (uint64_t)blockIdx.x * HIST_LARGE_THREADS + threadIdx.x;
+      for_each_group<K, 4>(keys, n, tid, (uint64_t)gridDim.x * HIST_LARGE_THREADS, [&](const K (&kb)[V], int m) {
+        uint32_t bins[V];
+#pragma unroll
+        for (int i = 0; i < V; ++i) bins[i] = (uint32_t)((map_key<KK>(kb[i]) - kmin) >> shift);
+        lds_count_group<V>(h, bins, m);
+      });
+      __syncthreads();
+      uint32_t* out = partials + (size_t)blockIdx.x * nbins;
+      for (uint32_t b = threadIdx.x; b < nbins; b += HIST_LARGE_THREADS) out[b] = h[b];
+      return;
+    }
     ndig = DIG ? plan_fused_digits(p, shift) : 0;
   }
   ndig = ndig < DMAX ? ndig : DMAX;  // the counters hold one key's digits
@@ -437,13 +457,16 @@ hipError_t launch_hist_reduce(const uint32_t* partials, int ngroups, uint32_t nb
   return hipGetLastError();
 }
 
-// Sums the per-block entropy partials in a fixed order and sets the ratio.
-__global__ __launch_bounds__(256) void k_entropy_final(const double* __restrict__ hpart, int nparts,
-                                                       DevFeatures* __restrict__ df) {
-  __shared__ double s[256];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += 256) acc += hpart[i];
-  s[threadIdx.x] = acc;
+// Sums the per-block entropy partials in a fixed order (256 strided sums,
+// then those in order) and sets the ratio.  Threads 0..255 of the workgroup
+// do the work; every thread of it must call this (it holds a barrier).
+__device__ __forceinline__ void entropy_final_block(const double* __restrict__ hpart, int nparts,
+                                                    DevFeatures* df, double* s) {
+  if (threadIdx.x < 256) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 256) acc += hpart[i];
+    s[threadIdx.x] = acc;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     double H = 0.0;
@@ -452,6 +475,12 @@ __global__ __launch_bounds__(256) void k_entropy_final(const double* __restrict_
     df->entropy_bits = H;
     df->entropy_ratio = df->nbins > 1 ? H / log2((double)df->nbins) : 0.0;
   }
+}
+
+__global__ __launch_bounds__(256) void k_entropy_final(const double* __restrict__ hpart, int nparts,
+                                                       DevFeatures* __restrict__ df) {
+  __shared__ double s[256];
+  entropy_final_block(hpart, nparts, df, s);
 }
 
 hipError_t launch_entropy_final(const double* hpart, int nparts, DevFeatures* df, hipStream_t s) {
@@ -574,6 +603,8 @@ __device__ __forceinline__ void derived_digit_pieces(const uint32_t* __restrict_
 // or above the histogram's shift is summed from the reduced histogram
 // instead (its value is a function of the bin; a wave whose 64 bins share
 // the digit adds once).  The pass's 256 counts are then exclusively scanned.
+// With hpart set, workgroup 0 first finishes the entropy into df (the
+// feature vector the plan lives in), saving the launch of k_entropy_final.
 constexpr int DIGIT_REDUCE_THREADS = 1024;
 static_assert(DIGIT_REDUCE_THREADS * 64 == 65536, "derived digits: 64 bins per thread");
 __global__ __launch_bounds__(DIGIT_REDUCE_THREADS) void k_digit_reduce(const uint32_t* __restrict__ parts,
@@ -581,9 +612,15 @@ __global__ __launch_bounds__(DIGIT_REDUCE_THREADS) void k_digit_reduce(const uin
                                                                        int nblocks, int ndig,
                                                                        uint32_t* __restrict__ counts,
                                                                        uint32_t* __restrict__ offsets,
-                                                                       const DevFeatures* __restrict__ plan) {
+                                                                       const DevFeatures* plan,
+                                                                       const double* __restrict__ hpart, int nparts,
+                                                                       DevFeatures* df) {
   constexpr int G = DIGIT_REDUCE_THREADS / 256;
   const int p = blockIdx.x, t = threadIdx.x, d = t % 256, g = t / 256;
+  if (hpart && p == 0) {  // uniform over the workgroup
+    __shared__ double s_ent[256];
+    entropy_final_block(hpart, nparts, df, s_ent);
+  }
   int nf = ndig;  // digits the block partials hold
   if (plan) {
     if (plan->reserved & PLAN_SKIP) return;
@@ -627,10 +664,14 @@ __global__ __launch_bounds__(DIGIT_REDUCE_THREADS) void k_digit_reduce(const uin
 }
 
 hipError_t launch_digit_reduce(const uint32_t* digit_partials, const uint32_t* hist, int nblocks, int ndig,
-                               uint32_t* counts, uint32_t* offsets, hipStream_t s, const DevFeatures* plan) {
+                               uint32_t* counts, uint32_t* offsets, hipStream_t s, const DevFeatures* plan,
+                               const double* hpart, int nparts, DevFeatures* df) {
   if (plan && !hist) return hipErrorInvalidValue;  // derived digits read the reduced histogram
-  k_digit_reduce<<<plan ? 8 : ndig, DIGIT_REDUCE_THREADS, 0, s>>>(digit_partials, hist, nblocks, ndig, counts,
-                                                                   offsets, plan);
+  if (hpart && !df) return hipErrorInvalidValue;
+  const int nb = plan ? 8 : ndig;
+  if (nb < 1) return hipErrorInvalidValue;
+  k_digit_reduce<<<nb, DIGIT_REDUCE_THREADS, 0, s>>>(digit_partials, hist, nblocks, ndig, counts, offsets, plan,
+                                                     hpart, nparts, df);
   return hipGetLastError();
 }
 

@@ -111,6 +111,9 @@ inline Layout plan_layout(uint64_t n, int key_bytes, int with_payload, bool need
   const uint64_t tile = (uint64_t)os_tile(key_bytes, with_payload != 0);
   const uint64_t tiles = ceil_div(n ? n : 1, tile);
   L.df = take(sizeof(DevFeatures));
+  // the digit counts start 256 bytes after the feature vector (take aligns
+  // to 256), so the AUTO step reads both back with one copy
+  L.dcounts = take(4 * 8 * 256);
   L.mm = take(sizeof(MinMaxPartial) * (size_t)minmax_blocks(n));
   L.hpart = take(sizeof(double) * 2048);  // one partial per reduce block (<= 65,536 / 32)
   const size_t small_parts = (size_t)hist_small_blocks(n) * HIST_SMALL_MAX_BINS;
@@ -121,7 +124,6 @@ inline Layout plan_layout(uint64_t n, int key_bytes, int with_payload, bool need
   L.offs = take(4 * 65537);
   const size_t dblocks = (size_t)std::max(digit_hist_blocks(n), hist_large_blocks(n));
   L.dparts = take(4 * dblocks * 8 * 256);
-  L.dcounts = take(4 * 8 * 256);
   L.doffs = take(4 * 8 * 256);
   L.status = take(8 * tiles * 256);
   L.counters = take(4 * 64);

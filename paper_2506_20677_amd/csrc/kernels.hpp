@@ -125,7 +125,8 @@ hipError_t launch_hist_large(int kk, const void* keys, uint64_t n, uint64_t kmin
                              uint32_t* partials, uint32_t* corr, int nblocks, int ndig,
                              uint32_t* digit_partials, hipStream_t s, const DevFeatures* plan = nullptr);
 // With a plan: ngroups is the small histogram's block count and
-// ngroups_large the large one's; the grid covers 65,536 bins.
+// ngroups_large the large one's (the same when the planned large kernel
+// counted the small histogram too); the grid covers 65,536 bins.
 hipError_t launch_hist_reduce(const uint32_t* partials, int ngroups, uint32_t nbins, int large,
                               const uint32_t* corr, uint32_t* hist_out, uint64_t n, double* hpart,
                               int* nparts_out, hipStream_t s, const DevFeatures* plan = nullptr,
@@ -141,10 +142,13 @@ hipError_t launch_expand(int kk, const uint32_t* offsets, uint32_t nbins, uint64
 hipError_t launch_digit_hist(int kk, const void* keys, uint64_t n, uint64_t kmin, int ndig,
                              uint32_t* digit_partials, int nblocks, hipStream_t s);
 // Sums per-block digit counts into counts[ndig][256] and their exclusive
-// scans into offsets[ndig][256].
+// scans into offsets[ndig][256].  With hpart (nparts entropy partials of the
+// histogram reduce) it also finishes the entropy into df, as
+// launch_entropy_final would.
 hipError_t launch_digit_reduce(const uint32_t* digit_partials, const uint32_t* hist, int nblocks, int ndig,
                                uint32_t* counts, uint32_t* offsets, hipStream_t s,
-                               const DevFeatures* plan = nullptr);
+                               const DevFeatures* plan = nullptr, const double* hpart = nullptr, int nparts = 0,
+                               DevFeatures* df = nullptr);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t count, uint64_t value, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t s);
 

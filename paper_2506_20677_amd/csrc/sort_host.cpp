@@ -113,35 +113,36 @@ static ahs_status step_features_auto(SortJob& j, const ahs_config& c, bool model
             "minmax launch");
   }
   uint32_t* corr = at<uint32_t>(j.ws, j.L.corr);
-  const int gs = hist_small_blocks(j.n), gl = hist_large_blocks(j.n);
+  // one histogram launch: the planned large kernel counts the small exact
+  // histogram too (one row per workgroup), or nothing
+  const int gl = hist_large_blocks(j.n);
   AHS_HIP(j, launch_fill_u32(corr, 65536, 0u, j.s), "fill");
   {
     ProfScope p(j.ctx, "feature_hist", j.s, (double)j.key_bytes * j.n);
-    AHS_HIP(j, launch_hist_small(j.kk, j.kin, j.n, 0, 0, 0, parts, gs, j.s, df), "histogram launch");
     AHS_HIP(j, launch_hist_large(j.kk, j.kin, j.n, 0, 0, parts, corr, gl, 0, at<uint32_t>(j.ws, j.L.dparts), j.s, df),
             "histogram launch");
   }
+  int nparts = 0;
   {
     ProfScope p(j.ctx, "hist_reduce", j.s);
-    int nparts = 0;
     AHS_HIP(j,
-            launch_hist_reduce(parts, gs, 0, 0, corr, at<uint32_t>(j.ws, j.L.hist), j.n, at<double>(j.ws, j.L.hpart),
+            launch_hist_reduce(parts, gl, 0, 0, corr, at<uint32_t>(j.ws, j.L.hist), j.n, at<double>(j.ws, j.L.hpart),
                                &nparts, j.s, df, gl, minmax_blocks(j.n)),
             "histogram reduce");
-    AHS_HIP(j, launch_entropy_final(at<double>(j.ws, j.L.hpart), nparts, df, j.s), "entropy");
   }
   {
+    // the digit reduce also finishes the entropy
     ProfScope p(j.ctx, "digit_reduce", j.s);
     AHS_HIP(j,
             launch_digit_reduce(at<uint32_t>(j.ws, j.L.dparts), at<uint32_t>(j.ws, j.L.hist), gl, 0,
-                                at<uint32_t>(j.ws, j.L.dcounts),
-                                at<uint32_t>(j.ws, j.L.doffs), j.s, df),
+                                at<uint32_t>(j.ws, j.L.dcounts), at<uint32_t>(j.ws, j.L.doffs), j.s, df,
+                                at<double>(j.ws, j.L.hpart), nparts, df),
             "digit reduce");
   }
+  // the digit counts follow the feature vector in the workspace: one copy
+  static_assert(sizeof(DevFeatures) <= 256, "feature vector slot");
   char* pin = static_cast<char*>(j.ctx->pinned);
-  AHS_HIP(j, hipMemcpyAsync(pin, df, sizeof(DevFeatures), hipMemcpyDeviceToHost, j.s), "copy features");
-  AHS_HIP(j, hipMemcpyAsync(pin + 256, at<uint32_t>(j.ws, j.L.dcounts), 4 * 8 * 256, hipMemcpyDeviceToHost, j.s),
-          "copy digit counts");
+  AHS_HIP(j, hipMemcpyAsync(pin, df, 256 + 4 * 8 * 256, hipMemcpyDeviceToHost, j.s), "copy features");
   AHS_HIP(j, hipStreamSynchronize(j.s), "synchronize");
   memcpy(&j.f, pin, sizeof(DevFeatures));
   const uint32_t plan = j.f.reserved;
