@@ -47,6 +47,8 @@ namespace ahs {
 // kernels load the layout the record names.
 constexpr uint32_t SS_CELL_MAX = 16;
 constexpr uint32_t SS_TREE = 0x80000000u;  // layout flag in the record's shift word
+constexpr uint32_t SS_EQOUT = 0x40000000u;  // the plan marked buckets that go straight to the output
+constexpr uint32_t SS_WORD_FLAGS = SS_TREE | SS_EQOUT;
 
 __host__ __device__ __forceinline__ uint32_t ss_tree_sorted_index(uint32_t k) {
   const uint32_t d = 31u - (uint32_t)__builtin_clz(k);
@@ -78,6 +80,14 @@ __device__ __forceinline__ uint32_t ss_cells_load(SsCells<K>& c, const void* spl
     for (int k = (int)threadIdx.x; k < (int)ss_cell_words((int)sizeof(K)); k += NT) c.cntw[k] = rw[k];
   }
   return word;
+}
+
+// The record's output mask: bit b marks bucket b (valid when the word holds
+// SS_EQOUT).
+template <typename K>
+__device__ __forceinline__ const uint32_t* ss_eq_mask(const void* spl, uint32_t sidx) {
+  const unsigned char* rec = static_cast<const unsigned char*>(spl) + (size_t)sidx * ss_spl_rec_bytes((int)sizeof(K));
+  return reinterpret_cast<const uint32_t*>(rec + ss_eq_mask_offset((int)sizeof(K)));
 }
 
 // Bucket id of x in the layout TREE names (the caller branches once per
@@ -307,7 +317,7 @@ __global__ __launch_bounds__(SS_THREADS) void k_ss_count(const typename KeyTrait
         for (int i = 0; i < IPT; ++i) {
           K y = x[i];
           if constexpr (key_mapped<KK>) y = map_in ? map_key<KK>(y) : y;
-          bk[i] = ss_classify<decltype(tree)::value, K>(y, s_cells, base, shift & ~SS_TREE);
+          bk[i] = ss_classify<decltype(tree)::value, K>(y, s_cells, base, shift & ~SS_WORD_FLAGS);
           if (i % CS == CS - 1) __builtin_amdgcn_sched_barrier(0);
         }
       };
@@ -366,7 +376,9 @@ __device__ __forceinline__ bool ss_mask_any(const uint64_t* __restrict__ m, uint
 
 __global__ __launch_bounds__(SS_NB) void k_ss_plan(const SsSeg* __restrict__ segs, SsLevelIn lv,
                                                    const uint32_t* __restrict__ counts, uint32_t* __restrict__ offs,
-                                                   uint32_t dst_buf, int copy_in_place, SsSeg* __restrict__ next,
+                                                   uint32_t dst_buf, int copy_in_place, int eq_out,
+                                                   unsigned char* __restrict__ spl, uint32_t rec_bytes,
+                                                   uint32_t word_off, SsSeg* __restrict__ next,
                                                    SsItem* __restrict__ items, SsCounters* __restrict__ ctr,
                                                    uint32_t item_cap, uint32_t seg_cap) {
   constexpr int NW = SS_NB / WAVE;
@@ -391,6 +403,18 @@ __global__ __launch_bounds__(SS_NB) void k_ss_plan(const SsSeg* __restrict__ seg
     if (b == 0) s_ex[SS_NB] = total;
     __syncthreads();
     const bool small = c <= W;
+    if (eq_out) {
+      // buckets that the scatter writes straight to the output: a bit mask
+      // and a flag in the segment's record
+      const uint64_t m = __ballot(ss_eq_to_out(b, c));
+      unsigned char* rec = spl + (size_t)sidx * rec_bytes;
+      uint32_t* mw = reinterpret_cast<uint32_t*>(rec + word_off + 4);
+      if (lane == 0) {
+        mw[2 * w] = (uint32_t)m;
+        mw[2 * w + 1] = (uint32_t)(m >> 32);
+        if (m) atomicOr(reinterpret_cast<uint32_t*>(rec + word_off), SS_EQOUT);
+      }
+    }
     bool start = false;
     if (small) {
       if (b == 0) {
@@ -428,7 +452,9 @@ __global__ __launch_bounds__(SS_NB) void k_ss_plan(const SsSeg* __restrict__ seg
     } else if (!small) {
       len = c;
       if (b & 1u) {
-        if (!eq_final) n_it = (c + SS_CAP - 1) / SS_CAP;
+        // the scatter wrote it to the output already (eq_out), or it sits
+        // in place in the output, or copy items move (and unmap) it there
+        if (!eq_final && !(eq_out && ss_eq_to_out(b, c))) n_it = (c + SS_CAP - 1) / SS_CAP;
         flags |= SS_ITEM_COPY;
       } else if (c <= (uint32_t)SS_CAP) {
         n_it = 1;
@@ -537,6 +563,7 @@ __global__ __launch_bounds__(SS_THREADS, PERSIST ? 4 : 1) void k_ss_scatter(SsSc
   K* s_keys = reinterpret_cast<K*>(s_raw);
   uint16_t* s_dig = reinterpret_cast<uint16_t*>(s_raw + KEY_BYTES);
   __shared__ uint32_t s_dadj[SS_NB];  // segment-relative position of tile key j with id b: s_dadj[b] + j
+  __shared__ uint32_t s_eqo[SS_NB / 32];  // bit b: bucket b goes straight to the output (ss_eq_to_out)
   __shared__ SsCells<K> s_cells;
   __shared__ uint32_t s_vals[PAY ? TILE : 1];
   __shared__ uint32_t s_scan[NW + 1];
@@ -577,7 +604,11 @@ __global__ __launch_bounds__(SS_THREADS, PERSIST ? 4 : 1) void k_ss_scatter(SsSc
     // the segment's record after the key loads: its scalar word and its
     // loads overlap theirs
     const uint32_t shift = ss_cells_load<K, SS_THREADS>(s_cells, a.spl, sidx);
-    __syncthreads();  // splitters and cell table in LDS
+    if (shift & SS_EQOUT) {  // uniform: the plan marked buckets for the output
+      const uint32_t* mw = ss_eq_mask<K>(a.spl, sidx);
+      if (t < SS_NB / 32) s_eqo[t] = mw[t];
+    }
+    __syncthreads();  // splitters, cell table and output mask in LDS
     const K base = s_cells.spl[0];
     auto classify_all = [&](auto tree) {
 #pragma unroll
@@ -587,7 +618,7 @@ __global__ __launch_bounds__(SS_THREADS, PERSIST ? 4 : 1) void k_ss_scatter(SsSc
         if constexpr (key_mapped<KK>) x = a.map_in ? map_key<KK>(x) : x;
         if (idx < valid) {
           k[i] = x;
-          d[i] = ss_classify<decltype(tree)::value, K>(x, s_cells, base, shift & ~SS_TREE);
+          d[i] = ss_classify<decltype(tree)::value, K>(x, s_cells, base, shift & ~SS_WORD_FLAGS);
         } else {
           k[i] = ~K(0);
           d[i] = SS_NB - 1;
@@ -643,7 +674,27 @@ __global__ __launch_bounds__(SS_THREADS, PERSIST ? 4 : 1) void k_ss_scatter(SsSc
       dst[o] = x;
       if constexpr (PAY) a.vdst[o] = s_vals[j];
     };
-    if (valid == (uint32_t)TILE) {
+    if (shift & SS_EQOUT) {
+      // some bucket of equal keys goes to the output (uniform over the
+      // workgroup): one key at a time, each with its destination buffer
+      K* __restrict__ kout = (K*)a.out;
+#pragma unroll 4
+      for (uint32_t j = t; j < valid; j += SS_THREADS) {
+        K x = s_keys[j];
+        const uint32_t dg = s_dig[j];
+        const uint32_t rel = s_dadj[dg] + j;
+        if (rel >= sg.size) continue;  // unreachable with consistent counts
+        const uint64_t o = sg.start + rel;
+        if ((s_eqo[dg >> 5] >> (dg & 31u)) & 1u) {
+          if constexpr (key_mapped<KK>) x = unmap_key<KK>(x);
+          kout[o] = x;
+          if constexpr (PAY) a.vout[o] = s_vals[j];
+        } else {
+          dst[o] = x;
+          if constexpr (PAY) a.vdst[o] = s_vals[j];
+        }
+      }
+    } else if (valid == (uint32_t)TILE) {
       // full tile: all LDS reads first, then the stores
       K x[IPT];
       uint32_t rel[IPT];
@@ -784,11 +835,14 @@ hipError_t launch_ss_count(int kk, const void* src, int map_in, const SsSeg* seg
 }
 
 hipError_t launch_ss_plan(const SsSeg* segs, const SsLevelIn& lv, const uint32_t* counts, uint32_t* offs,
-                          uint32_t dst_buf, int copy_in_place, SsSeg* next, SsItem* items, SsCounters* ctr,
-                          uint32_t item_cap, uint32_t seg_cap, int nblocks, hipStream_t s) {
+                          uint32_t dst_buf, int copy_in_place, int eq_out, void* spl, int key_bytes, SsSeg* next,
+                          SsItem* items, SsCounters* ctr, uint32_t item_cap, uint32_t seg_cap, int nblocks,
+                          hipStream_t s) {
+  if (key_bytes != 4 && key_bytes != 8) return hipErrorInvalidValue;
   if (nblocks <= 0) return hipSuccess;
   if ((uint32_t)nblocks > MAX_GRID_BLOCKS) nblocks = (int)MAX_GRID_BLOCKS;  // the kernel strides over segments
-  k_ss_plan<<<nblocks, SS_NB, 0, s>>>(segs, lv, counts, offs, dst_buf, copy_in_place, next, items, ctr, item_cap,
+  k_ss_plan<<<nblocks, SS_NB, 0, s>>>(segs, lv, counts, offs, dst_buf, copy_in_place, eq_out, static_cast<unsigned char*>(spl),
+                                      (uint32_t)ss_spl_rec_bytes(key_bytes), (uint32_t)ss_word_offset(key_bytes), next, items, ctr, item_cap,
                                       seg_cap);
   return hipGetLastError();
 }

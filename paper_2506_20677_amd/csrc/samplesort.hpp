@@ -17,13 +17,18 @@ constexpr int SS_TARGET = 4096;       // bucket size a level aims at (splitters 
 constexpr int SS_THREADS = 512;
 // Per-segment splitter record: the 255 splitters in ascending order and in
 // search-tree order (256 slots each), the cell table of the bucket
-// classification (cells + 1 counts as bytes, padded to words) and the word
-// holding the cell shift and the layout flag.  64-bit keys take half the
+// classification (cells + 1 counts as bytes, padded to words), the word
+// holding the cell shift and the flags, and the plan's 512-bit mask of the
+// buckets that go straight to the output.  64-bit keys take half the
 // cells, which keeps three 64-bit scatter tiles per CU in LDS.
 __host__ __device__ constexpr uint32_t ss_cells_log2(int key_bytes) { return key_bytes == 4 ? 10u : 9u; }
 __host__ __device__ constexpr uint32_t ss_cell_words(int key_bytes) { return ((1u << ss_cells_log2(key_bytes)) + 4u) / 4u; }
+__host__ __device__ constexpr size_t ss_word_offset(int key_bytes) {
+  return (size_t)key_bytes * 512 + 4 * ss_cell_words(key_bytes);
+}
+__host__ __device__ constexpr size_t ss_eq_mask_offset(int key_bytes) { return ss_word_offset(key_bytes) + 4; }
 __host__ __device__ constexpr size_t ss_spl_rec_bytes(int key_bytes) {
-  return ((size_t)key_bytes * 512 + 4 * ss_cell_words(key_bytes) + 4 + 15) / 16 * 16;
+  return (ss_eq_mask_offset(key_bytes) + 64 + 15) / 16 * 16;
 }
 constexpr int SS_MAX_LEVELS = 48;
 // u32 scatter tiles of 24 keys per thread measured 6 % faster than 16 on
@@ -97,6 +102,11 @@ struct SsScatterArgs {
   void* status;        // [tiles][SS_NB] words of status_word_bytes(max_seg), zero before the launch
   uint32_t* tile_counter;
   uint64_t max_seg;    // largest segment (selects the status word size)
+  // Final output: the buckets the plan marked in a segment's record (large
+  // buckets of equal keys) are written there directly, unmapped and already
+  // in place, instead of into dst.
+  void* out;
+  uint32_t* vout;
 };
 
 struct SsBlockArgs {
@@ -128,9 +138,18 @@ hipError_t launch_ss_sample(int kk, const void* src, int map_in, const SsSeg* se
 hipError_t launch_ss_zero_status(void* status, const SsLevelIn& lv, uint32_t words_per_tile, hipStream_t s);
 hipError_t launch_ss_count(int kk, const void* src, int map_in, const SsSeg* segs, const SsLevelIn& lv,
                            const void* spl, uint32_t* counts, int nblocks, hipStream_t s);
+// eq_out: large buckets of equal keys go straight to the output (marked in
+// the segment's record for the scatter; no item); the host sets it when
+// the output is not the level's source.
 hipError_t launch_ss_plan(const SsSeg* segs, const SsLevelIn& lv, const uint32_t* counts, uint32_t* offs,
-                          uint32_t dst_buf, int copy_in_place, SsSeg* next, SsItem* items, SsCounters* ctr,
-                          uint32_t item_cap, uint32_t seg_cap, int nblocks, hipStream_t s);
+                          uint32_t dst_buf, int copy_in_place, int eq_out, void* spl, int key_bytes, SsSeg* next,
+                          SsItem* items, SsCounters* ctr, uint32_t item_cap, uint32_t seg_cap, int nblocks,
+                          hipStream_t s);
+// The rule both the plan and the scatter apply: bucket b (odd ids hold keys
+// equal to a splitter) of c keys goes straight to the output.
+__host__ __device__ __forceinline__ bool ss_eq_to_out(uint32_t b, uint32_t c) {
+  return (b & 1u) && c > (uint32_t)(SS_CAP / 2);
+}
 hipError_t launch_ss_tiles(SsSeg* segs, SsCounters* ctr, uint32_t tile_keys, uint32_t seg_cap, hipStream_t s);
 // nblocks 0: one block per tile (host-driven); else a persistent grid.
 hipError_t launch_ss_scatter(int kk, int with_vals, const SsScatterArgs& a, uint32_t nblocks, hipStream_t s);

@@ -108,7 +108,12 @@ ahs_status launch_level(SortJob& j, const SsLayout& S, const SsTables& T, const 
     SS_HIP(launch_ss_count(j.kk, bufs[P.src_buf], map_in, T.segs[P.cur], P.lv, T.spl, T.counts, P.count_grid, j.s),
            "count");
   }
-  SS_HIP(launch_ss_plan(T.segs[P.cur], P.lv, T.counts, T.offs, P.dst_buf, mapped ? 1 : 0, T.segs[P.cur ^ 1], T.items,
+  // large buckets of equal keys go straight to the output unless it is
+  // the level's source (an in-place call's level 0, or a level reading the
+  // output)
+  const bool eq_out = bufs[P.src_buf] != j.kout && (!pay || vbufs[P.src_buf] != j.vout);
+  SS_HIP(launch_ss_plan(T.segs[P.cur], P.lv, T.counts, T.offs, P.dst_buf, mapped ? 1 : 0, eq_out ? 1 : 0, T.spl,
+                        j.key_bytes, T.segs[P.cur ^ 1], T.items,
                         T.ctr + P.level, (uint32_t)S.item_cap, (uint32_t)S.seg_cap, P.plan_grid, j.s),
          "plan");
   SsScatterArgs sa;
@@ -124,6 +129,8 @@ ahs_status launch_level(SortJob& j, const SsLayout& S, const SsTables& T, const 
   sa.status = T.status;
   sa.tile_counter = T.tilectr + P.level;
   sa.max_seg = max_seg;
+  sa.out = j.kout;
+  sa.vout = pay ? j.vout : nullptr;
   {
     ProfScope p(j.ctx, "ss_scatter", j.s, P.move_bytes);
     SS_HIP(launch_ss_scatter(j.kk, pay, sa, P.scatter_grid, j.s), "scatter");
