@@ -1,9 +1,15 @@
 #!/usr/bin/env python3
-"""Measures, on the GPU this runs on, which forced strategy (COUNTING, RADIX,
-QUICK) sorts each of a grid of synthetic workloads fastest, and writes one
-CSV row per workload: its features (n, span, nbins, entropy) and the three
-wall times of ahs_sort with that strategy forced (inputs resident on the
-device, the host round trips each path needs included).  These are the
+"""Measures, on the GPU this runs on, which decision (COUNTING, RADIX,
+QUICK) makes AUTO fastest on each of a grid of synthetic workloads, and
+writes one CSV row per workload: its features (n, span, nbins, entropy) and
+the three wall times of ahs_sort(AUTO) with the decision pinned to that
+strategy (inputs resident on the device, the host round trips included).
+AUTO computes the features first and the strategies reuse what they can
+(radix the fused digit counts, counting the exact histogram; the sample
+sort nothing), so a strategy's time here is its cost after the features,
+not its forced time: forced radix and counting recompute the min/max and
+their counts.  The decision is pinned by a constant model (no trees; the
+initial scores favour one class) attached to the context.  These are the
 labels the selector model of Sec. III-H is trained on (train_gbt.py).
 
 Workloads: u32 keys uniform over k values (k from 16 to 2^32), 64..65,536
@@ -25,6 +31,7 @@ import csv
 import os
 import statistics
 import sys
+import tempfile
 import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -121,16 +128,29 @@ def make_keys(dtype, lg, dist, param, g, dev):
     return x.view(torch.uint64)
 
 
-def time_sort(keys, out, strategy, ctx, reps):
+def time_sort(keys, out, strategy, ctx, cfg, reps):
     ts = []
     for r in range(reps + 1):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        ahs.ahs_sort(keys, strategy=strategy, out=out, ctx=ctx)
+        _, _, chosen, _ = ahs.ahs_sort(keys, strategy=strategy, cfg=cfg, out=out, ctx=ctx)
         torch.cuda.synchronize()
         if r:
             ts.append(time.perf_counter() - t)
-    return statistics.median(ts)
+    return statistics.median(ts), chosen
+
+
+def constant_models(tmpdir):
+    """One model file per strategy whose prediction is always that strategy."""
+    out = {}
+    for i, name in enumerate(("counting", "radix", "quick")):
+        path = os.path.join(tmpdir, f"always_{name}.gbt")
+        base = ["0.0"] * 3
+        base[i] = "1.0"
+        with open(path, "w") as fh:
+            fh.write(f"ahs-gbt 1\nnum_class 3\nbase_score {' '.join(base)}\nnum_trees 0\n")
+        out[name] = ahs.ahs_model_load(path)
+    return out
 
 
 def main():
@@ -147,6 +167,9 @@ def main():
     ctx = ahs.default_context(0)
     ctx.workspace(ahs.ahs_workspace_bytes(1 << args.max_log2n, ahs.U64, False, ahs.AUTO))
     cfg = ahs.ahs_config_init(ahs.PRESET_GPU)
+    cfg_m = ahs.ahs_config_init(ahs.PRESET_GPU, use_model=1)
+    tmpdir = tempfile.mkdtemp()
+    pinned = constant_models(tmpdir)
     rows = []
     wl = workloads(args.max_log2n)
     only = [d for d in args.dists.split(",") if d]
@@ -164,7 +187,11 @@ def main():
             if s == ahs.COUNTING and f.span >= 65536:
                 t[name] = float("inf")
                 continue
-            t[name] = time_sort(keys, out, s, ctx, args.reps)
+            ctx.set_model(pinned[name])
+            t[name], chosen = time_sort(keys, out, ahs.AUTO, ctx, cfg_m, args.reps)
+            if chosen != s:
+                raise SystemExit(f"AUTO ran {ahs.STRATEGY_NAMES[chosen]} with the decision pinned to {name}")
+        ctx.set_model(None)
         best = min(t, key=t.get)
         rows.append({"dtype": dtype, "n": f.n, "dist": dist, "param": param, "span": f.span, "nbins": f.nbins,
                      "entropy_bits": repr(f.entropy_bits), "t_counting": t["counting"], "t_radix": t["radix"],

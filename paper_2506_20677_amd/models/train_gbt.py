@@ -12,10 +12,15 @@ keeps its arithmetic: class score = initial raw score + learning rate x the
 leaf values of the class's trees, and the largest score wins.  scikit-learn
 sends x <= t to the left child, the library x < t, so thresholds are moved
 to the next double above.  The trees are fitted over log2 n, log2 k and H,
-so that a split between two measured sizes or spans falls at their
-geometric mean (an input halfway between 2^24 and 2^26 keys in log scale
-follows the nearer one); the export turns a log threshold t back into 2^t,
-which leaves every training row on the same side.  The written model is then re-evaluated with the
+so that a split between two measured sizes falls at their geometric mean
+(an input halfway between 2^24 and 2^26 keys in log scale follows the
+nearer one); the export turns a log threshold t back into 2^t, which leaves
+every training row on the same side.  log2 k is rounded up to a multiple of
+1/4 first: spans within a factor 2^(1/4) look alike, so the trees cannot
+split between the random spans of two draws of one family (say 4.24e9 and
+4.27e9), and k = 65,536 (counting feasible) stays apart from 65,537.  A
+threshold between two such steps is exported at the step below it, as
+k < next double above 2^step.  The written model is then re-evaluated with the
 library's own evaluator (ahs_model_predict, a host function), which must
 reproduce scikit-learn's class on every training row.
 """
@@ -44,11 +49,15 @@ def load(path):
     return rows, np.array(X), np.array(y), np.array(w), np.array(times)
 
 
+K_STEPS = 4  # log2 k in steps of 1 / K_STEPS
+
+
 def fit_space(X):
-    """Columns the trees are fitted over: log2 n, log2 k, H."""
+    """Columns the trees are fitted over: log2 n, log2 k rounded up to a
+    step, H."""
     Z = np.array(X, dtype=np.float64)
     Z[:, 0] = np.log2(Z[:, 0])
-    Z[:, 1] = np.log2(Z[:, 1])
+    Z[:, 1] = np.ceil(np.log2(Z[:, 1]) * K_STEPS) / K_STEPS
     return Z
 
 
@@ -66,7 +75,9 @@ def export(clf, path):
                     nodes.append(f"{i} leaf {float(t.value[i][0][0]) * lr!r}")
                 else:
                     thr = float(t.threshold[i])
-                    if int(t.feature[i]) in (0, 1):  # log2 n, log2 k
+                    if int(t.feature[i]) == 1:  # stepped log2 k: the step at or below t
+                        thr = float(2.0 ** (math.floor(thr * K_STEPS) / K_STEPS))
+                    elif int(t.feature[i]) == 0:  # log2 n
                         thr = float(2.0 ** thr)
                     thr = float(np.nextafter(thr, np.inf))
                     nodes.append(f"{i} split {int(t.feature[i])} {thr!r} {int(t.children_left[i])} "
