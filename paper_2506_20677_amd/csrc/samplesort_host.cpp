@@ -141,6 +141,30 @@ ahs_status launch_level(SortJob& j, const SsLayout& S, const SsTables& T, const 
   return AHS_OK;
 }
 
+// Levels a segment of max_seg keys is expected to take: splitters aim at
+// SS_TARGET-key buckets (at most 255 per level), so a level takes a segment
+// of up to 255 * SS_TARGET keys to single-level buckets and a larger one
+// down by 256.
+int expected_levels(uint64_t max_seg) {
+  int e = 0;
+  for (uint64_t s = max_seg; s > (uint64_t)SS_CAP; ++e)
+    s = s <= (uint64_t)SS_P * SS_TARGET ? (uint64_t)SS_TARGET : ceil_div(s, (uint64_t)SS_P + 1);
+  return e;
+}
+
+// Buffer a level scatters into.  The levels alternate between the scratch
+// buffer and the output so that the last expected level writes the output:
+// its buckets are then block-sorted in place there (sorting from the
+// scratch buffer into the output measured 12 % slower).  An in-place call
+// (output = input) starts in the scratch buffer, since level 0 reads the
+// input.
+uint32_t level_dst(const SortJob& j, int level, uint64_t max_seg) {
+  const bool alias = j.kin == j.kout || (j.vin && j.vin == j.vout);
+  const int last = expected_levels(max_seg) - 1;
+  const bool out = alias ? (level % 2 == 1) : ((last - level) % 2 == 0);
+  return out ? SS_BUF_OUT : SS_BUF_TMP;
+}
+
 ahs_status clear_counters(SortJob& j, const SsTables& T) {
   SS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(T.ctr), sizeof(SsCounters) / 4 * SS_MAX_LEVELS, 0u, j.s),
          "fill");
@@ -163,7 +187,7 @@ ahs_status ss_levels_host(SortJob& j, const SsLayout& S, const SsTables& T, uint
     LevelPlan P;
     P.level = level;
     P.src_buf = src_buf;
-    P.dst_buf = (level % 2 == 0) ? SS_BUF_TMP : SS_BUF_OUT;
+    P.dst_buf = level_dst(j, level, max_seg);
     P.cur = cur;
     P.lv = SsLevelIn{nullptr, nsegs, ntiles, (uint32_t)S.seg_cap, (uint32_t)S.tile_cap};
     P.sample_grid = (int)nsegs;
@@ -217,7 +241,7 @@ ahs_status ss_levels_device(SortJob& j, const SsLayout& S, const SsTables& T, co
     LevelPlan P;
     P.level = level;
     P.src_buf = src_buf;
-    P.dst_buf = (level % 2 == 0) ? SS_BUF_TMP : SS_BUF_OUT;
+    P.dst_buf = level_dst(j, level, max_seg);
     P.cur = cur;
     P.lv = SsLevelIn{level == 0 ? in0 : T.ctr + (level - 1), 0u, 0u, seg_cap, (uint32_t)S.tile_cap};
     P.sample_grid = seg_grid;
