@@ -423,6 +423,40 @@ def test_quick_in_place():
         run_pair(keys, np.arange(n, dtype=np.uint32), ahs.QUICK, in_place=True)
 
 
+@pytest.mark.parametrize("dtype", [np.uint32, np.int32, np.float32, np.uint64, np.int64, np.float64])
+def test_quick_large_equal_key_buckets(dtype):
+    """Forced QUICK where buckets of equal keys hold more than 4,096 keys and
+    are scattered straight to the output: at level 0 (five distinct values,
+    signed zeros and negative keys included, so signed and float keys are
+    unmapped on the way) and at level 1 (24 values of 6,000 copies each
+    among keys that need a second level); ragged size, with a payload, out
+    of place and in place (level 0 then reads the output and the scatter
+    keeps those buckets in the scratch buffer)."""
+    r = np.random.default_rng(41)
+    n = (1 << 22) + 777
+    dt = np.dtype(dtype)
+    if dt.kind == "f":
+        vals = np.array([-3.5, -0.0, 0.0, 1.25, 7e3], dtype=dt)
+        wide = (r.standard_normal(n) * 1e3).astype(dt)
+    elif dt.kind == "i":
+        info = np.iinfo(dt)
+        vals = np.array([info.min, -1, 0, 3, info.max], dtype=dt)
+        wide = r.integers(info.min, info.max, n, dtype=dt, endpoint=True)
+    else:
+        info = np.iinfo(dt)
+        vals = np.array([0, 7, 1 << 20, info.max - 1, info.max], dtype=dt)
+        wide = r.integers(0, info.max, n, dtype=dt, endpoint=True)
+    few = vals[r.integers(0, vals.size, n)]
+    mixed = wide.copy()
+    heavy = wide[r.integers(0, n, 24)]
+    mixed[r.permutation(n)[: 24 * 6000]] = np.repeat(heavy, 6000)
+    pay = np.arange(n, dtype=np.uint32)
+    for keys in (few, mixed):
+        run_pair(keys, None, ahs.QUICK)
+        run_pair(keys, pay, ahs.QUICK)
+        run_pair(keys.copy(), pay.copy(), ahs.QUICK, in_place=True)
+
+
 def test_auto_general_path():
     for case in ("uniform32", "sorted32", "reverse32", "swapped32"):
         keys = gen.strategy_sweep(case, n=1 << 20)
