@@ -168,8 +168,8 @@ def main():
     ctx.workspace(ahs.ahs_workspace_bytes(1 << args.max_log2n, ahs.U64, False, ahs.AUTO))
     cfg = ahs.ahs_config_init(ahs.PRESET_GPU)
     cfg_m = ahs.ahs_config_init(ahs.PRESET_GPU, use_model=1)
-    tmpdir = tempfile.mkdtemp()
-    pinned = constant_models(tmpdir)
+    with tempfile.TemporaryDirectory() as tmpdir:  # the files are parsed at load
+        pinned = constant_models(tmpdir)
     rows = []
     wl = workloads(args.max_log2n)
     only = [d for d in args.dists.split(",") if d]
