@@ -137,8 +137,14 @@ __device__ __forceinline__ uint64_t ss_mix(uint64_t z) {
 // ------------------------------------------------------------------ init
 // Level 0: one segment (or, for n <= SS_CAP, one block-sort item) covering
 // the whole input.
-__global__ void k_ss_init(SsSeg* segs, SsItem* items, uint64_t n) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+// Clears the per-level counter records and tile counters and, with segs
+// set, makes the whole input segment 0 and item 0 (one launch for all the
+// set-up a sort needs).
+__global__ void k_ss_init(SsSeg* segs, SsItem* items, uint64_t n, uint32_t* ctr_words, uint32_t nctr,
+                          uint32_t* tilectr, uint32_t ntile) {
+  for (uint32_t i = threadIdx.x; i < nctr; i += blockDim.x) ctr_words[i] = 0u;
+  for (uint32_t i = threadIdx.x; i < ntile; i += blockDim.x) tilectr[i] = 0u;
+  if (segs && threadIdx.x == 0 && blockIdx.x == 0) {
     segs[0].start = 0;
     segs[0].size = (uint32_t)n;
     segs[0].first_tile = 0;
@@ -787,8 +793,11 @@ __global__ __launch_bounds__(SS_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 }
 
 // ------------------------------------------------------------------ launchers
-hipError_t launch_ss_init(SsSeg* segs, SsItem* items, uint64_t n, hipStream_t s) {
-  k_ss_init<<<1, 64, 0, s>>>(segs, items, n);
+hipError_t launch_ss_init(SsSeg* segs, SsItem* items, uint64_t n, SsCounters* ctr, uint32_t* tilectr, int levels,
+                          hipStream_t s) {
+  if (levels < 0 || levels > SS_MAX_LEVELS || (segs && !items)) return hipErrorInvalidValue;
+  k_ss_init<<<1, 256, 0, s>>>(segs, items, n, reinterpret_cast<uint32_t*>(ctr),
+                              (uint32_t)(sizeof(SsCounters) / 4 * levels), tilectr, (uint32_t)levels);
   return hipGetLastError();
 }
 

@@ -129,7 +129,10 @@ struct SsLayout {
 };
 SsLayout ss_layout(uint64_t n, int key_bytes);
 
-hipError_t launch_ss_init(SsSeg* segs, SsItem* items, uint64_t n, hipStream_t s);
+// Zeroes `levels` counter records and tile counters; with segs set, also
+// makes [0, n) segment 0 and item 0.
+hipError_t launch_ss_init(SsSeg* segs, SsItem* items, uint64_t n, SsCounters* ctr, uint32_t* tilectr, int levels,
+                          hipStream_t s);
 // Every level kernel loops over its work (segments, tiles, items) with a
 // grid stride, so device-driven levels launch fixed grids.  The sample
 // kernel also clears the level's bucket counts.

@@ -166,20 +166,18 @@ uint32_t level_dst(const SortJob& j, int level, uint64_t max_seg) {
 }
 
 ahs_status clear_counters(SortJob& j, const SsTables& T) {
-  SS_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(T.ctr), sizeof(SsCounters) / 4 * SS_MAX_LEVELS, 0u, j.s),
-         "fill");
-  SS_HIP(launch_fill_u32(T.tilectr, SS_MAX_LEVELS, 0u, j.s), "fill");
+  SS_HIP(launch_ss_init(nullptr, nullptr, 0, T.ctr, T.tilectr, SS_MAX_LEVELS, j.s), "clear counters");
   return AHS_OK;
 }
 
 }  // namespace
 
 ahs_status ss_levels_host(SortJob& j, const SsLayout& S, const SsTables& T, uint32_t nsegs, uint32_t ntiles,
-                          uint64_t level_keys, uint64_t max_seg) {
+                          uint64_t level_keys, uint64_t max_seg, bool counters_cleared) {
   const int pay = j.vin != nullptr;
   const double rec_bytes = 2.0 * j.key_bytes + (pay ? 8.0 : 0.0);  // read + write per key
   SsBlockArgs ba = block_args(j, T);
-  AHS_TRY(clear_counters(j, T));
+  if (!counters_cleared) AHS_TRY(clear_counters(j, T));
   uint32_t src_buf = SS_BUF_IN;
   int cur = 0;
   for (int level = 0; level < SS_MAX_LEVELS; ++level) {
@@ -266,15 +264,18 @@ ahs_status run_samplesort(SortJob& j) {
   const SsLayout S = ss_layout(j.n, j.key_bytes);
   const SsTables T = ss_tables(j, S);
   const int pay = j.vin != nullptr;
-  SS_HIP(launch_ss_init(T.segs[0], T.items, j.n, j.s), "sample sort init");
-  if (j.n <= (uint64_t)SS_CAP) {
+  // one launch: segment 0, item 0 and, when levels follow, their counters
+  const bool levels = j.n > (uint64_t)SS_CAP;
+  SS_HIP(launch_ss_init(T.segs[0], T.items, j.n, T.ctr, T.tilectr, levels ? SS_MAX_LEVELS : 0, j.s),
+         "sample sort init");
+  if (!levels) {
     ProfScope p(j.ctx, "ss_block_sort", j.s, (2.0 * j.key_bytes + (pay ? 8.0 : 0.0)) * j.n);
     SsBlockArgs ba = block_args(j, T);
     ba.nitems = 1;
     SS_HIP(launch_ss_block(j.kk, pay, ba, 0, j.s), "block sort");
     return AHS_OK;
   }
-  return ss_levels_host(j, S, T, 1, (uint32_t)ceil_div(j.n, (uint64_t)ss_tile(j.key_bytes)), j.n, j.n);
+  return ss_levels_host(j, S, T, 1, (uint32_t)ceil_div(j.n, (uint64_t)ss_tile(j.key_bytes)), j.n, j.n, true);
 }
 
 }  // namespace ahs

@@ -24,7 +24,8 @@ SsTables ss_tables(SortJob& j, const SsLayout& S);
 // ntiles tiles, level_keys keys), level 0 reading the input buffer.  Reads
 // one counter record per level back to size the next level's grids.
 ahs_status ss_levels_host(SortJob& j, const SsLayout& S, const SsTables& T, uint32_t nsegs, uint32_t ntiles,
-                          uint64_t level_keys, uint64_t max_seg);
+                          uint64_t level_keys, uint64_t max_seg,
+                          bool counters_cleared = false);
 
 // Device-driven levels: `levels` levels whose sizes the kernels read from
 // the previous level's record (level 0 from *in0).  Never synchronises.
