@@ -248,6 +248,26 @@ def test_segmented_float_with_nan(case):
     assert (chosen[:10] != ahs.SEG_NAN).all()
 
 
+@pytest.mark.parametrize("mode,in_place", [("blocking", False), ("blocking", True), ("async", False),
+                                           ("async", True), ("graph", False)])
+@pytest.mark.parametrize("dt", [np.uint32, np.int32])
+def test_segmented_quick_large_equal_key_buckets(dt, mode, in_place):
+    """Segments the FSM sends to the sample sort (100 distinct values over a
+    span below the radix threshold) holding up to 2^20 keys, so their
+    buckets of equal keys exceed 4,096 keys and are scattered straight to
+    the output; signed keys, payload, every dispatch mode, and in place."""
+    r = np.random.default_rng(61)
+    sizes = [1 << 20, 300_001, 150_000, 9000, 4097, 100, 1, 65_537]
+    offs = offsets_of(sizes)
+    n = int(offs[-1])
+    lo = -250_000 if dt == np.int32 else 0
+    vals = r.integers(lo, lo + 500_000, 100).astype(dt)
+    keys = vals[r.integers(0, vals.size, n)]
+    chosen = run_segments(keys, offs, np.arange(n, dtype=np.uint32), mode=mode, in_place=in_place,
+                          hint=1 << 20)
+    assert chosen[0] == ahs.QUICK
+
+
 def test_segmented_in_place():
     keys, offs, _ = gen.segments(nseg=50, seed=27, sizes=mixed_sizes(50, 27, 1 << 15))
     run_segments(keys, offs, np.arange(keys.size, dtype=np.uint32), in_place=True)
