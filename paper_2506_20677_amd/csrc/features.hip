@@ -75,9 +75,14 @@ __global__ __launch_bounds__(MINMAX_THREADS) void k_minmax(const typename KeyTra
   }
 }
 
-// One workgroup folds the partials and derives span, shift and nbins.
+// One workgroup folds the partials and derives span, shift and nbins.  With
+// corr set, a plan for the packed histogram also zeroes its 65,536
+// correction words here (the histogram kernel adds to them), which saves a
+// fill launch.
 __global__ __launch_bounds__(256) void k_minmax_final(const MinMaxPartial* __restrict__ part, int nparts,
-                                                      uint64_t n, DevFeatures* __restrict__ df, FeaturePlanCfg pc) {
+                                                      uint64_t n, DevFeatures* __restrict__ df, FeaturePlanCfg pc,
+                                                      uint32_t* __restrict__ corr) {
+  __shared__ uint32_t s_plan;
   uint64_t mn = ~0ull, mx = 0, nan = 0;
   for (int i = threadIdx.x; i < nparts; i += 256) {
     mn = part[i].mn < mn ? part[i].mn : mn;
@@ -125,6 +130,15 @@ __global__ __launch_bounds__(256) void k_minmax_final(const MinMaxPartial* __res
       f.reserved = plan;
     }
     *df = f;
+    s_plan = f.reserved;
+  }
+  if (corr) {
+    __syncthreads();
+    if (s_plan & PLAN_LARGE) {
+      u32x4* c4 = reinterpret_cast<u32x4*>(corr);
+      const u32x4 z = {0u, 0u, 0u, 0u};
+      for (int i = threadIdx.x; i < 65536 / 4; i += 256) c4[i] = z;
+    }
   }
 }
 
@@ -139,7 +153,9 @@ static void minmax_kk(const void* keys, uint64_t n, MinMaxPartial* partials, int
 }
 
 hipError_t launch_minmax(int kk, const void* keys, uint64_t n, MinMaxPartial* partials, int nblocks,
-                         DevFeatures* df, hipStream_t s, const FeaturePlanCfg* plan_cfg, uint32_t* mod_partials) {
+                         DevFeatures* df, hipStream_t s, const FeaturePlanCfg* plan_cfg, uint32_t* mod_partials,
+                         uint32_t* corr) {
+  if (corr && !plan_cfg) return hipErrorInvalidValue;  // only a plan says whether the packed histogram follows
   switch (kk) {
     case KK_U32: minmax_kk<KK_U32>(keys, n, partials, nblocks, mod_partials, s); break;
     case KK_U64: minmax_kk<KK_U64>(keys, n, partials, nblocks, mod_partials, s); break;
@@ -154,7 +170,7 @@ hipError_t launch_minmax(int kk, const void* keys, uint64_t n, MinMaxPartial* pa
   FeaturePlanCfg pc = {};
   if (plan_cfg) pc = *plan_cfg;
   pc.fused = (plan_cfg && mod_partials) ? 1u : 0u;
-  k_minmax_final<<<1, 256, 0, s>>>(partials, nblocks, n, df, pc);
+  k_minmax_final<<<1, 256, 0, s>>>(partials, nblocks, n, df, pc, corr);
   return hipGetLastError();
 }
 

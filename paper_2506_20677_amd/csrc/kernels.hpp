@@ -115,9 +115,11 @@ constexpr int HRED_MAX_BLOCKS = 1024;  // reduce blocks covering 65,536 bins
 // by mapped value modulo HIST_SMALL_MAX_BINS into mod_partials[block][.]:
 // when the span turns out below HIST_SMALL_MAX_BINS that is the exact
 // histogram of key - min rotated by min, and the plan marks it PLAN_FUSED.
+// With a plan and corr set, a plan for the packed 65,536-bin histogram also
+// zeroes its 65,536 correction words.
 hipError_t launch_minmax(int kk, const void* keys, uint64_t n, MinMaxPartial* partials, int nblocks,
                          DevFeatures* df, hipStream_t s, const FeaturePlanCfg* plan_cfg = nullptr,
-                         uint32_t* mod_partials = nullptr);
+                         uint32_t* mod_partials = nullptr, uint32_t* corr = nullptr);
 hipError_t launch_hist_small(int kk, const void* keys, uint64_t n, uint64_t kmin, uint32_t shift,
                              uint32_t nbins, uint32_t* partials, int nblocks, hipStream_t s,
                              const DevFeatures* plan = nullptr);

@@ -92,6 +92,7 @@ static ahs_status step_hist(SortJob& j, uint32_t* hist_out, int ndig_fused) {
 static ahs_status step_features_auto(SortJob& j, const ahs_config& c, bool model, bool want_hist,
                                      DigitCounts* dcounts, uint32_t* plan_out) {
   DevFeatures* df = at<DevFeatures>(j.ws, j.L.df);
+  uint32_t* corr = at<uint32_t>(j.ws, j.L.corr);
   FeaturePlanCfg pc = {};
   pc.enabled = 1;
   pc.kcount_minus1 = c.k_count - 1;
@@ -109,14 +110,13 @@ static ahs_status step_features_auto(SortJob& j, const ahs_config& c, bool model
     ProfScope p(j.ctx, "minmax", j.s, (double)j.key_bytes * j.n);
     AHS_HIP(j,
             launch_minmax(j.kk, j.kin, j.n, at<MinMaxPartial>(j.ws, j.L.mm), minmax_blocks(j.n), df, j.s, &pc,
-                          j.n >= FUSED_HIST_MIN_N ? parts : nullptr),
+                          j.n >= FUSED_HIST_MIN_N ? parts : nullptr, corr),
             "minmax launch");
   }
-  uint32_t* corr = at<uint32_t>(j.ws, j.L.corr);
   // one histogram launch: the planned large kernel counts the small exact
-  // histogram too (one row per workgroup), or nothing
+  // histogram too (one row per workgroup), or nothing; the min/max final
+  // kernel zeroed the correction words if the packed histogram follows
   const int gl = hist_large_blocks(j.n);
-  AHS_HIP(j, launch_fill_u32(corr, 65536, 0u, j.s), "fill");
   {
     ProfScope p(j.ctx, "feature_hist", j.s, (double)j.key_bytes * j.n);
     AHS_HIP(j, launch_hist_large(j.kk, j.kin, j.n, 0, 0, parts, corr, gl, 0, at<uint32_t>(j.ws, j.L.dparts), j.s, df),
